@@ -1,0 +1,205 @@
+/*
+ * oica.h -- C ABI of the MI355X (gfx950) hot path of matrix-form ordering ICA.
+ *
+ * Paper: Y. Matsuda and K. Yamaguchi, "Efficient Estimation of Unique Components
+ * in Independent Component Analysis by Matrix Representation", arXiv 2408.17118.
+ * The paper states the problem as: given whitened observations X and the
+ * hyper-parameters (number of random starts, iteration cap, threshold), return
+ * the separating rows in the order of the ordering criterion.  The calls below
+ * follow that statement: whitening (done "in advance" in the paper), the batched
+ * fixed point over many random starts, and the selection of unique components.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Layout is row-major.  X and Xw are N x T (T samples, contiguous per row).
+ *    W0, W and U hold one vector per row (K x N or n x N).
+ *  - Every array argument is a caller-owned DEVICE pointer unless its comment
+ *    says "host".  The library never frees caller memory and keeps no pointer
+ *    to it after a call returns.  The library owns its context and an internal
+ *    workspace that grows on demand and is freed by oica_destroy.
+ *  - All work is enqueued on the context's HIP stream.  A call returns after
+ *    enqueueing unless its comment says it synchronises (calls that report a
+ *    count or a data-dependent error to the host do).
+ *  - Return value: OICA_OK (0) or a negative OICA_E_* code.  Argument errors
+ *    are detected on the host before any device work, so they can be tested
+ *    without a GPU.  After an error, oica_last_error() gives a readable detail.
+ *    Per-row outcomes of the fixed point go in the status array, never in the
+ *    return code.
+ *  - A context may be used by one host thread at a time.
+ */
+#ifndef OICA_H
+#define OICA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oica_ctx oica_ctx;
+
+typedef enum { OICA_F64 = 0, OICA_F32 = 1, OICA_BF16 = 2 } oica_dtype;
+
+enum {
+  OICA_OK = 0,
+  OICA_E_ARG = -1,         /* null pointer, bad size, bad parameter          */
+  OICA_E_SHAPE = -2,       /* output capacity too small                      */
+  OICA_E_RANK = -3,        /* covariance singular: data cannot be whitened   */
+  OICA_E_NONFINITE = -4,   /* NaN or Inf in the input                        */
+  OICA_E_DEVICE = -5,      /* HIP runtime error                              */
+  OICA_E_NOMEM = -6,       /* workspace allocation failed                    */
+  OICA_E_UNSUPPORTED = -7  /* size or dtype outside what the kernels handle  */
+};
+
+/* Per-row outcome of the fixed point (status array). */
+enum {
+  OICA_ROW_NOTCONV = 0,    /* still moving after max_iter passes             */
+  OICA_ROW_CONV = 1,       /* step fell below the threshold                  */
+  OICA_ROW_PRUNED = 2,     /* dropped by the learned pruner (state kept)     */
+  OICA_ROW_DEGENERATE = 3  /* update had zero or non-finite norm             */
+};
+
+/* Largest number of components (dimension N) the kernels handle. */
+#define OICA_MAX_N 128
+
+/* Version of this ABI: major * 10000 + minor * 100 + patch. */
+int oica_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  *out (host) receives the
+ * handle.  Errors: OICA_E_ARG (out == NULL, device out of range), OICA_E_DEVICE. */
+int oica_create(oica_ctx **out, int device, void *hip_stream);
+
+/* Destroy a context and free its workspace (synchronises its stream). NULL is a no-op. */
+void oica_destroy(oica_ctx *ctx);
+
+/* Static name of a return code. Never NULL. */
+const char *oica_status_string(int status);
+
+/* Detail of the last error on ctx (valid until the next call on ctx); "" if none. */
+const char *oica_last_error(const oica_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int oica_set_stream(oica_ctx *ctx, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Whitening (Sec. 2.2: the observations are whitened before the method runs,
+ * so that every unit row w gives a component with zero mean and unit variance,
+ * the constraints of Theorem 1).
+ *
+ *   mean = X 1 / T;  C = (X - mean)(X - mean)^T / T   (FP64, divided by T)
+ *   C = E D E^T, eigenvalues descending, each eigenvector's largest-magnitude
+ *   entry positive;  V = D^(-1/2) E^T;  Xw = V (X - mean).
+ *
+ * N in [1, OICA_MAX_N], T > N.  X_raw: N x T of raw_t (OICA_F64 or OICA_F32).
+ * Xw: N x T of out_t (OICA_F32 or OICA_BF16, round to nearest even).
+ * Xw_f32: optional extra FP32 copy (N x T) written when out_t == OICA_BF16,
+ *   needed later by the FP32 refinement and by the final kurtosis; NULL to skip.
+ * V (N x N), mean (N), eigval (N): FP64 outputs; any may be NULL.
+ * Synchronises.  Errors: OICA_E_ARG, OICA_E_UNSUPPORTED (N > OICA_MAX_N),
+ * OICA_E_NONFINITE (NaN/Inf in X_raw), OICA_E_RANK (smallest eigenvalue
+ * <= 1e-12 x largest), OICA_E_NOMEM, OICA_E_DEVICE.
+ * ------------------------------------------------------------------------- */
+int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t,
+                void *Xw, oica_dtype out_t, float *Xw_f32,
+                double *V, double *mean, double *eigval);
+
+/* ---------------------------------------------------------------------------
+ * The batched kurtosis fixed point with removal of converged rows (Sec. 3.1,
+ * eqs. 4-5 in the order of Algorithm 2, and Sec. 3.2), followed by the
+ * kurtosis of every final row (eq. 2).
+ *
+ *   B = rows of W0 normalised (FP64, stored FP32);  every row active.
+ *   repeat (at least once, at most max_iter passes):
+ *     for the active rows P:  Z = P Xw;  G = (Z o Z o Z) Xw^T / T - 3 P
+ *     b = g / ||g||;  d = min(||b - b_prev||, ||b + b_prev||)
+ *     d < tol -> CONV (row leaves the active set);  ||g|| == 0 or non-finite
+ *     -> DEGENERATE (row keeps b_prev and leaves the active set)
+ *   kurt[l] = sum_m (b_l . x_m)^4 / T - 3 over the FP32 data, FP64 sums.
+ *
+ * precision = OICA_F32: the passes run on FP32 data (Xw of xw_t = OICA_F32).
+ * precision = OICA_BF16: the passes run on BF16 data (Xw of xw_t = OICA_BF16,
+ *   BF16 products, FP32 sums) with threshold tol_bf16; then refine_iters
+ *   passes on the FP32 copy Xw_f32 for every converged row, and a row counts
+ *   as CONV if its last refinement step is below tol.
+ * traj: optional K x traj_iters x 2 FP32 record of (kurtosis of the row
+ *   before pass t+1, step d of pass t+1); NaN once a row has stopped.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int max_iter;          /* >= 1                                           */
+  double tol;            /* > 0, FP32 threshold (1e-6 is the paper's)      */
+  oica_dtype precision;  /* OICA_F32 or OICA_BF16                          */
+  double tol_bf16;       /* > 0, used when precision == OICA_BF16          */
+  int refine_iters;      /* FP32 passes after the BF16 loop (>= 0)         */
+  int traj_iters;        /* 0..16: passes recorded into traj               */
+  int check_every;       /* host polls the active count every this many
+                            passes (>= 1; 0 = default 4)                   */
+} oica_fp_params;
+
+typedef struct {         /* host */
+  int64_t thread_iters;  /* sum over passes of the active rows             */
+  int passes;            /* passes that had at least one active row        */
+  int64_t refine_thread_iters; /* FP32 refinement row updates (BF16 mode)  */
+  double ms;             /* wall time of the call (stream-synchronised)    */
+} oica_fp_stats;
+
+/* N in [1, OICA_MAX_N], T > N, K >= 1.
+ * Xw: N x T of xw_t; Xw_f32: N x T FP32 (may equal Xw when xw_t == F32; required).
+ * W0: K x N FP32 (rows need not be normalised; a zero row ends DEGENERATE).
+ * Outputs, all K rows in the original row order: W_out K x N FP32 unit rows,
+ * kurt K FP64, iters K int32 (updates applied to the row), status K uint8.
+ * traj may be NULL when traj_iters == 0; stats (host) may be NULL.
+ * Synchronises (the active count is polled on the host).
+ * Errors: OICA_E_ARG, OICA_E_UNSUPPORTED, OICA_E_NOMEM, OICA_E_DEVICE. */
+int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
+                     const float *Xw_f32, int K, const float *W0, const oica_fp_params *params,
+                     float *W_out, double *kurt, int32_t *iters, uint8_t *status,
+                     float *traj, oica_fp_stats *stats);
+
+/* One unnormalised update for K given rows (eqs. 4-5, Algorithm 2 order):
+ * G = (Z o Z o Z) Xw^T / T - 3 B with Z = B Xw, and s4 = sum_m z^4 / T per row.
+ * B: K x N FP32 (used as given, not normalised).  G: K x N FP64, s4: K FP64.
+ * Runs the same fused kernel and split reduction as oica_fixed_point.
+ * Does not synchronise. */
+int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t, int K,
+                const float *B, double *G, double *s4);
+
+/* Kurtosis of eq. (2) for K rows: kurt[l] = sum_m (b_l . x_m)^4 / T - 3,
+ * FP32 products of FP32 data with FP64 sums over samples.  Does not synchronise. */
+int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
+                  const float *W, double *kurt);
+
+/* ---------------------------------------------------------------------------
+ * Unique components (generalises Algorithm 2's argmax over the random starts
+ * and its Gaussianity test, eq. 3, to the whole ordered set):
+ *   candidates = rows with status CONV (if none: every non-degenerate row),
+ *   with finite kurtosis;  order = upsilon(kurt) descending, then row index,
+ *   upsilon(a) = a - 2 log(1 + a/2) (eq. 1, +inf for a <= -2);
+ *   greedy leader clustering up to sign in that order: a row joins the first
+ *   representative r with 1 - |b . b_r| <= tau, else starts a new cluster;
+ *   representatives are output in that order with the sign that makes their
+ *   largest-magnitude entry positive;  the Gaussianity walk accepts ranks
+ *   r = 1, 2, ... while upsilon_r >= 2 (N - r + 2)(N - r + 1) / T.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double tau;            /* clustering threshold on 1 - |cos|, in (0, 1)  */
+  int gaussianity_test;  /* 0: accept every cluster                        */
+  int n_top;             /* > 0: cap the accepted count                    */
+} oica_unique_params;
+
+/* W: K x N FP32 unit rows; kurt: K FP64; status: K uint8 (as from oica_fixed_point).
+ * Outputs (device) for the first min(n_unique, cap) clusters: U cap x N FP64,
+ * kurt_u, ups_u (cap FP64), rep_thread, cluster_size (cap int32).
+ * n_unique, n_accepted: host.  Synchronises.
+ * Errors: OICA_E_ARG; OICA_E_SHAPE if cap < n_unique (the counts are still
+ * written, and the first cap clusters). */
+int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const double *kurt,
+                const uint8_t *status, const oica_unique_params *params, int cap,
+                double *U, double *kurt_u, double *ups_u, int32_t *rep_thread,
+                int32_t *cluster_size, int *n_unique, int *n_accepted);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OICA_H */

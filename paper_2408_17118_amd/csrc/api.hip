@@ -1,0 +1,356 @@
+// Host side of the C ABI declared in include/oica.h: context, workspace,
+// argument checks (all before any device work) and launch orchestration.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+
+#include "oica_internal.h"
+
+using namespace oica;
+
+struct oica_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  int *small_dev = nullptr;    // 64 ints of device bookkeeping
+  int *small_host = nullptr;   // 64 ints of pinned host memory
+  std::string err;
+};
+
+namespace {
+
+int fail(oica_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(oica_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                            \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, OICA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure_ws(oica_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return OICA_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->ws) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4 + (1u << 20);
+  if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws = nullptr;
+    return fail(ctx, OICA_E_NOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  ctx->ws_bytes = want;
+  return OICA_OK;
+}
+
+struct Carve {
+  char *p;
+  template <typename T>
+  T *take(size_t count) {
+    T *r = (T *)p;
+    p += (count * sizeof(T) + 255) & ~(size_t)255;
+    return r;
+  }
+};
+
+int check_dims(oica_ctx *ctx, int N, int64_t T) {
+  if (N < 1) return fail(ctx, OICA_E_ARG, "N must be >= 1 (got %d)", N);
+  if (N > OICA_MAX_N) return fail(ctx, OICA_E_UNSUPPORTED, "N=%d exceeds OICA_MAX_N=%d", N, OICA_MAX_N);
+  if (T <= N) return fail(ctx, OICA_E_ARG, "T must exceed N (N=%d, T=%lld)", N, (long long)T);
+  if (T > (int64_t)1 << 40) return fail(ctx, OICA_E_UNSUPPORTED, "T=%lld too large", (long long)T);
+  return OICA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oica_version(void) { return 10000; }
+
+const char *oica_status_string(int status) {
+  switch (status) {
+    case OICA_OK: return "OICA_OK";
+    case OICA_E_ARG: return "OICA_E_ARG";
+    case OICA_E_SHAPE: return "OICA_E_SHAPE";
+    case OICA_E_RANK: return "OICA_E_RANK";
+    case OICA_E_NONFINITE: return "OICA_E_NONFINITE";
+    case OICA_E_DEVICE: return "OICA_E_DEVICE";
+    case OICA_E_NOMEM: return "OICA_E_NOMEM";
+    case OICA_E_UNSUPPORTED: return "OICA_E_UNSUPPORTED";
+    default: return "OICA_E_UNKNOWN";
+  }
+}
+
+const char *oica_last_error(const oica_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int oica_create(oica_ctx **out, int device, void *hip_stream) {
+  if (!out) return OICA_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return OICA_E_DEVICE;
+  }
+  if (device < 0 || device >= n) return OICA_E_ARG;
+  oica_ctx *ctx = new oica_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->small_dev, 64 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&ctx->small_host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx->small_dev) (void)hipFree(ctx->small_dev);
+    delete ctx;
+    return OICA_E_DEVICE;
+  }
+  *out = ctx;
+  return OICA_OK;
+}
+
+void oica_destroy(oica_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->small_dev) (void)hipFree(ctx->small_dev);
+  if (ctx->small_host) (void)hipHostFree(ctx->small_host);
+  delete ctx;
+}
+
+int oica_set_stream(oica_ctx *ctx, void *hip_stream) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return OICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t, void *Xw,
+                oica_dtype out_t, float *Xw_f32, double *V, double *mean, double *eigval) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (!X_raw || !Xw) return fail(ctx, OICA_E_ARG, "X_raw and Xw must be non-null");
+  if (raw_t != OICA_F64 && raw_t != OICA_F32)
+    return fail(ctx, OICA_E_UNSUPPORTED, "raw_t must be OICA_F64 or OICA_F32");
+  if (out_t != OICA_F32 && out_t != OICA_BF16)
+    return fail(ctx, OICA_E_UNSUPPORTED, "out_t must be OICA_F32 or OICA_BF16");
+  rc = ensure_ws(ctx, whiten_workspace_bytes(N, T));
+  if (rc) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, launch_whiten(ctx->stream, N, T, X_raw, raw_t, Xw, out_t, Xw_f32, V, mean, eigval,
+                             ctx->ws, ctx->ws_bytes, ctx->small_dev));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small_dev, sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const int flags = ctx->small_host[0];
+  if (flags & 1) return fail(ctx, OICA_E_NONFINITE, "X_raw contains NaN or Inf");
+  if (flags & 2) return fail(ctx, OICA_E_RANK, "covariance is rank deficient (eigenvalue ratio <= 1e-12)");
+  return OICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
+  if (!p) return fail(ctx, OICA_E_ARG, "params must be non-null");
+  if (p->max_iter < 1) return fail(ctx, OICA_E_ARG, "max_iter must be >= 1");
+  if (!(p->tol > 0) || !isfinite(p->tol)) return fail(ctx, OICA_E_ARG, "tol must be > 0");
+  if (p->precision != OICA_F32 && p->precision != OICA_BF16)
+    return fail(ctx, OICA_E_UNSUPPORTED, "precision must be OICA_F32 or OICA_BF16");
+  if (p->precision == OICA_BF16 && (!(p->tol_bf16 > 0) || !isfinite(p->tol_bf16)))
+    return fail(ctx, OICA_E_ARG, "tol_bf16 must be > 0");
+  if (p->refine_iters < 0) return fail(ctx, OICA_E_ARG, "refine_iters must be >= 0");
+  if (p->traj_iters < 0 || p->traj_iters > 16) return fail(ctx, OICA_E_ARG, "traj_iters must be in [0, 16]");
+  if (p->check_every < 0) return fail(ctx, OICA_E_ARG, "check_every must be >= 0");
+  return OICA_OK;
+}
+
+// Run passes on data X (F32) from the rows currently in B with active list
+// act[0] (count already in ctl->kact[0]); returns the number of passes launched.
+int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const void *X, bool bf16,
+               int K, float *B, int *act0, int *act1, float *gpart, float *s4part, FpControl *ctl,
+               int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
+               float *traj, int traj_iters) {
+  int kmax = K;  // upper bound on the active count (it never grows)
+  for (int pass = 0; pass < max_iter; ++pass) {
+    int *cur = (pass & 1) ? act1 : act0;
+    int *nxt = (pass & 1) ? act0 : act1;
+    HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
+                                     gpart, s4part, ctl, pass));
+    HIP_TRY(ctx, launch_epilogue(ctx->stream, plan, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
+                                 s4part, tol, iters, status, traj, traj_iters));
+    if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      const FpControl *h = (const FpControl *)ctx->small_host;
+      const int left = h->kact[(pass + 1) & 1];
+      if (left == 0) break;
+      kmax = left;
+    }
+  }
+  return OICA_OK;
+}
+
+}  // namespace
+
+int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
+                     const float *Xw_f32, int K, const float *W0, const oica_fp_params *params,
+                     float *W_out, double *kurt, int32_t *iters, uint8_t *status, float *traj,
+                     oica_fp_stats *stats) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1 (got %d)", K);
+  if (K > (1 << 24)) return fail(ctx, OICA_E_UNSUPPORTED, "K=%d too large", K);
+  rc = check_fp_params(ctx, params);
+  if (rc) return rc;
+  if (!Xw || !Xw_f32 || !W0 || !W_out || !kurt || !iters || !status)
+    return fail(ctx, OICA_E_ARG, "Xw, Xw_f32, W0, W_out, kurt, iters and status must be non-null");
+  if (params->traj_iters > 0 && !traj) return fail(ctx, OICA_E_ARG, "traj must be non-null when traj_iters > 0");
+  const bool bf16 = params->precision == OICA_BF16;
+  if (bf16 && xw_t != OICA_BF16) return fail(ctx, OICA_E_ARG, "BF16 precision needs xw_t == OICA_BF16");
+  if (!bf16 && xw_t != OICA_F32) return fail(ctx, OICA_E_ARG, "F32 precision needs xw_t == OICA_F32");
+  if (bf16) return fail(ctx, OICA_E_UNSUPPORTED, "BF16 precision is not built into this library");
+
+  const auto t0 = std::chrono::steady_clock::now();
+  const FusedPlan plan = make_plan(N, T, K, bf16);
+  const size_t gfl = fp_workspace_floats(plan, N, K);
+  const int np = fused_np(N);
+  const size_t rows_max = gfl / np;
+  size_t need = 0;
+  need += gfl * sizeof(float) + 256;            // gpart
+  need += rows_max * sizeof(float) + 256;       // s4part
+  need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
+  need += 2 * ((size_t)K * sizeof(int) + 256);  // act lists
+  need += sizeof(FpControl) + 256;
+  rc = ensure_ws(ctx, need);
+  if (rc) return rc;
+  Carve cv{(char *)ctx->ws};
+  float *gpart = cv.take<float>(gfl);
+  float *s4part = cv.take<float>(rows_max);
+  double *s4part64 = cv.take<double>(rows_max);
+  int *act0 = cv.take<int>(K);
+  int *act1 = cv.take<int>(K);
+  FpControl *ctl = cv.take<FpControl>(1);
+
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, sizeof(FpControl), ctx->stream));
+  HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj,
+                                params->traj_iters));
+  const int check_every = params->check_every > 0 ? params->check_every : 4;
+  rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, ctl,
+                  params->max_iter, params->tol, check_every, iters, status, traj,
+                  params->traj_iters);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan, N, T, Xw_f32, K, W_out, s4part64, kurt));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    const FpControl *h = (const FpControl *)ctx->small_host;
+    stats->thread_iters = h->thread_iters;
+    stats->passes = h->passes;
+    stats->refine_thread_iters = 0;
+    stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return OICA_OK;
+}
+
+int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t, int K,
+                const float *B, double *G, double *s4) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1");
+  if (!Xw || !B || !G || !s4) return fail(ctx, OICA_E_ARG, "Xw, B, G and s4 must be non-null");
+  if (xw_t != OICA_F32) return fail(ctx, OICA_E_UNSUPPORTED, "xw_t must be OICA_F32");
+  const FusedPlan plan = make_plan(N, T, K, false);
+  const size_t gfl = fp_workspace_floats(plan, N, K);
+  const size_t rows_max = gfl / fused_np(N);
+  rc = ensure_ws(ctx, gfl * 4 + rows_max * 4 + 1024);
+  if (rc) return rc;
+  Carve cv{(char *)ctx->ws};
+  float *gpart = cv.take<float>(gfl);
+  float *s4part = cv.take<float>(rows_max);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, Xw, false, B, nullptr, nullptr, K, gpart,
+                                   s4part, nullptr, 0));
+  HIP_TRY(ctx, launch_update_out(ctx->stream, plan, N, T, K, B, gpart, s4part, G, s4));
+  return OICA_OK;
+}
+
+int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K, const float *W,
+                  double *kurt) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1");
+  if (!Xw_f32 || !W || !kurt) return fail(ctx, OICA_E_ARG, "Xw_f32, W and kurt must be non-null");
+  const FusedPlan plan = make_plan(N, T, K, false);
+  const size_t rows_max = fp_workspace_floats(plan, N, K) / fused_np(N);
+  rc = ensure_ws(ctx, rows_max * 8 + 1024);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan, N, T, Xw_f32, K, W, (double *)ctx->ws, kurt));
+  return OICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const double *kurt,
+                const uint8_t *status, const oica_unique_params *params, int cap, double *U,
+                double *kurt_u, double *ups_u, int32_t *rep_thread, int32_t *cluster_size,
+                int *n_unique, int *n_accepted) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1");
+  if (!params) return fail(ctx, OICA_E_ARG, "params must be non-null");
+  if (!(params->tau > 0.0 && params->tau < 1.0)) return fail(ctx, OICA_E_ARG, "tau must be in (0, 1)");
+  if (params->n_top < 0) return fail(ctx, OICA_E_ARG, "n_top must be >= 0");
+  if (cap < 0) return fail(ctx, OICA_E_ARG, "cap must be >= 0");
+  if (!W || !kurt || !status || !n_unique || !n_accepted)
+    return fail(ctx, OICA_E_ARG, "W, kurt, status, n_unique and n_accepted must be non-null");
+  if (cap > 0 && (!U || !kurt_u || !ups_u || !rep_thread || !cluster_size))
+    return fail(ctx, OICA_E_ARG, "output arrays must be non-null when cap > 0");
+  rc = ensure_ws(ctx, unique_workspace_bytes(K));
+  if (rc) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, launch_unique(ctx->stream, N, T, K, W, kurt, status, params->tau,
+                             params->gaussianity_test, params->n_top, cap, U, kurt_u, ups_u,
+                             rep_thread, cluster_size, ctx->ws, ctx->small_host, ctx->small_dev));
+  *n_unique = ctx->small_host[1];
+  *n_accepted = ctx->small_host[3];
+  if (cap < *n_unique)
+    return fail(ctx, OICA_E_SHAPE, "cap=%d is smaller than the %d clusters found", cap, *n_unique);
+  return OICA_OK;
+}
+
+}  // extern "C"

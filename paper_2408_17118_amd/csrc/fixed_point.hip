@@ -1,0 +1,455 @@
+// Batched kurtosis fixed point on gfx950 (Sec. 3.1-3.2 of the paper: the L
+// random starts stacked as the rows of B, Z = B X, B <- (Z o Z o Z) X^T / M - 3B,
+// converged rows removed from the product).
+//
+// One fused kernel does both contractions of a pass without storing Z:
+//   GEMM1  Z^T = X^T B^T   (contraction over the N features, FP32 MFMA)
+//   cube   P = Z o Z o Z   (in registers, on the accumulator layout of GEMM1)
+//   GEMM2  G^T += X P^T    (contraction over the samples, FP32 MFMA)
+// Work is split over (row block, sample split) pairs; each pair writes a
+// partial G that the epilogue kernel sums in a fixed order, so results are
+// deterministic.  The epilogue normalises, measures the step, updates the
+// per-row state and appends still-moving rows to the next active list.
+//
+// MFMA v_mfma_f32_32x32x2f32 operand layout (wave64, lane l, h = l / 32,
+// i = l % 32):  A[i][h], B[h][i]  (one float each);  D[r][i] in vgpr v with
+// r = 8 (v / 4) + 4 h + (v % 4).  GEMM1 produces Z^T with the rows of B on the
+// lane index, so the same registers are directly the B operand of GEMM2 with
+// the samples permuted by r(v, h); GEMM2's A operand reads X with the same
+// permutation.
+#include "oica_internal.h"
+
+#include <math.h>
+
+namespace oica {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVES = 4;        // waves per work-group
+constexpr int TT = 64;          // samples per LDS tile (two 32-sample sub-tiles)
+constexpr int SX = TT + 1;      // LDS row stride in floats; odd, so column reads hit 32 banks
+constexpr int MIN_SUB = 8;      // each sample split covers >= 8 sub-tiles (256 samples)
+constexpr int GRID = 1024;      // work-groups per fused launch (multiple of 8)
+
+int fused_np(int N) { return ((N + 31) / 32) * 32; }
+
+static inline int wk_for_np(int np) { return np <= 64 ? 2 : 1; }
+
+FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
+  (void)kmax;
+  (void)bf16;
+  FusedPlan p;
+  int np = fused_np(N);
+  p.grid = GRID;
+  p.kwg = WAVES * wk_for_np(np) * 32;
+  int64_t n_sub = (T + 31) / 32;
+  p.n_sub = (int)n_sub;
+  int64_t ms = n_sub / MIN_SUB;
+  if (ms < 1) ms = 1;
+  if (ms > GRID) ms = GRID;
+  p.max_splits = (int)ms;
+  return p;
+}
+
+// Partial-buffer rows per split: positions are padded to whole row blocks.
+static inline __host__ __device__ int padded_rows(int kact, int kwg) {
+  return ((kact + kwg - 1) / kwg) * kwg;
+}
+
+size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax) {
+  int np = fused_np(N);
+  size_t worst = 0;
+  // the partial buffer holds n_splits(n_kb) * n_kb * kwg rows; take the max
+  // over every n_kb a run can reach
+  int kb_max = (kmax + p.kwg - 1) / p.kwg;
+  for (int nkb = 1; nkb <= kb_max; ++nkb) {
+    size_t rows = (size_t)plan_splits(p, nkb) * (size_t)nkb * (size_t)p.kwg;
+    if (rows > worst) worst = rows;
+  }
+  return worst * (size_t)np;
+}
+
+// ---------------------------------------------------------------------------
+// Fused pass kernel.
+//   KURT = false: writes partial G (NP floats per row) and partial sum z^4.
+//   KURT = true : skips GEMM2 and writes partial sum z^4 in FP64.
+// ---------------------------------------------------------------------------
+template <int NP, int WK, bool KURT>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
+    const float *__restrict__ X, int N, long long T, FusedPlan plan,
+    const float *__restrict__ Bm, const int *__restrict__ act, const int *__restrict__ kact_dev,
+    int kact_host, float *__restrict__ gpart, float *__restrict__ s4part,
+    double *__restrict__ s4part64, FpControl *ctl, int pass) {
+  constexpr int KWG = WAVES * WK * 32;
+  constexpr int HALF = NP / 2;
+  __shared__ float xs[NP * SX];
+
+  const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
+  if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->kact[(pass + 1) & 1] = 0;
+    if (kact > 0) {
+      ctl->passes = pass + 1;
+      ctl->thread_iters += kact;
+    }
+  }
+  if (kact <= 0) return;
+
+  const int n_kb = (kact + KWG - 1) / KWG;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * KWG;
+  const int work = n_kb * n_sp;
+  const int per_xcd_items = (work + 7) / 8;
+  const int per_xcd_wgs = plan.grid / 8;
+  const int xcd = blockIdx.x % 8;
+  const int local = blockIdx.x / 8;
+
+  const int tid = threadIdx.x;
+  const int wave = tid / 64;
+  const int lane = tid % 64;
+  const int h = lane / 32;
+  const int li = lane % 32;
+
+  for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
+    const int w_item = xcd * per_xcd_items + it;
+    if (w_item >= work) break;
+    const int kb = w_item % n_kb;
+    const int sp = w_item / n_kb;
+    const long long sub0 = (long long)sp * plan.n_sub / n_sp;
+    const long long sub1 = (long long)(sp + 1) * plan.n_sub / n_sp;
+    const long long t_begin = sub0 * 32;
+    long long t_end = sub1 * 32;
+    if (t_end > T) t_end = T;
+
+    // B rows of this wave into registers: column block w covers positions
+    // kb*KWG + wave*WK*32 + w*32 + li; feature n = HALF*h + s.
+    float breg[WK][HALF];
+    int pos[WK];
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      pos[w] = kb * KWG + wave * WK * 32 + w * 32 + li;
+      int row = -1;
+      if (pos[w] < kact) row = act ? act[pos[w]] : pos[w];
+#pragma unroll
+      for (int s = 0; s < HALF; ++s) {
+        const int n = HALF * h + s;
+        breg[w][s] = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
+      }
+    }
+
+    f32x16 gacc[WK][NP / 32];
+    float s4acc[WK];
+    double s4acc64[WK];
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      s4acc[w] = 0.f;
+      s4acc64[w] = 0.0;
+#pragma unroll
+      for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
+    }
+
+    for (long long m_tile = t_begin; m_tile < t_end; m_tile += TT) {
+      __syncthreads();
+      for (int e = tid; e < NP * TT; e += WAVES * 64) {
+        const int n = e / TT;
+        const int m = e % TT;
+        const long long gm = m_tile + m;
+        xs[n * SX + m] = (n < N && gm < t_end) ? X[(size_t)n * (size_t)T + (size_t)gm] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sub = 0; sub < TT / 32; ++sub) {
+        if (m_tile + sub * 32 >= t_end) break;
+        const int m0 = sub * 32;
+        f32x16 zacc[WK];
+#pragma unroll
+        for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
+#pragma unroll
+        for (int s = 0; s < HALF; ++s) {
+          const float a = xs[(HALF * h + s) * SX + m0 + li];
+#pragma unroll
+          for (int w = 0; w < WK; ++w)
+            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, breg[w][s], zacc[w], 0, 0, 0);
+        }
+        if constexpr (KURT) {
+#pragma unroll
+          for (int w = 0; w < WK; ++w) {
+            float t4 = 0.f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const float z2 = zacc[w][v] * zacc[w][v];
+              t4 = fmaf(z2, z2, t4);
+            }
+            s4acc64[w] += (double)t4;
+          }
+        } else {
+          f32x16 p3[WK];
+#pragma unroll
+          for (int w = 0; w < WK; ++w) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const float z = zacc[w][v];
+              const float z2 = z * z;
+              p3[w][v] = z2 * z;
+              s4acc[w] = fmaf(z2, z2, s4acc[w]);
+            }
+          }
+#pragma unroll
+          for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int m = m0 + 8 * (v / 4) + 4 * h + (v % 4);
+              const float a = xs[(nb * 32 + li) * SX + m];
+#pragma unroll
+              for (int w = 0; w < WK; ++w)
+                gacc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, p3[w][v], gacc[w][nb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+
+    // Write this item's partials.
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      if constexpr (KURT) {
+        const double tot = s4acc64[w] + __shfl_xor(s4acc64[w], 32);
+        if (h == 0 && pos[w] < kact) s4part64[(size_t)sp * rows_pad + pos[w]] = tot;
+      } else {
+        const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
+        if (pos[w] < kact) {
+          if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
+          float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
+#pragma unroll
+          for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              f32x4 v4;
+              v4[0] = gacc[w][nb][4 * q + 0];
+              v4[1] = gacc[w][nb][4 * q + 1];
+              v4[2] = gacc[w][nb][4 * q + 2];
+              v4[3] = gacc[w][nb][4 * q + 3];
+              *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave reductions (64 lanes).
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: one wave per active position.
+// ---------------------------------------------------------------------------
+template <int NP>
+__global__ __launch_bounds__(256) void k_epilogue(
+    FusedPlan plan, int N, long long T, float *__restrict__ Bm, const int *__restrict__ act_cur,
+    int *__restrict__ act_next, FpControl *ctl, int pass, const float *__restrict__ gpart,
+    const float *__restrict__ s4part, double tol, int32_t *__restrict__ iters,
+    uint8_t *__restrict__ status, float *__restrict__ traj, int traj_iters) {
+  const int kact = ctl->kact[pass & 1];
+  const int lane = threadIdx.x % 64;
+  const int posn = blockIdx.x * 4 + threadIdx.x / 64;
+  if (posn >= kact) return;
+  const int n_kb = (kact + plan.kwg - 1) / plan.kwg;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * plan.kwg;
+  const int row = act_cur[posn];
+
+  const int n0 = lane, n1 = lane + 64;
+  double g0 = 0.0, g1 = 0.0, s4 = 0.0;
+  for (int sp = 0; sp < n_sp; ++sp) {
+    const float *src = gpart + ((size_t)sp * rows_pad + posn) * NP;
+    if (n0 < NP) g0 += (double)src[n0];
+    if (n1 < NP) g1 += (double)src[n1];
+    if (lane == 0) s4 += (double)s4part[(size_t)sp * rows_pad + posn];
+  }
+  float *brow = Bm + (size_t)row * N;
+  const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
+  const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
+  const double invT = 1.0 / (double)T;
+  g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
+  g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+  const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
+  s4 = __shfl(s4, 0);
+  const double alpha = s4 * invT - 3.0;
+  double d;
+  if (!(gn > 0.0) || !isfinite(gn)) {
+    d = NAN;
+    if (lane == 0) status[row] = OICA_ROW_DEGENERATE;
+  } else {
+    const double b0 = g0 / gn, b1 = g1 / gn;
+    const double dm = wave_sum((b0 - bp0) * (b0 - bp0) + (b1 - bp1) * (b1 - bp1));
+    const double dp = wave_sum((b0 + bp0) * (b0 + bp0) + (b1 + bp1) * (b1 + bp1));
+    d = sqrt(dm < dp ? dm : dp);
+    if (n0 < N) brow[n0] = (float)b0;
+    if (n1 < N) brow[n1] = (float)b1;
+    if (lane == 0) {
+      iters[row] += 1;
+      if (d < tol) {
+        status[row] = OICA_ROW_CONV;
+      } else {
+        const int slot = atomicAdd(&ctl->kact[(pass + 1) & 1], 1);
+        act_next[slot] = row;
+      }
+    }
+  }
+  if (lane == 0 && pass < traj_iters) {
+    traj[((size_t)row * traj_iters + pass) * 2 + 0] = (float)alpha;
+    traj[((size_t)row * traj_iters + pass) * 2 + 1] = (float)d;
+  }
+}
+
+// Row initialisation: normalise W0 in FP64, mark zero/non-finite rows
+// DEGENERATE, build the first active list.
+__global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *__restrict__ Bm,
+                            int32_t *__restrict__ iters, uint8_t *__restrict__ status,
+                            int *__restrict__ act0, FpControl *ctl, float *__restrict__ traj,
+                            int traj_iters) {
+  const int lane = threadIdx.x % 64;
+  const int row = blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= K) return;
+  const float *src = W0 + (size_t)row * N;
+  const int n0 = lane, n1 = lane + 64;
+  const double w0 = n0 < N ? (double)src[n0] : 0.0;
+  const double w1 = n1 < N ? (double)src[n1] : 0.0;
+  const double nrm = sqrt(wave_sum(w0 * w0 + w1 * w1));
+  const bool ok = nrm > 0.0 && isfinite(nrm);
+  float *dst = Bm + (size_t)row * N;
+  if (n0 < N) dst[n0] = (float)(w0 / nrm);
+  if (n1 < N) dst[n1] = (float)(w1 / nrm);
+  for (int t = lane; t < 2 * traj_iters; t += 64) traj[(size_t)row * traj_iters * 2 + t] = NAN;
+  if (lane == 0) {
+    iters[row] = 0;
+    if (ok) {
+      status[row] = OICA_ROW_NOTCONV;
+      const int slot = atomicAdd(&ctl->kact[0], 1);
+      act0[slot] = row;
+    } else {
+      status[row] = OICA_ROW_DEGENERATE;
+    }
+  }
+}
+
+// G = sum_sp gpart / T - 3 B and s4 = sum_sp s4part / T for rows 0..K-1
+// (positions equal rows).
+template <int NP>
+__global__ void k_update_out(FusedPlan plan, int N, long long T, int K, const float *__restrict__ Bm,
+                             const float *__restrict__ gpart, const float *__restrict__ s4part,
+                             double *__restrict__ G, double *__restrict__ s4out) {
+  const int lane = threadIdx.x % 64;
+  const int row = blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= K) return;
+  const int n_kb = (K + plan.kwg - 1) / plan.kwg;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * plan.kwg;
+  const double invT = 1.0 / (double)T;
+  for (int n = lane; n < N; n += 64) {
+    double g = 0.0;
+    for (int sp = 0; sp < n_sp; ++sp) g += (double)gpart[((size_t)sp * rows_pad + row) * NP + n];
+    G[(size_t)row * N + n] = g * invT - 3.0 * (double)Bm[(size_t)row * N + n];
+  }
+  if (lane == 0) {
+    double s = 0.0;
+    for (int sp = 0; sp < n_sp; ++sp) s += (double)s4part[(size_t)sp * rows_pad + row];
+    s4out[row] = s * invT;
+  }
+}
+
+template <int NP>
+__global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__restrict__ s4part64,
+                           double *__restrict__ kurt) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= K) return;
+  const int kwg = plan.kwg;
+  const int n_kb = (K + kwg - 1) / kwg;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * kwg;
+  double s = 0.0;
+  for (int sp = 0; sp < n_sp; ++sp) s += s4part64[(size_t)sp * rows_pad + row];
+  kurt[row] = s / (double)T - 3.0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define OICA_NP_SWITCH(np, ...)                     \
+  switch (np) {                                     \
+    case 32: { constexpr int NP_ = 32; __VA_ARGS__; break; }   \
+    case 64: { constexpr int NP_ = 64; __VA_ARGS__; break; }   \
+    case 96: { constexpr int NP_ = 96; __VA_ARGS__; break; }   \
+    case 128: { constexpr int NP_ = 128; __VA_ARGS__; break; } \
+    default: return hipErrorInvalidValue;           \
+  }
+
+hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
+                            int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
+                            float *traj, int traj_iters) {
+  hipLaunchKernelGGL(k_init_rows, dim3((K + 3) / 4), dim3(256), 0, st, K, N, W0, B, iters, status,
+                     act0, ctl, traj, traj_iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_t T, const void *X,
+                               bool bf16, const float *B, const int *act, const int *kact_dev,
+                               int kact_host, float *gpart, float *s4part, FpControl *ctl,
+                               int pass) {
+  if (bf16) return hipErrorInvalidValue;  // BF16 data use the BF16 kernel family
+  const int np = fused_np(N);
+  OICA_NP_SWITCH(np, {
+    constexpr int WK_ = NP_ <= 64 ? 2 : 1;
+    hipLaunchKernelGGL((k_fused_f32<NP_, WK_, false>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                       (const float *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
+                       s4part, (double *)nullptr, ctl, pass);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax, float *B,
+                           const int *act_cur, int *act_next, FpControl *ctl, int pass,
+                           const float *gpart, const float *s4part, double tol, int32_t *iters,
+                           uint8_t *status, float *traj, int traj_iters) {
+  const int np = fused_np(N);
+  OICA_NP_SWITCH(np, {
+    hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 3) / 4), dim3(256), 0, st, p, N,
+                       (long long)T, B, act_cur, act_next, ctl, pass, gpart, s4part, tol, iters,
+                       status, traj, traj_iters);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t T, int K,
+                             const float *B, const float *gpart, const float *s4part, double *G,
+                             double *s4) {
+  const int np = fused_np(N);
+  OICA_NP_SWITCH(np, {
+    hipLaunchKernelGGL((k_update_out<NP_>), dim3((K + 3) / 4), dim3(256), 0, st, p, N,
+                       (long long)T, K, B, gpart, s4part, G, s4);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T, const float *X,
+                           int K, const float *W, double *s4part64, double *kurt) {
+  const int np = fused_np(N);
+  OICA_NP_SWITCH(np, {
+    constexpr int WK_ = NP_ <= 64 ? 2 : 1;
+    hipLaunchKernelGGL((k_fused_f32<NP_, WK_, true>), dim3(p.grid), dim3(WAVES * 64), 0, st, X, N,
+                       (long long)T, p, W, (const int *)nullptr, (const int *)nullptr, K,
+                       (float *)nullptr, (float *)nullptr, s4part64, (FpControl *)nullptr, 0);
+    hipLaunchKernelGGL((k_kurt_out<NP_>), dim3((K + 255) / 256), dim3(256), 0, st, p,
+                       (long long)T, K, s4part64, kurt);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace oica

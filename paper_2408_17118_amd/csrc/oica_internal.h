@@ -1,0 +1,95 @@
+// Internal declarations shared by the host runtime and the kernel translation
+// units of liboica.  Nothing here is part of the public ABI (include/oica.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/oica.h"
+
+namespace oica {
+
+// Device-side bookkeeping of one fixed-point run.  Written by single lanes of
+// the fixed-point kernels; read back by the host when it polls.
+struct FpControl {
+  int kact[2];            // active-row count, double buffered by pass parity
+  int passes;             // passes that had at least one active row
+  int pad;
+  long long thread_iters; // sum over passes of the active-row count
+};
+
+// Launch plan of the fused update kernel.  The grid is fixed for a whole run;
+// each work-group derives its (row block, sample split) from the active count
+// it reads on the device, so no host round trip is needed between passes.
+struct FusedPlan {
+  int grid;         // work-groups launched (multiple of 8)
+  int max_splits;   // cap on sample splits (each split >= a minimum length)
+  int kwg;          // rows per work-group
+  int n_sub;        // 32-sample sub-tiles covering T
+};
+
+// Number of sample splits used when n_kb row blocks are active.  Host and
+// device evaluate the same expression.
+__host__ __device__ inline int plan_splits(const FusedPlan &p, int n_kb) {
+  if (n_kb <= 0) return 0;
+  int s = p.grid / n_kb;
+  if (s > p.max_splits) s = p.max_splits;
+  if (s < 1) s = 1;
+  return s;
+}
+
+// ---- launchers (defined next to their kernels) ----------------------------
+
+// whiten.hip
+hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t,
+                         void *Xw, oica_dtype out_t, float *Xw_f32, double *V_out,
+                         double *mean_out, double *eig_out, void *ws, size_t ws_bytes,
+                         int *flags_dev);
+size_t whiten_workspace_bytes(int N, int64_t T);
+
+// fixed_point.hip
+struct FpBuffers {
+  float *B;          // K x N current rows (FP32), output order = row order
+  int *act[2];       // active lists, double buffered
+  float *gpart;      // splits x K_cap x NP partial G
+  float *s4part;     // splits x K_cap partial sum z^4 (update mode)
+  double *s4part64;  // splits x K_cap partial sum z^4 (kurtosis mode)
+  FpControl *ctl;
+};
+
+int fused_np(int N);  // padded feature count used by the kernels for N
+FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16);
+size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
+
+hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
+                            int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
+                            float *traj, int traj_iters);
+hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_t T,
+                               const void *X, bool bf16, const float *B, const int *act,
+                               const int *kact_dev, int kact_host, float *gpart, float *s4part,
+                               FpControl *ctl, int pass);
+hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax,
+                           float *B, const int *act_cur, int *act_next, FpControl *ctl, int pass,
+                           const float *gpart, const float *s4part, double tol, int32_t *iters,
+                           uint8_t *status, float *traj, int traj_iters);
+hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t T, int K,
+                             const float *B, const float *gpart, const float *s4part, double *G,
+                             double *s4);
+hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
+                           const float *X, int K, const float *W, double *s4part64,
+                           double *kurt);
+hipError_t launch_finish_rows(hipStream_t st, int K, int N, const float *B, float *W_out);
+hipError_t launch_refine_select(hipStream_t st, int K, const uint8_t *status, int *act0,
+                                FpControl *ctl, uint8_t *status_out);
+
+// unique.hip
+size_t unique_workspace_bytes(int K);
+hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W,
+                         const double *kurt, const uint8_t *status, double tau, int gtest,
+                         int n_top, int cap, double *U, double *kurt_u, double *ups_u,
+                         int32_t *rep_thread, int32_t *cluster_size, void *ws, int *counts_host,
+                         int *counts_dev);
+
+}  // namespace oica

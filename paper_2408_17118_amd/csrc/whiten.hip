@@ -1,0 +1,434 @@
+// PCA whitening on gfx950, all in FP64 (the paper whitens the observations
+// before the method runs; Theorem 1's constraints are zero sample mean and
+// identity sample covariance, the covariance normalised by the sample count).
+//
+//   k_mean_part / k_mean_final   mu = X 1 / T          (two-level, fixed order)
+//   k_cov_part  / k_cov_final    C = Xc Xc^T / T       (split over T, fixed order)
+//   k_jacobi                     C = E D E^T            (cyclic Jacobi, one work-group,
+//                                                        C in LDS, E in global memory)
+//   k_canon                      descending order, sign rule, rank check,
+//                                Wh = D^(-1/2) E^T
+//   k_apply                      Xw = Wh (X - mu)       (FP64 tiles; FP32 / BF16 out)
+// Every pass is HBM-bound except the Jacobi solve, which is O(N^3) on N <= 128.
+#include "oica_internal.h"
+
+#include <math.h>
+
+namespace oica {
+
+constexpr int NMAX = OICA_MAX_N;
+constexpr int COV_TS = 32;        // samples per LDS tile in the covariance pass
+constexpr int CHUNK = 4096;       // samples per work-group in the reduction passes
+constexpr int MAX_CHUNKS = 256;
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename TIN>
+__device__ inline double ld(const TIN *p, size_t i) {
+  return (double)p[i];
+}
+
+static inline int n_chunks(int64_t T) {
+  int64_t c = (T + CHUNK - 1) / CHUNK;
+  if (c > MAX_CHUNKS) c = MAX_CHUNKS;
+  if (c < 1) c = 1;
+  return (int)c;
+}
+
+// Partial row sums over a sample chunk; one wave per row (strided), lanes over samples.
+template <typename TIN>
+__global__ __launch_bounds__(256) void k_mean_part(const TIN *__restrict__ X, int N, long long T,
+                                                   int chunks, double *__restrict__ part,
+                                                   int *__restrict__ flags) {
+  const int c = blockIdx.x;
+  const long long t0 = (long long)c * T / chunks, t1 = (long long)(c + 1) * T / chunks;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int n = wave; n < N; n += 4) {
+    double s = 0.0;
+    bool bad = false;
+    const TIN *row = X + (size_t)n * (size_t)T;
+    for (long long m = t0 + lane; m < t1; m += 64) {
+      const double v = ld(row, (size_t)m);
+      bad |= !isfinite(v);
+      s += v;
+    }
+    s = wsum(s);
+    if (bad) atomicOr(flags, 1);
+    if (lane == 0) part[(size_t)c * N + n] = s;
+  }
+}
+
+__global__ void k_mean_final(int N, long long T, int chunks, const double *__restrict__ part,
+                             double *__restrict__ mean) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
+  mean[n] = s / (double)T;
+}
+
+// Partial centred second moments over a chunk.  256 threads = 16 x 16, each
+// owning an 8 x 8 block of the (padded 128 x 128) matrix.
+template <typename TIN>
+__global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int N, long long T,
+                                                  int chunks, const double *__restrict__ mean,
+                                                  double *__restrict__ part) {
+  __shared__ double xs[COV_TS][NMAX + 2];
+  const int c = blockIdx.x;
+  const long long t0 = (long long)c * T / chunks, t1 = (long long)(c + 1) * T / chunks;
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  const bool active = (8 * ti < N) && (8 * tj < N);
+  double acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  for (long long m0 = t0; m0 < t1; m0 += COV_TS) {
+    __syncthreads();
+    for (int e = tid; e < COV_TS * NMAX; e += 256) {
+      const int n = e / COV_TS, s = e % COV_TS;
+      const long long m = m0 + s;
+      double v = 0.0;
+      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)T + (size_t)m) - mean[n];
+      xs[s][n] = v;
+    }
+    __syncthreads();
+    if (active) {
+      for (int s = 0; s < COV_TS; ++s) {
+        double a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = xs[s][8 * ti + q];
+          b[q] = xs[s][8 * tj + q];
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+      }
+    }
+  }
+  if (active) {
+    for (int p = 0; p < 8; ++p)
+      for (int q = 0; q < 8; ++q) {
+        const int i = 8 * ti + p, j = 8 * tj + q;
+        if (i < N && j < N) part[((size_t)c * N + i) * N + j] = acc[p][q];
+      }
+  }
+}
+
+__global__ void k_cov_final(int N, long long T, int chunks, const double *__restrict__ part,
+                            double *__restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int i = e / N, j = e % N;
+  // symmetric by construction: sum the upper triangle element for both
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[((size_t)c * N + a) * N + b];
+  C[e] = s / (double)T;
+}
+
+// Cyclic Jacobi with round-robin pairing: each round applies N/2 disjoint
+// rotations at once (rows first, then columns), a sweep is N-1 rounds
+// (N rounded up to even; the padding index is never rotated).
+// A lives in LDS; the accumulated rotations E live in global memory.
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_MAX_SWEEPS = 40;
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__restrict__ C,
+                                                         double *__restrict__ E,
+                                                         int *__restrict__ sweeps_out) {
+  __shared__ double a[NMAX * (NMAX + 1)];
+  __shared__ double rc[NMAX / 2], rs[NMAX / 2];
+  __shared__ int rp[NMAX / 2], rq[NMAX / 2];
+  __shared__ int rotated;
+  const int LD = N + 1;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N * N; e += JAC_THREADS) {
+    const int i = e / N, j = e % N;
+    a[i * LD + j] = C[e];
+    E[e] = (i == j) ? 1.0 : 0.0;
+  }
+  const int ne = N + (N & 1);
+  const int npair = ne / 2;
+  int sweep = 0;
+  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < ne - 1; ++r) {
+      if (tid < npair) {
+        int p, q;
+        if (tid == 0) {
+          p = ne - 1;
+          q = r;
+        } else {
+          p = (r + tid) % (ne - 1);
+          q = (r - tid + ne - 1) % (ne - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < N) {
+          const double apq = a[p * LD + q];
+          const double app = a[p * LD + p], aqq = a[q * LD + q];
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app) * fabs(aqq))) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            double t;
+            if (fabs(theta) > 1e150)
+              t = 0.5 / theta;
+            else
+              t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            rotated = 1;
+          }
+        }
+        rc[tid] = c;
+        rs[tid] = s;
+        rp[tid] = p;
+        rq[tid] = q < N ? q : -1;
+      }
+      __syncthreads();
+      // rows p, q of A  <-  J^T A
+      for (int e = tid; e < npair * N; e += JAC_THREADS) {
+        const int k = e / N, j = e % N;
+        const int q = rq[k];
+        if (q < 0 || rs[k] == 0.0) continue;
+        const int p = rp[k];
+        const double c = rc[k], s = rs[k];
+        const double apj = a[p * LD + j], aqj = a[q * LD + j];
+        a[p * LD + j] = c * apj - s * aqj;
+        a[q * LD + j] = s * apj + c * aqj;
+      }
+      __syncthreads();
+      // columns p, q of A and of E  <-  (.) J
+      for (int e = tid; e < npair * N; e += JAC_THREADS) {
+        const int k = e / N, i = e % N;
+        const int q = rq[k];
+        if (q < 0 || rs[k] == 0.0) continue;
+        const int p = rp[k];
+        const double c = rc[k], s = rs[k];
+        const double aip = a[i * LD + p], aiq = a[i * LD + q];
+        a[i * LD + p] = c * aip - s * aiq;
+        a[i * LD + q] = s * aip + c * aiq;
+        const double eip = E[i * N + p], eiq = E[i * N + q];
+        E[i * N + p] = c * eip - s * eiq;
+        E[i * N + q] = s * eip + c * eiq;
+      }
+      __syncthreads();
+    }
+    if (rotated == 0) break;
+    __syncthreads();
+  }
+  // eigenvalues: diagonal, written to the last row of the scratch after E
+  for (int i = tid; i < N; i += JAC_THREADS) E[N * N + i] = a[i * LD + i];
+  if (tid == 0) sweeps_out[0] = sweep;
+}
+
+// Sort descending (rank by count, ties by index), sign rule, rank check,
+// whitening matrix Wh = D^(-1/2) E^T.
+__global__ void k_canon(int N, const double *__restrict__ E, double *__restrict__ Wh,
+                        double *__restrict__ eig_out, int *__restrict__ flags) {
+  const int i = threadIdx.x;  // one thread per eigenpair, N <= 128
+  __shared__ double d[NMAX];
+  __shared__ int rank_of[NMAX];
+  const double *dv = E + N * N;
+  if (i < N) d[i] = dv[i];
+  __syncthreads();
+  if (i < N) {
+    int r = 0;
+    for (int j = 0; j < N; ++j)
+      if (d[j] > d[i] || (d[j] == d[i] && j < i)) ++r;
+    rank_of[i] = r;
+  }
+  __syncthreads();
+  if (i < N) {
+    const int r = rank_of[i];
+    // sign: largest-magnitude entry of column i positive (lowest row on ties)
+    int pm = 0;
+    double best = -1.0;
+    for (int row = 0; row < N; ++row) {
+      const double v = fabs(E[row * N + i]);
+      if (v > best) {
+        best = v;
+        pm = row;
+      }
+    }
+    const double sg = E[pm * N + i] < 0 ? -1.0 : 1.0;
+    const double lam = d[i];
+    const double sc = sg / sqrt(lam);
+    for (int col = 0; col < N; ++col) Wh[r * N + col] = sc * E[col * N + i];
+    eig_out[r] = lam;
+  }
+  __syncthreads();
+  if (i == 0) {
+    double mx = -INFINITY, mn = INFINITY;
+    bool fin = true;
+    for (int j = 0; j < N; ++j) {
+      mx = fmax(mx, d[j]);
+      mn = fmin(mn, d[j]);
+      fin &= isfinite(d[j]);
+    }
+    if (!fin || !(mx > 0.0) || !(mn > 1e-12 * mx)) atomicOr(flags, 2);
+  }
+}
+
+// Round a double to bfloat16, nearest-even, directly from the double bits
+// (no intermediate FP32 rounding).
+__device__ inline uint16_t bf16_rne(double x) {
+  const unsigned long long u = __double_as_longlong(x);
+  const unsigned long long sign = u >> 63;
+  const int exp = (int)((u >> 52) & 0x7FF);
+  if (exp == 0) return (uint16_t)(sign << 15);                     // zero / subnormal -> signed 0
+  if (exp == 0x7FF) return (uint16_t)((sign << 15) | 0x7FC0);       // Inf/NaN (data is finite)
+  const unsigned long long mag = u & 0x7FFFFFFFFFFFFFFFull;
+  const unsigned long long lsb = (mag >> 45) & 1ull;
+  const unsigned long long r = (mag + 0x0FFFFFFFFFFFull + lsb) >> 45;  // 11-bit exp : 7-bit mant
+  int e = (int)(r >> 7) - 1023 + 127;
+  const int mant = (int)(r & 0x7F);
+  if (e <= 0) return (uint16_t)(sign << 15);
+  if (e >= 255) return (uint16_t)((sign << 15) | 0x7F80);
+  return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)mant);
+}
+
+// Xw = Wh (X - mu): 64 x 64 output tiles, 4 x 4 outputs per thread, FP64.
+constexpr int AP_T = 64;
+constexpr int AP_K = 16;
+template <typename TIN>
+__global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N, long long T,
+                                               const double *__restrict__ Wh,
+                                               const double *__restrict__ mean,
+                                               float *__restrict__ out32, uint16_t *__restrict__ outbf,
+                                               float *__restrict__ out32b) {
+  __shared__ double ws[AP_T][AP_K + 1];
+  __shared__ double xs[AP_K][AP_T + 1];
+  const long long m_base = (long long)blockIdx.x * AP_T;
+  const int i_base = blockIdx.y * AP_T;
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int j0 = 0; j0 < N; j0 += AP_K) {
+    __syncthreads();
+    for (int e = tid; e < AP_T * AP_K; e += 256) {
+      const int r = e / AP_K, k = e % AP_K;
+      const int i = i_base + r, j = j0 + k;
+      ws[r][k] = (i < N && j < N) ? Wh[i * N + j] : 0.0;
+    }
+    for (int e = tid; e < AP_K * AP_T; e += 256) {
+      const int k = e / AP_T, s = e % AP_T;
+      const int j = j0 + k;
+      const long long m = m_base + s;
+      xs[k][s] = (j < N && m < T) ? ld(X, (size_t)j * (size_t)T + (size_t)m) - mean[j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < AP_K; ++k) {
+      double wv[4], xv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) wv[a] = ws[tr + 16 * a][k];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) xv[b] = xs[k][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(wv[a], xv[b], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i_base + tr + 16 * a;
+    if (i >= N) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long long m = m_base + tc + 16 * b;
+      if (m >= T) continue;
+      const size_t o = (size_t)i * (size_t)T + (size_t)m;
+      if (out32) out32[o] = (float)acc[a][b];
+      if (outbf) outbf[o] = bf16_rne(acc[a][b]);
+      if (out32b) out32b[o] = (float)acc[a][b];
+    }
+  }
+}
+
+size_t whiten_workspace_bytes(int N, int64_t T) {
+  const int ch = n_chunks(T);
+  size_t b = 0;
+  b += (size_t)ch * N * sizeof(double);          // mean partials
+  b += (size_t)ch * N * N * sizeof(double);      // covariance partials
+  b += (size_t)N * N * sizeof(double);           // C
+  b += (size_t)(N * N + N) * sizeof(double);     // E + eigenvalues
+  b += (size_t)N * N * sizeof(double);           // Wh
+  b += (size_t)N * sizeof(double) * 2;           // mean, eig
+  b += 64;                                       // sweeps
+  return b + 1024;
+}
+
+template <typename TIN>
+static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, void *Xw,
+                              oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
+                              double *eig_out, char *ws, int *flags_dev) {
+  const int ch = n_chunks(T);
+  char *p = ws;
+  auto take = [&](size_t bytes) {
+    char *r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  double *mpart = (double *)take((size_t)ch * N * sizeof(double));
+  double *cpart = (double *)take((size_t)ch * N * N * sizeof(double));
+  double *C = (double *)take((size_t)N * N * sizeof(double));
+  double *E = (double *)take((size_t)(N * N + N) * sizeof(double));
+  double *Wh = V_out ? V_out : (double *)take((size_t)N * N * sizeof(double));
+  double *mean = mean_out ? mean_out : (double *)take((size_t)N * sizeof(double));
+  double *eig = eig_out ? eig_out : (double *)take((size_t)N * sizeof(double));
+  int *sweeps = (int *)take(64);
+
+  hipLaunchKernelGGL((k_mean_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mpart,
+                     flags_dev);
+  hipLaunchKernelGGL(k_mean_final, dim3((N + 127) / 128), dim3(128), 0, st, N, (long long)T, ch,
+                     mpart, mean);
+  hipLaunchKernelGGL((k_cov_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mean,
+                     cpart);
+  hipLaunchKernelGGL(k_cov_final, dim3((N * N + 255) / 256), dim3(256), 0, st, N, (long long)T, ch,
+                     cpart, C);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), 0, st, N, C, E, sweeps);
+  hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, N, E, Wh, eig, flags_dev);
+  float *o32 = nullptr, *o32b = nullptr;
+  uint16_t *obf = nullptr;
+  if (out_t == OICA_F32) {
+    o32 = (float *)Xw;
+  } else {
+    obf = (uint16_t *)Xw;
+    o32b = Xw_f32;
+  }
+  dim3 g((unsigned)((T + AP_T - 1) / AP_T), (unsigned)((N + AP_T - 1) / AP_T));
+  hipLaunchKernelGGL((k_apply<TIN>), g, dim3(256), 0, st, X, N, (long long)T, Wh, mean, o32, obf,
+                     o32b);
+  return hipGetLastError();
+}
+
+hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, void *Xw,
+                         oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
+                         double *eig_out, void *ws, size_t ws_bytes, int *flags_dev) {
+  (void)ws_bytes;
+  if (raw_t == OICA_F64)
+    return whiten_impl<double>(st, N, T, (const double *)X, Xw, out_t, Xw_f32, V_out, mean_out,
+                               eig_out, (char *)ws, flags_dev);
+  return whiten_impl<float>(st, N, T, (const float *)X, Xw, out_t, Xw_f32, V_out, mean_out, eig_out,
+                            (char *)ws, flags_dev);
+}
+
+}  // namespace oica

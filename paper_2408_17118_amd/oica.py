@@ -1,0 +1,242 @@
+"""Thin Python binding of liboica (include/oica.h) over ctypes.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+liboica.so.  PyTorch provides device memory and the stream.  If the shared
+library is missing, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liboica.so")
+_lib = None
+
+OICA_F64, OICA_F32, OICA_BF16 = 0, 1, 2
+ROW_NOTCONV, ROW_CONV, ROW_PRUNED, ROW_DEGENERATE = 0, 1, 2, 3
+MAX_N = 128
+
+ERRORS = {
+    0: "OICA_OK", -1: "OICA_E_ARG", -2: "OICA_E_SHAPE", -3: "OICA_E_RANK",
+    -4: "OICA_E_NONFINITE", -5: "OICA_E_DEVICE", -6: "OICA_E_NOMEM", -7: "OICA_E_UNSUPPORTED",
+}
+
+
+class OicaError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {detail}")
+        self.code = code
+        self.detail = detail
+
+
+class FpParams(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
+                ("tol_bf16", C.c_double), ("refine_iters", C.c_int), ("traj_iters", C.c_int),
+                ("check_every", C.c_int)]
+
+
+class FpStats(C.Structure):
+    _fields_ = [("thread_iters", C.c_int64), ("passes", C.c_int),
+                ("refine_thread_iters", C.c_int64), ("ms", C.c_double)]
+
+
+class UniqueParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("gaussianity_test", C.c_int), ("n_top", C.c_int)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "oica_version": (C.c_int, []),
+    "oica_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "oica_destroy": (None, [_P]),
+    "oica_status_string": (C.c_char_p, [C.c_int]),
+    "oica_last_error": (C.c_char_p, [_P]),
+    "oica_set_stream": (C.c_int, [_P, _P]),
+    "oica_whiten": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P, _P, _P, _P]),
+    "oica_fixed_point": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P,
+                                   C.POINTER(FpParams), _P, _P, _P, _P, _P, C.POINTER(FpStats)]),
+    "oica_update": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, C.c_int, _P, _P, _P]),
+    "oica_kurtosis": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, _P]),
+    "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
+                              C.c_int, _P, _P, _P, _P, _P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load liboica.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise OicaError(-5, f"{_LIB_PATH} not built; run python -m paper_2408_17118_amd.build")
+        lib = C.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+_DT = {torch.float64: OICA_F64, torch.float32: OICA_F32, torch.bfloat16: OICA_BF16}
+
+
+class Context:
+    """An oica_ctx bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = self.lib.oica_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise OicaError(rc, "oica_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.oica_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise OicaError(rc, (self.lib.oica_last_error(self.h) or b"").decode())
+
+    def _tdev(self):
+        return torch.device("cuda", self.device)
+
+    # ---- a1-a3 ------------------------------------------------------------
+    def whiten(self, X: torch.Tensor, out_dtype=torch.float32, want_f32=True):
+        """X: N x T raw data (float64 or float32, device).  Returns
+        (Xw, Xw_f32, V, mean, eigval); Xw_f32 is Xw itself for FP32 output."""
+        _dev(X, "X")
+        N, T = X.shape
+        dev = self._tdev()
+        Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
+        Xw32 = None
+        if out_dtype == torch.bfloat16 and want_f32:
+            Xw32 = torch.empty((N, T), dtype=torch.float32, device=dev)
+        V = torch.empty((N, N), dtype=torch.float64, device=dev)
+        mean = torch.empty(N, dtype=torch.float64, device=dev)
+        eig = torch.empty(N, dtype=torch.float64, device=dev)
+        rc = self.lib.oica_whiten(self.h, N, T, _ptr(X), _DT[X.dtype], _ptr(Xw), _DT[out_dtype],
+                                  _ptr(Xw32), _ptr(V), _ptr(mean), _ptr(eig))
+        self._check(rc)
+        return Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig
+
+    # ---- a4-a11, a14 ----------------------------------------------------------
+    def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
+                    tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4):
+        _dev(Xw, "Xw")
+        _dev(W0, "W0")
+        if W0.dtype != torch.float32:
+            raise TypeError("W0 must be float32")
+        N, T = Xw.shape
+        K = W0.shape[0]
+        if Xw_f32 is None:
+            Xw_f32 = Xw
+        _dev(Xw_f32, "Xw_f32")
+        dev = self._tdev()
+        W = torch.empty((K, N), dtype=torch.float32, device=dev)
+        kurt = torch.empty(K, dtype=torch.float64, device=dev)
+        iters = torch.empty(K, dtype=torch.int32, device=dev)
+        status = torch.empty(K, dtype=torch.uint8, device=dev)
+        traj = torch.empty((K, traj_iters, 2), dtype=torch.float32, device=dev) if traj_iters else None
+        p = FpParams(max_iter, tol, OICA_BF16 if precision == "bf16" else OICA_F32, tol_bf16,
+                     refine_iters, traj_iters, check_every)
+        st = FpStats()
+        rc = self.lib.oica_fixed_point(self.h, N, T, _ptr(Xw), _DT[Xw.dtype], _ptr(Xw_f32), K,
+                                       _ptr(W0), C.byref(p), _ptr(W), _ptr(kurt), _ptr(iters),
+                                       _ptr(status), _ptr(traj), C.byref(st))
+        self._check(rc)
+        return {"W": W, "kurt": kurt, "iters": iters, "status": status, "traj": traj,
+                "thread_iters": int(st.thread_iters), "passes": int(st.passes),
+                "refine_thread_iters": int(st.refine_thread_iters), "ms": float(st.ms)}
+
+    def update(self, Xw, B):
+        _dev(Xw, "Xw")
+        _dev(B, "B")
+        N, T = Xw.shape
+        K = B.shape[0]
+        G = torch.empty((K, N), dtype=torch.float64, device=self._tdev())
+        s4 = torch.empty(K, dtype=torch.float64, device=self._tdev())
+        rc = self.lib.oica_update(self.h, N, T, _ptr(Xw), _DT[Xw.dtype], K, _ptr(B), _ptr(G), _ptr(s4))
+        self._check(rc)
+        return G, s4
+
+    def kurtosis(self, Xw_f32, W):
+        _dev(Xw_f32, "Xw_f32")
+        _dev(W, "W")
+        N, T = Xw_f32.shape
+        K = W.shape[0]
+        kurt = torch.empty(K, dtype=torch.float64, device=self._tdev())
+        rc = self.lib.oica_kurtosis(self.h, N, T, _ptr(Xw_f32), K, _ptr(W), _ptr(kurt))
+        self._check(rc)
+        return kurt
+
+    # ---- a12-a13 ----------------------------------------------------------------
+    def unique(self, W, kurt, status, T, tau=1e-3, gaussianity_test=True, n_top=0, cap=None):
+        _dev(W, "W")
+        K, N = W.shape
+        cap = K if cap is None else cap
+        dev = self._tdev()
+        U = torch.empty((max(cap, 1), N), dtype=torch.float64, device=dev)
+        ku = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        uu = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        rep = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        size = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        nu, na = C.c_int(), C.c_int()
+        p = UniqueParams(tau, 1 if gaussianity_test else 0, n_top)
+        rc = self.lib.oica_unique(self.h, N, T, K, _ptr(W), _ptr(kurt), _ptr(status), C.byref(p), cap,
+                                  _ptr(U), _ptr(ku), _ptr(uu), _ptr(rep), _ptr(size), C.byref(nu),
+                                  C.byref(na))
+        self._check(rc)
+        n = nu.value
+        return {"U": U[:n], "alpha": ku[:n], "upsilon": uu[:n], "rep": rep[:n], "size": size[:n],
+                "n_unique": n, "n_accepted": na.value}
+
+
+def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
+                 tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5):
+    """Whole hot path on device-resident raw data: whiten -> fixed point -> unique."""
+    xw_dtype = torch.bfloat16 if precision == "bf16" else torch.float32
+    Xw, Xw32, V, mean, eig = ctx.whiten(X, out_dtype=xw_dtype)
+    fp = ctx.fixed_point(Xw, W0, Xw_f32=Xw32, max_iter=max_iter, tol=tol, precision=precision,
+                         tol_bf16=tol_bf16, refine_iters=refine_iters)
+    res = ctx.unique(fp["W"], fp["kurt"], fp["status"], X.shape[1], tau=tau,
+                     gaussianity_test=gaussianity_test)
+    res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)
+    return res
