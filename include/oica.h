@@ -135,6 +135,8 @@ typedef struct {
   int traj_iters;        /* 0..16: passes recorded into traj               */
   int check_every;       /* host polls the active count every this many
                             passes (>= 1; 0 = default 4)                   */
+  int profile;           /* 1: time every fused update launch with HIP
+                            events on the context's stream (stats below)   */
 } oica_fp_params;
 
 typedef struct {         /* host */
@@ -142,6 +144,10 @@ typedef struct {         /* host */
   int passes;            /* passes that had at least one active row        */
   int64_t refine_thread_iters; /* FP32 refinement row updates (BF16 mode)  */
   double ms;             /* wall time of the call (stream-synchronised)    */
+  double update_ms;      /* profile = 1: summed duration of every fused
+                            update launch (launches issued after the last
+                            row stopped, before the next poll, exit at once) */
+  int update_launches;   /* profile = 1: number of those launches          */
 } oica_fp_stats;
 
 /* N in [1, OICA_MAX_N], T > N, K >= 1.

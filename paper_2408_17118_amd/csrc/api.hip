@@ -8,6 +8,7 @@
 
 #include <chrono>
 #include <string>
+#include <vector>
 
 #include "oica_internal.h"
 
@@ -20,6 +21,7 @@ struct oica_ctx {
   size_t ws_bytes = 0;
   int *small_dev = nullptr;    // 64 ints of device bookkeeping
   int *small_host = nullptr;   // 64 ints of pinned host memory
+  std::vector<hipEvent_t> events;  // start/stop pairs for kernel timing
   std::string err;
 };
 
@@ -134,6 +136,7 @@ void oica_destroy(oica_ctx *ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->small_dev) (void)hipFree(ctx->small_dev);
   if (ctx->small_host) (void)hipHostFree(ctx->small_host);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -192,13 +195,24 @@ int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
 int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const void *X, bool bf16,
                int K, float *B, int *act0, int *act1, float *gpart, float *s4part, FpControl *ctl,
                int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
-               float *traj, int traj_iters) {
+               float *traj, int traj_iters, bool profile, int *launched) {
   int kmax = K;  // upper bound on the active count (it never grows)
+  *launched = 0;
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
+    if (profile) {
+      while ((int)ctx->events.size() < 2 * (pass + 1)) {
+        hipEvent_t e;
+        HIP_TRY(ctx, hipEventCreate(&e));
+        ctx->events.push_back(e);
+      }
+      HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass], ctx->stream));
+    }
     HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
                                      gpart, s4part, ctl, pass));
+    if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
+    *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, plan, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
                                  s4part, tol, iters, status, traj, traj_iters));
     if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
@@ -262,9 +276,11 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj,
                                 params->traj_iters));
   const int check_every = params->check_every > 0 ? params->check_every : 4;
+  int launched = 0;
+  const bool profile = params->profile != 0;
   rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, ctl,
                   params->max_iter, params->tol, check_every, iters, status, traj,
-                  params->traj_iters);
+                  params->traj_iters, profile, &launched);
   if (rc) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                               ctx->stream));
@@ -276,6 +292,17 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
     stats->passes = h->passes;
     stats->refine_thread_iters = 0;
     stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->update_ms = 0.0;
+    stats->update_launches = 0;
+    if (profile) {
+      const int n = launched;
+      for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+        stats->update_ms += ms;
+      }
+      stats->update_launches = n;
+    }
   }
   return OICA_OK;
 }
