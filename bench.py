@@ -27,6 +27,26 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+HBM_PROFILE = os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_counters.txt")
+
+
+def counted_traffic():
+    """HBM bytes per launch of the fused update from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
+    changed since those counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(HBM_PROFILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        src = os.path.join(ROOT, fields["source_file"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -35,9 +55,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1024,
+    ap.add_argument("--cpu-rows", type=int, default=4096,
                     help="start rows in the CPU-oracle sample")
-    ap.add_argument("--cpu-passes", type=int, default=2)
+    ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -159,7 +179,8 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved_tflops / PEAK_FP32_MFMA_TFLOPS) if achieved_tflops else None,
-            "traffic": None,
+            "traffic": counted_traffic(),
+            "traffic_unit": "bytes/launch (HBM FETCH+WRITE, calibrated)",
             "avg_launch_ms": upd_ms / launches if launches else None,
             "avg_rows_per_launch": ti / launches if launches else None,
             "update_share_of_step": (upd_ms / args.steps) / ms_per_step if ms_per_step else None,

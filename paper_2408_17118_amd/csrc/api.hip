@@ -193,7 +193,8 @@ int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
 // Run passes on data X (F32) from the rows currently in B with active list
 // act[0] (count already in ctl->kact[0]); returns the number of passes launched.
 int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const void *X, bool bf16,
-               int K, float *B, int *act0, int *act1, float *gpart, float *s4part, FpControl *ctl,
+               int K, float *B, int *act0, int *act1, float *gpart, float *s4part, double *red,
+               FpControl *ctl,
                int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
                float *traj, int traj_iters, bool profile, int *launched) {
   int kmax = K;  // upper bound on the active count (it never grows)
@@ -214,7 +215,7 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
     if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
     *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, plan, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
-                                 s4part, tol, iters, status, traj, traj_iters));
+                                 s4part, red, tol, iters, status, traj, traj_iters));
     if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                                   ctx->stream));
@@ -259,6 +260,8 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   need += gfl * sizeof(float) + 256;            // gpart
   need += rows_max * sizeof(float) + 256;       // s4part
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
+  const size_t red_n = fp_reduce_doubles(plan, N, K);
+  need += red_n * sizeof(double) + 256;         // split-group sums
   need += 2 * ((size_t)K * sizeof(int) + 256);  // act lists
   need += sizeof(FpControl) + 256;
   rc = ensure_ws(ctx, need);
@@ -267,6 +270,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   float *gpart = cv.take<float>(gfl);
   float *s4part = cv.take<float>(rows_max);
   double *s4part64 = cv.take<double>(rows_max);
+  double *red = cv.take<double>(red_n);
   int *act0 = cv.take<int>(K);
   int *act1 = cv.take<int>(K);
   FpControl *ctl = cv.take<FpControl>(1);
@@ -278,7 +282,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   const int check_every = params->check_every > 0 ? params->check_every : 4;
   int launched = 0;
   const bool profile = params->profile != 0;
-  rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, ctl,
+  rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
                   params->max_iter, params->tol, check_every, iters, status, traj,
                   params->traj_iters, profile, &launched);
   if (rc) return rc;

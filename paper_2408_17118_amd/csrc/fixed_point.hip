@@ -248,30 +248,97 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// First stage of the split reduction: sums of SPLIT_GROUP consecutive splits,
+// in split order, for every (group, active position, feature) and for the
+// z^4 partial (stored as feature NP).  Grid-stride over all items so the
+// long-split tail passes (few rows, many splits) are as parallel as the
+// full-width passes.
+// ---------------------------------------------------------------------------
+constexpr int SPLIT_GROUP = 16;
+constexpr int RED_GRID = 2048;
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_split_reduce(FusedPlan plan, const FpControl *ctl, int pass,
+                                                      const float *__restrict__ gpart,
+                                                      const float *__restrict__ s4part,
+                                                      double *__restrict__ red) {
+  constexpr int RS = NP + 1;
+  const int kact = ctl->kact[pass & 1];
+  if (kact <= 0) return;
+  const int n_kb = (kact + plan.kwg - 1) / plan.kwg;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * plan.kwg;
+  const int groups = (n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
+  const long long per_group = (long long)kact * RS;
+  const long long items = (long long)groups * per_group;
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < items;
+       idx += (long long)gridDim.x * 256) {
+    const int g = (int)(idx / per_group);
+    const int rem = (int)(idx - (long long)g * per_group);
+    const int posn = rem / RS;
+    const int n = rem - posn * RS;
+    const int sp0 = g * SPLIT_GROUP;
+    float v[SPLIT_GROUP];
+#pragma unroll
+    for (int u = 0; u < SPLIT_GROUP; ++u) {
+      const int sp = sp0 + u;
+      v[u] = 0.f;
+      if (sp < n_sp)
+        v[u] = n < NP ? gpart[((size_t)sp * rows_pad + posn) * NP + n]
+                      : s4part[(size_t)sp * rows_pad + posn];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPLIT_GROUP; ++u) acc += (double)v[u];
+    red[(size_t)idx] = acc;
+  }
+}
+
+size_t fp_reduce_doubles(const FusedPlan &p, int N, int kmax) {
+  const size_t rows_max = fp_workspace_floats(p, N, kmax) / (size_t)fused_np(N);
+  return (rows_max / SPLIT_GROUP + (size_t)kmax + 1) * (size_t)(fused_np(N) + 1);
+}
+
+// ---------------------------------------------------------------------------
 // Epilogue: one wave per active position.
 // ---------------------------------------------------------------------------
 template <int NP>
 __global__ __launch_bounds__(256) void k_epilogue(
     FusedPlan plan, int N, long long T, float *__restrict__ Bm, const int *__restrict__ act_cur,
-    int *__restrict__ act_next, FpControl *ctl, int pass, const float *__restrict__ gpart,
-    const float *__restrict__ s4part, double tol, int32_t *__restrict__ iters,
-    uint8_t *__restrict__ status, float *__restrict__ traj, int traj_iters) {
+    int *__restrict__ act_next, FpControl *ctl, int pass, const double *__restrict__ red,
+    double tol, int32_t *__restrict__ iters, uint8_t *__restrict__ status,
+    float *__restrict__ traj, int traj_iters) {
+  constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
   const int lane = threadIdx.x % 64;
   const int posn = blockIdx.x * 4 + threadIdx.x / 64;
   if (posn >= kact) return;
   const int n_kb = (kact + plan.kwg - 1) / plan.kwg;
   const int n_sp = plan_splits(plan, n_kb);
-  const int rows_pad = n_kb * plan.kwg;
+  const int groups = (n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
   const int row = act_cur[posn];
 
   const int n0 = lane, n1 = lane + 64;
   double g0 = 0.0, g1 = 0.0, s4 = 0.0;
-  for (int sp = 0; sp < n_sp; ++sp) {
-    const float *src = gpart + ((size_t)sp * rows_pad + posn) * NP;
-    if (n0 < NP) g0 += (double)src[n0];
-    if (n1 < NP) g1 += (double)src[n1];
-    if (lane == 0) s4 += (double)s4part[(size_t)sp * rows_pad + posn];
+  // second stage: group sums in group order, EPI_U loads in flight per lane
+  constexpr int EPI_U = 8;
+  for (int q0 = 0; q0 < groups; q0 += EPI_U) {
+    double v0[EPI_U], v1[EPI_U], v4[EPI_U];
+#pragma unroll
+    for (int u = 0; u < EPI_U; ++u) {
+      const int q = q0 + u;
+      const bool ok = q < groups;
+      const double *src = red + ((size_t)(ok ? q : 0) * kact + posn) * RS;
+      v0[u] = (ok && n0 < NP) ? src[n0] : 0.0;
+      v1[u] = (ok && n1 < NP) ? src[n1] : 0.0;
+      v4[u] = (ok && lane == 0) ? src[NP] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPI_U; ++u) {
+      g0 += v0[u];
+      g1 += v1[u];
+      s4 += v4[u];
+    }
   }
   float *brow = Bm + (size_t)row * N;
   const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
@@ -416,13 +483,15 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
 
 hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax, float *B,
                            const int *act_cur, int *act_next, FpControl *ctl, int pass,
-                           const float *gpart, const float *s4part, double tol, int32_t *iters,
-                           uint8_t *status, float *traj, int traj_iters) {
+                           const float *gpart, const float *s4part, double *red, double tol,
+                           int32_t *iters, uint8_t *status, float *traj, int traj_iters) {
   const int np = fused_np(N);
   OICA_NP_SWITCH(np, {
+    hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
+                       (const FpControl *)ctl, pass, gpart, s4part, red);
     hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 3) / 4), dim3(256), 0, st, p, N,
-                       (long long)T, B, act_cur, act_next, ctl, pass, gpart, s4part, tol, iters,
-                       status, traj, traj_iters);
+                       (long long)T, B, act_cur, act_next, ctl, pass, (const double *)red, tol,
+                       iters, status, traj, traj_iters);
   });
   return hipGetLastError();
 }

@@ -70,10 +70,11 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
                                const void *X, bool bf16, const float *B, const int *act,
                                const int *kact_dev, int kact_host, float *gpart, float *s4part,
                                FpControl *ctl, int pass);
+size_t fp_reduce_doubles(const FusedPlan &p, int N, int kmax);
 hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax,
                            float *B, const int *act_cur, int *act_next, FpControl *ctl, int pass,
-                           const float *gpart, const float *s4part, double tol, int32_t *iters,
-                           uint8_t *status, float *traj, int traj_iters);
+                           const float *gpart, const float *s4part, double *red, double tol,
+                           int32_t *iters, uint8_t *status, float *traj, int traj_iters);
 hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t T, int K,
                              const float *B, const float *gpart, const float *s4part, double *G,
                              double *s4);

@@ -5,7 +5,7 @@
 //   k_mean_part / k_mean_final   mu = X 1 / T          (two-level, fixed order)
 //   k_cov_part  / k_cov_final    C = Xc Xc^T / T       (split over T, fixed order)
 //   k_jacobi                     C = E D E^T            (cyclic Jacobi, one work-group,
-//                                                        C in LDS, E in global memory)
+//                                                        C in LDS, E in LDS when it fits)
 //   k_canon                      descending order, sign rule, rank check,
 //                                Wh = D^(-1/2) E^T
 //   k_apply                      Xw = Wh (X - mu)       (FP64 tiles; FP32 / BF16 out)
@@ -18,8 +18,9 @@ namespace oica {
 
 constexpr int NMAX = OICA_MAX_N;
 constexpr int COV_TS = 32;        // samples per LDS tile in the covariance pass
-constexpr int CHUNK = 4096;       // samples per work-group in the reduction passes
-constexpr int MAX_CHUNKS = 256;
+constexpr int MIN_CHUNK = 256;    // fewest samples per work-group in the reduction passes
+constexpr int MAX_CHUNKS = 1024;  // mean pass
+constexpr int MAX_COV_CHUNKS = 512;
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -32,11 +33,14 @@ __device__ inline double ld(const TIN *p, size_t i) {
   return (double)p[i];
 }
 
-static inline int n_chunks(int64_t T) {
-  int64_t c = (T + CHUNK - 1) / CHUNK;
-  if (c > MAX_CHUNKS) c = MAX_CHUNKS;
+static inline int n_chunks(int64_t T, int cap = MAX_CHUNKS) {
+  int64_t c = T / MIN_CHUNK;
+  if (c > cap) c = cap;
   if (c < 1) c = 1;
   return (int)c;
+}
+static inline int n_cov_chunks(int N, int64_t T) {
+  return n_chunks(T, N <= 64 ? MAX_COV_CHUNKS : MAX_COV_CHUNKS / 2);
 }
 
 // Partial row sums over a sample chunk; one wave per row (strided), lanes over samples.
@@ -62,35 +66,40 @@ __global__ __launch_bounds__(256) void k_mean_part(const TIN *__restrict__ X, in
   }
 }
 
+// One wave per row: lanes take chunks lane, lane + 64, ...; fixed shuffle tree.
 __global__ void k_mean_final(int N, long long T, int chunks, const double *__restrict__ part,
                              double *__restrict__ mean) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   if (n >= N) return;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
-  mean[n] = s / (double)T;
+  for (int c = lane; c < chunks; c += 64) s += part[(size_t)c * N + n];
+  s = wsum(s);
+  if (lane == 0) mean[n] = s / (double)T;
 }
 
 // Partial centred second moments over a chunk.  256 threads = 16 x 16, each
-// owning an 8 x 8 block of the (padded 128 x 128) matrix.
-template <typename TIN>
+// owning an RB x RB block of the (padded 16 RB)^2 matrix (RB = 4 for N <= 64,
+// 8 for N <= 128).
+template <typename TIN, int RB>
 __global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int N, long long T,
                                                   int chunks, const double *__restrict__ mean,
                                                   double *__restrict__ part) {
-  __shared__ double xs[COV_TS][NMAX + 2];
+  constexpr int NP = 16 * RB;
+  __shared__ double xs[COV_TS][NP + 2];
   const int c = blockIdx.x;
   const long long t0 = (long long)c * T / chunks, t1 = (long long)(c + 1) * T / chunks;
   const int tid = threadIdx.x;
   const int ti = tid / 16, tj = tid % 16;
-  const bool active = (8 * ti < N) && (8 * tj < N);
-  double acc[8][8];
+  const bool active = (RB * ti < N) && (RB * tj < N);
+  double acc[RB][RB];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < RB; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < RB; ++b) acc[a][b] = 0.0;
   for (long long m0 = t0; m0 < t1; m0 += COV_TS) {
     __syncthreads();
-    for (int e = tid; e < COV_TS * NMAX; e += 256) {
+    for (int e = tid; e < COV_TS * NP; e += 256) {
       const int n = e / COV_TS, s = e % COV_TS;
       const long long m = m0 + s;
       double v = 0.0;
@@ -100,61 +109,84 @@ __global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int
     __syncthreads();
     if (active) {
       for (int s = 0; s < COV_TS; ++s) {
-        double a[8], b[8];
+        double a[RB], b[RB];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          a[q] = xs[s][8 * ti + q];
-          b[q] = xs[s][8 * tj + q];
+        for (int q = 0; q < RB; ++q) {
+          a[q] = xs[s][RB * ti + q];
+          b[q] = xs[s][RB * tj + q];
         }
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+        for (int p = 0; p < RB; ++p)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+          for (int q = 0; q < RB; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
       }
     }
   }
   if (active) {
-    for (int p = 0; p < 8; ++p)
-      for (int q = 0; q < 8; ++q) {
-        const int i = 8 * ti + p, j = 8 * tj + q;
+    for (int p = 0; p < RB; ++p)
+      for (int q = 0; q < RB; ++q) {
+        const int i = RB * ti + p, j = RB * tj + q;
         if (i < N && j < N) part[((size_t)c * N + i) * N + j] = acc[p][q];
       }
   }
 }
 
+// One wave per matrix element (lanes over chunks, fixed shuffle tree); the
+// upper-triangle partial is used for both (i, j) and (j, i), so C is exactly
+// symmetric.
 __global__ void k_cov_final(int N, long long T, int chunks, const double *__restrict__ part,
                             double *__restrict__ C) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   if (e >= N * N) return;
   const int i = e / N, j = e % N;
-  // symmetric by construction: sum the upper triangle element for both
   const int a = i < j ? i : j, b = i < j ? j : i;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[((size_t)c * N + a) * N + b];
-  C[e] = s / (double)T;
+  for (int c = lane; c < chunks; c += 64) s += part[((size_t)c * N + a) * N + b];
+  s = wsum(s);
+  if (lane == 0) C[e] = s / (double)T;
 }
 
 // Cyclic Jacobi with round-robin pairing: each round applies N/2 disjoint
 // rotations at once (rows first, then columns), a sweep is N-1 rounds
-// (N rounded up to even; the padding index is never rotated).
-// A lives in LDS; the accumulated rotations E live in global memory.
+// (N rounded up to even; the padding index is never rotated).  A rotation is
+// applied only while |a_pq| exceeds both N eps sqrt(|a_pp a_qq|) and
+// eps max_i |a_ii| (the rounding floor that rotations themselves leave in every
+// element, the absolute accuracy a dense symmetric eigensolver reaches); a
+// sweep without rotations ends the solve.
+// A lives in LDS; the accumulated rotations E live in LDS too when both fit
+// (E_LDS), else in global memory.
 constexpr int JAC_THREADS = 1024;
-constexpr int JAC_MAX_SWEEPS = 40;
+constexpr int JAC_MAX_SWEEPS = 30;
+constexpr double JAC_EPS = 2.220446049250313e-16;
 
+template <bool E_LDS>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__restrict__ C,
-                                                         double *__restrict__ E,
+                                                         double *__restrict__ Eg,
                                                          int *__restrict__ sweeps_out) {
-  __shared__ double a[NMAX * (NMAX + 1)];
+  extern __shared__ double jac_smem[];
   __shared__ double rc[NMAX / 2], rs[NMAX / 2];
   __shared__ int rp[NMAX / 2], rq[NMAX / 2];
   __shared__ int rotated;
   const int LD = N + 1;
+  double *a = jac_smem;
+  double *E = E_LDS ? jac_smem + N * LD : Eg;
   const int tid = threadIdx.x;
+  __shared__ double dscale;
+  const double thr = JAC_EPS * (double)N;
   for (int e = tid; e < N * N; e += JAC_THREADS) {
     const int i = e / N, j = e % N;
     a[i * LD + j] = C[e];
     E[e] = (i == j) ? 1.0 : 0.0;
   }
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < N; ++i) m = fmax(m, fabs(C[i * N + i]));
+    dscale = JAC_EPS * m;
+  }
+  __syncthreads();
+  // element loops: thread (k = tid / 16, jj = tid % 16) owns pair k, columns jj, jj+16, ...
+  const int tk = tid / 16, tj = tid % 16;
   const int ne = N + (N & 1);
   const int npair = ne / 2;
   int sweep = 0;
@@ -180,7 +212,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__r
         if (q < N) {
           const double apq = a[p * LD + q];
           const double app = a[p * LD + p], aqq = a[q * LD + q];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > dscale && fabs(apq) > thr * sqrt(fabs(app) * fabs(aqq))) {
             const double theta = (aqq - app) / (2.0 * apq);
             double t;
             if (fabs(theta) > 1e150)
@@ -199,40 +231,45 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__r
       }
       __syncthreads();
       // rows p, q of A  <-  J^T A
-      for (int e = tid; e < npair * N; e += JAC_THREADS) {
-        const int k = e / N, j = e % N;
-        const int q = rq[k];
-        if (q < 0 || rs[k] == 0.0) continue;
-        const int p = rp[k];
-        const double c = rc[k], s = rs[k];
-        const double apj = a[p * LD + j], aqj = a[q * LD + j];
-        a[p * LD + j] = c * apj - s * aqj;
-        a[q * LD + j] = s * apj + c * aqj;
+      if (tk < npair && rq[tk] >= 0 && rs[tk] != 0.0) {
+        const int p = rp[tk], q = rq[tk];
+        const double c = rc[tk], s = rs[tk];
+        for (int j = tj; j < N; j += 16) {
+          const double apj = a[p * LD + j], aqj = a[q * LD + j];
+          a[p * LD + j] = c * apj - s * aqj;
+          a[q * LD + j] = s * apj + c * aqj;
+        }
       }
       __syncthreads();
       // columns p, q of A and of E  <-  (.) J
-      for (int e = tid; e < npair * N; e += JAC_THREADS) {
-        const int k = e / N, i = e % N;
-        const int q = rq[k];
-        if (q < 0 || rs[k] == 0.0) continue;
-        const int p = rp[k];
-        const double c = rc[k], s = rs[k];
-        const double aip = a[i * LD + p], aiq = a[i * LD + q];
-        a[i * LD + p] = c * aip - s * aiq;
-        a[i * LD + q] = s * aip + c * aiq;
-        const double eip = E[i * N + p], eiq = E[i * N + q];
-        E[i * N + p] = c * eip - s * eiq;
-        E[i * N + q] = s * eip + c * eiq;
+      if (tk < npair && rq[tk] >= 0 && rs[tk] != 0.0) {
+        const int p = rp[tk], q = rq[tk];
+        const double c = rc[tk], s = rs[tk];
+        for (int i = tj; i < N; i += 16) {
+          const double aip = a[i * LD + p], aiq = a[i * LD + q];
+          a[i * LD + p] = c * aip - s * aiq;
+          a[i * LD + q] = s * aip + c * aiq;
+          const double eip = E[i * N + p], eiq = E[i * N + q];
+          E[i * N + p] = c * eip - s * eiq;
+          E[i * N + q] = s * eip + c * eiq;
+        }
       }
       __syncthreads();
     }
     if (rotated == 0) break;
     __syncthreads();
   }
-  // eigenvalues: diagonal, written to the last row of the scratch after E
-  for (int i = tid; i < N; i += JAC_THREADS) E[N * N + i] = a[i * LD + i];
+  if (E_LDS)
+    for (int e = tid; e < N * N; e += JAC_THREADS) Eg[e] = E[e];
+  // eigenvalues: the diagonal, stored after E
+  for (int i = tid; i < N; i += JAC_THREADS) Eg[N * N + i] = a[i * LD + i];
   if (tid == 0) sweeps_out[0] = sweep;
 }
+
+static size_t jacobi_lds_bytes(int N, bool e_lds) {
+  return (size_t)N * (N + 1) * sizeof(double) + (e_lds ? (size_t)N * N * sizeof(double) : 0);
+}
+constexpr size_t LDS_LIMIT = 160 * 1024 - 2048;  // leave room for the static arrays
 
 // Sort descending (rank by count, ties by index), sign rule, rank check,
 // whitening matrix Wh = D^(-1/2) E^T.
@@ -365,9 +402,10 @@ __global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N,
 
 size_t whiten_workspace_bytes(int N, int64_t T) {
   const int ch = n_chunks(T);
+  const int cch = n_cov_chunks(N, T);
   size_t b = 0;
   b += (size_t)ch * N * sizeof(double);          // mean partials
-  b += (size_t)ch * N * N * sizeof(double);      // covariance partials
+  b += (size_t)cch * N * N * sizeof(double);     // covariance partials
   b += (size_t)N * N * sizeof(double);           // C
   b += (size_t)(N * N + N) * sizeof(double);     // E + eigenvalues
   b += (size_t)N * N * sizeof(double);           // Wh
@@ -381,6 +419,7 @@ static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, vo
                               oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
                               double *eig_out, char *ws, int *flags_dev) {
   const int ch = n_chunks(T);
+  const int cch = n_cov_chunks(N, T);
   char *p = ws;
   auto take = [&](size_t bytes) {
     char *r = p;
@@ -388,7 +427,7 @@ static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, vo
     return r;
   };
   double *mpart = (double *)take((size_t)ch * N * sizeof(double));
-  double *cpart = (double *)take((size_t)ch * N * N * sizeof(double));
+  double *cpart = (double *)take((size_t)cch * N * N * sizeof(double));
   double *C = (double *)take((size_t)N * N * sizeof(double));
   double *E = (double *)take((size_t)(N * N + N) * sizeof(double));
   double *Wh = V_out ? V_out : (double *)take((size_t)N * N * sizeof(double));
@@ -398,13 +437,33 @@ static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, vo
 
   hipLaunchKernelGGL((k_mean_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mpart,
                      flags_dev);
-  hipLaunchKernelGGL(k_mean_final, dim3((N + 127) / 128), dim3(128), 0, st, N, (long long)T, ch,
+  hipLaunchKernelGGL(k_mean_final, dim3((N + 3) / 4), dim3(256), 0, st, N, (long long)T, ch,
                      mpart, mean);
-  hipLaunchKernelGGL((k_cov_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mean,
-                     cpart);
-  hipLaunchKernelGGL(k_cov_final, dim3((N * N + 255) / 256), dim3(256), 0, st, N, (long long)T, ch,
+  if (N <= 64)
+    hipLaunchKernelGGL((k_cov_part<TIN, 4>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
+                       mean, cpart);
+  else
+    hipLaunchKernelGGL((k_cov_part<TIN, 8>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
+                       mean, cpart);
+  hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, N, (long long)T, cch,
                      cpart, C);
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), 0, st, N, C, E, sweeps);
+  const bool e_lds = jacobi_lds_bytes(N, true) <= LDS_LIMIT;
+  const size_t lds = jacobi_lds_bytes(N, e_lds);
+  if (e_lds) {
+    // raise the dynamic-LDS cap where the runtime asks for it; a refusal
+    // surfaces as a launch error below
+    (void)hipFuncSetAttribute((const void *)k_jacobi<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(JAC_THREADS), lds, st, N, C, E, sweeps);
+  } else {
+    // raise the dynamic-LDS cap where the runtime asks for it; a refusal
+    // surfaces as a launch error below
+    (void)hipFuncSetAttribute((const void *)k_jacobi<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(JAC_THREADS), lds, st, N, C, E, sweeps);
+  }
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, N, E, Wh, eig, flags_dev);
   float *o32 = nullptr, *o32b = nullptr;
   uint16_t *obf = nullptr;
