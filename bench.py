@@ -10,6 +10,11 @@ random starts (24 Laplace, 16 Student-t nu=5, 12 uniform, 8 sines, 4 Gaussian).
 Prints one JSON line.  ``value`` is thread-iterations per second over the whole
 step (a thread-iteration is one update of one start vector: 2 N T MACs);
 ``ms_per_step`` is the time from raw data in HBM to the unique list on the host.
+
+``--workload precision_n128`` times the precision form instead (N=128, T=1e6,
+K=16384): BF16 data and BF16 MFMA with FP32 sums, then FP32 passes until the
+FP32 threshold; its roofline entry is the BF16 fused kernel against the BF16
+MFMA peak.
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 HBM_PROFILE = os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_counters.txt")
 
@@ -52,6 +58,8 @@ def counted_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="eeg_shaped_n64",
+                    choices=["eeg_shaped_n64", "precision_n128"])
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,8 +124,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda", 0)
-    prob = synth.eeg_shaped()
+    bf16 = args.workload == "precision_n128"
+    prob = synth.precision_workload() if bf16 else synth.eeg_shaped()
     N, T, K = prob.N, prob.T, prob.K
+    precision = "bf16" if bf16 else "f32"
     X = torch.from_numpy(prob.X).to(dev)
     W0 = torch.from_numpy(prob.W0.astype(np.float32)).to(dev)
     ctx = oica.Context(0)
@@ -129,7 +139,8 @@ def main():
         del src, dst
 
     def step(profile=False):
-        return oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, tau=1e-3, profile=profile)
+        return oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, tau=1e-3, profile=profile,
+                                 precision=precision, tol_bf16=1e-5, refine_iters=5)
 
     for i in range(args.warmup):
         r = step()
@@ -144,7 +155,8 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     ti = sum(r["fp"]["thread_iters"] for r in runs)
-    value = ti / (t1 - t0)
+    ti_refine = sum(r["fp"]["refine_thread_iters"] for r in runs)
+    value = (ti + ti_refine) / (t1 - t0)
     # dominant kernel: the fused update.  Algorithmic work per launch = 4 N T
     # flops per active row (2 N T MACs); average active rows per launch =
     # thread_iters / launches (launches issued after the last row stopped, before
@@ -153,6 +165,9 @@ def main():
     launches = sum(r["fp"]["update_launches"] for r in runs)
     flops = 4.0 * N * T * ti
     achieved_tflops = flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None
+    peak = PEAK_BF16_MFMA_TFLOPS if bf16 else PEAK_FP32_MFMA_TFLOPS
+    kname = ("k_fused_bf16<128,1> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA)" if bf16
+             else "k_fused_f32<64,2> (GEMM1 + cube + GEMM2, FP32 MFMA)")
     last = runs[-1]
     out = {
         "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",
@@ -165,28 +180,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
-        "config": {"workload": "eeg_shaped_n64", "N": N, "T": T, "K": K, "tol": 1e-6,
-                   "max_iter": 1000, "precision": "f32", "seed": 1,
+        "config": {"workload": args.workload, "N": N, "T": T, "K": K, "tol": 1e-6,
+                   "max_iter": 1000, "precision": precision, "seed": 3 if bf16 else 1,
                    "passes": last["fp"]["passes"], "thread_iters_per_step": last["fp"]["thread_iters"],
+                   "fp32_thread_iters_per_step": last["fp"]["refine_thread_iters"],
                    "n_unique": last["n_unique"], "n_accepted": last["n_accepted"],
                    "time_to_unique_ms": ms_per_step},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_fused_f32<64,2> (GEMM1 + cube + GEMM2, FP32 MFMA)",
+            "kernel": kname,
             "achieved": achieved_tflops,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": (achieved_tflops / PEAK_FP32_MFMA_TFLOPS) if achieved_tflops else None,
-            "traffic": counted_traffic(),
+            "frac": (achieved_tflops / peak) if achieved_tflops else None,
+            "traffic": None if bf16 else counted_traffic(),
             "traffic_unit": "bytes/launch (HBM FETCH+WRITE, calibrated)",
             "avg_launch_ms": upd_ms / launches if launches else None,
             "avg_rows_per_launch": ti / launches if launches else None,
             "update_share_of_step": (upd_ms / args.steps) / ms_per_step if ms_per_step else None,
         },
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not bf16:
         cb = cpu_baseline(prob, args.cpu_rows, args.cpu_passes)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     ctx.close()

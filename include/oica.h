@@ -119,10 +119,14 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
  *   kurt[l] = sum_m (b_l . x_m)^4 / T - 3 over the FP32 data, FP64 sums.
  *
  * precision = OICA_F32: the passes run on FP32 data (Xw of xw_t = OICA_F32).
- * precision = OICA_BF16: the passes run on BF16 data (Xw of xw_t = OICA_BF16,
- *   BF16 products, FP32 sums) with threshold tol_bf16; then refine_iters
- *   passes on the FP32 copy Xw_f32 for every converged row, and a row counts
- *   as CONV if its last refinement step is below tol.
+ * precision = OICA_BF16: the passes run on BF16 data (Xw of xw_t = OICA_BF16;
+ *   each row carried as BF16 hi + lo parts, z^3 rounded to BF16, FP32 sums)
+ *   with threshold tol_bf16, until every row has stopped, at most K/64 rows
+ *   are left, or the active count has not shrunk over two polls.  Then every
+ *   row that converged on BF16 data or was still moving continues on the FP32
+ *   copy Xw_f32 (FP32 kernels, threshold tol) for up to
+ *   max(refine_iters, max_iter - BF16 passes) passes; only the FP32 test
+ *   makes a row CONV.
  * traj: optional K x traj_iters x 2 FP32 record of (kurtosis of the row
  *   before pass t+1, step d of pass t+1); NaN once a row has stopped.
  * ------------------------------------------------------------------------- */
@@ -166,8 +170,8 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
 /* One unnormalised update for K given rows (eqs. 4-5, Algorithm 2 order):
  * G = (Z o Z o Z) Xw^T / T - 3 B with Z = B Xw, and s4 = sum_m z^4 / T per row.
  * B: K x N FP32 (used as given, not normalised).  G: K x N FP64, s4: K FP64.
- * Runs the same fused kernel and split reduction as oica_fixed_point.
- * Does not synchronise. */
+ * xw_t = OICA_F32 or OICA_BF16 selects the kernel family of oica_fixed_point's
+ * passes (BF16: B and z^3 rounded to BF16, FP32 sums).  Does not synchronise. */
 int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t, int K,
                 const float *B, double *G, double *s4);
 

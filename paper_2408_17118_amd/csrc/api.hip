@@ -196,9 +196,14 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
                int K, float *B, int *act0, int *act1, float *gpart, float *s4part, double *red,
                FpControl *ctl,
                int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
-               float *traj, int traj_iters, bool profile, int *launched) {
+               float *traj, int traj_iters, bool profile, int *launched, double *kernel_ms,
+               int exit_below = 0, int stall_polls = 0) {
+  // exit_below > 0: stop once at most exit_below rows are active;
+  // stall_polls > 0: stop once the active count has not shrunk over that many polls.
   int kmax = K;  // upper bound on the active count (it never grows)
+  int stalled = 0;
   *launched = 0;
+  *kernel_ms = 0.0;
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
@@ -223,7 +228,18 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       const FpControl *h = (const FpControl *)ctx->small_host;
       const int left = h->kact[(pass + 1) & 1];
       if (left == 0) break;
+      stalled = (left >= kmax) ? stalled + 1 : 0;
       kmax = left;
+      if (exit_below > 0 && left <= exit_below) break;
+      if (stall_polls > 0 && stalled >= stall_polls) break;
+    }
+  }
+  // every pass has been polled past, so all events have completed
+  if (profile) {
+    for (int i = 0; i < *launched; ++i) {
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+      *kernel_ms += ms;
     }
   }
   return OICA_OK;
@@ -249,7 +265,6 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   const bool bf16 = params->precision == OICA_BF16;
   if (bf16 && xw_t != OICA_BF16) return fail(ctx, OICA_E_ARG, "BF16 precision needs xw_t == OICA_BF16");
   if (!bf16 && xw_t != OICA_F32) return fail(ctx, OICA_E_ARG, "F32 precision needs xw_t == OICA_F32");
-  if (bf16) return fail(ctx, OICA_E_UNSUPPORTED, "BF16 precision is not built into this library");
 
   const auto t0 = std::chrono::steady_clock::now();
   const FusedPlan plan = make_plan(N, T, K, bf16);
@@ -262,8 +277,8 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
   const size_t red_n = fp_reduce_doubles(plan, N, K);
   need += red_n * sizeof(double) + 256;         // split-group sums
-  need += 2 * ((size_t)K * sizeof(int) + 256);  // act lists
-  need += sizeof(FpControl) + 256;
+  need += 3 * ((size_t)K * sizeof(int) + 256);  // act lists
+  need += 2 * (sizeof(FpControl) + 256);
   rc = ensure_ws(ctx, need);
   if (rc) return rc;
   Carve cv{(char *)ctx->ws};
@@ -273,40 +288,65 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   double *red = cv.take<double>(red_n);
   int *act0 = cv.take<int>(K);
   int *act1 = cv.take<int>(K);
+  int *act2 = cv.take<int>(K);
   FpControl *ctl = cv.take<FpControl>(1);
+  FpControl *ctl2 = cv.take<FpControl>(1);
 
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, sizeof(FpControl), ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 2 * 256, ctx->stream));
   HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj,
                                 params->traj_iters));
   const int check_every = params->check_every > 0 ? params->check_every : 4;
   int launched = 0;
+  double kernel_ms = 0.0;
   const bool profile = params->profile != 0;
+  // main loop: FP32 data at tol, or BF16 data at tol_bf16.  The BF16 loop ends
+  // early once at most K/64 rows are left or the active count stops shrinking
+  // (rows that sit at the BF16 rounding floor just above tol_bf16 would
+  // otherwise use up max_iter passes); those rows finish on FP32 data.
+  const int bf16_exit = bf16 ? (K / 64 > 0 ? K / 64 : 1) : 0;
+  const int bf16_stall = bf16 ? 2 : 0;
   rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
-                  params->max_iter, params->tol, check_every, iters, status, traj,
-                  params->traj_iters, profile, &launched);
+                  params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
+                  status, traj, params->traj_iters, profile, &launched, &kernel_ms, bf16_exit,
+                  bf16_stall);
   if (rc) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                               ctx->stream));
-  HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan, N, T, Xw_f32, K, W_out, s4part64, kurt));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const FpControl main_ctl = *(const FpControl *)ctx->small_host;
+  long long refine_ti = 0;
+  if (bf16) {
+    // FP32 passes for every row that converged on BF16 data or is still moving
+    const int left_rows = main_ctl.kact[launched & 1];
+    const int budget_left = params->max_iter - launched;
+    const int fp32_passes = budget_left > params->refine_iters ? budget_left : params->refine_iters;
+    const FusedPlan plan32 = make_plan(N, T, K, false);
+    HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2,
+                                      (launched & 1) ? act1 : act0, left_rows));
+    int l2 = 0;
+    double ms2 = 0.0;
+    if (fp32_passes > 0) {
+      rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
+                      ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
+                      false, &l2, &ms2);
+      if (rc) return rc;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl2, sizeof(FpControl), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    refine_ti = ((const FpControl *)ctx->small_host)->thread_iters;
+  }
+  HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
+                               s4part64, kurt));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
-    const FpControl *h = (const FpControl *)ctx->small_host;
-    stats->thread_iters = h->thread_iters;
-    stats->passes = h->passes;
-    stats->refine_thread_iters = 0;
+    stats->thread_iters = main_ctl.thread_iters;
+    stats->passes = main_ctl.passes;
+    stats->refine_thread_iters = refine_ti;
     stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    stats->update_ms = 0.0;
-    stats->update_launches = 0;
-    if (profile) {
-      const int n = launched;
-      for (int i = 0; i < n; ++i) {
-        float ms = 0.f;
-        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
-        stats->update_ms += ms;
-      }
-      stats->update_launches = n;
-    }
+    stats->update_ms = profile ? kernel_ms : 0.0;
+    stats->update_launches = profile ? launched : 0;
   }
   return OICA_OK;
 }
@@ -319,8 +359,10 @@ int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t
   if (rc) return rc;
   if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1");
   if (!Xw || !B || !G || !s4) return fail(ctx, OICA_E_ARG, "Xw, B, G and s4 must be non-null");
-  if (xw_t != OICA_F32) return fail(ctx, OICA_E_UNSUPPORTED, "xw_t must be OICA_F32");
-  const FusedPlan plan = make_plan(N, T, K, false);
+  if (xw_t != OICA_F32 && xw_t != OICA_BF16)
+    return fail(ctx, OICA_E_UNSUPPORTED, "xw_t must be OICA_F32 or OICA_BF16");
+  const bool bf16 = xw_t == OICA_BF16;
+  const FusedPlan plan = make_plan(N, T, K, bf16);
   const size_t gfl = fp_workspace_floats(plan, N, K);
   const size_t rows_max = gfl / fused_np(N);
   rc = ensure_ws(ctx, gfl * 4 + rows_max * 4 + 1024);
@@ -329,7 +371,7 @@ int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t
   float *gpart = cv.take<float>(gfl);
   float *s4part = cv.take<float>(rows_max);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, Xw, false, B, nullptr, nullptr, K, gpart,
+  HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, Xw, bf16, B, nullptr, nullptr, K, gpart,
                                    s4part, nullptr, 0));
   HIP_TRY(ctx, launch_update_out(ctx->stream, plan, N, T, K, B, gpart, s4part, G, s4));
   return OICA_OK;

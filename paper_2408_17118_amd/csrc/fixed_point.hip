@@ -239,6 +239,191 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
 }
 
 // ---------------------------------------------------------------------------
+// BF16 pass kernel: X stored in BF16, both contractions on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation; z^3 rounded to BF16
+// (nearest even) to feed GEMM2.  Each row b is split once per work item into
+// b_hi = bf16(b) and b_lo = bf16(b - b_hi), and GEMM1 runs on both, so z carries
+// b to ~2^-17 relative: rounding b itself to BF16 would make the update map
+// piecewise constant in b and leave the step stuck near 1e-4.  Operand layout (lane l, h = l / 32, i = l % 32): A[i][8h + j],
+// B[8h + j][i] for j = 0..7 (8 bf16 per lane); D as in the FP32 kernel.
+// GEMM1 reads the transposed LDS copy xt[m][n] (8 consecutive features, one
+// 16-byte read); GEMM2 reads xs[n][m] (two runs of 4 consecutive samples).
+// With v = 8q + j for MFMA q of a 32-sample sub-tile, GEMM1's accumulator
+// lane holds sample m = 16q + 8(j/4) + 4h + j%4 at k-index 8h + j, so the
+// cubed registers are GEMM2's B operand directly.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int BT = 64;          // samples per LDS tile
+constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
+template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
+
+template <int NP, int WK>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
+    const __bf16 *__restrict__ X, int N, long long T, FusedPlan plan, const float *__restrict__ Bm,
+    const int *__restrict__ act, const int *__restrict__ kact_dev, int kact_host,
+    float *__restrict__ gpart, float *__restrict__ s4part, FpControl *ctl, int pass) {
+  constexpr int KWG = WAVES * WK * 32;
+  constexpr int XTS = BfStride<NP>::v;
+  __shared__ __attribute__((aligned(16))) __bf16 xs[NP * BSX];
+  __shared__ __attribute__((aligned(16))) __bf16 xt[BT * XTS];
+
+  const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
+  if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->kact[(pass + 1) & 1] = 0;
+    if (kact > 0) {
+      ctl->passes = pass + 1;
+      ctl->thread_iters += kact;
+    }
+  }
+  if (kact <= 0) return;
+
+  const int n_kb = (kact + KWG - 1) / KWG;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int rows_pad = n_kb * KWG;
+  const int work = n_kb * n_sp;
+  const int per_xcd_items = (work + 7) / 8;
+  const int per_xcd_wgs = plan.grid / 8;
+  const int xcd = blockIdx.x % 8;
+  const int local = blockIdx.x / 8;
+
+  const int tid = threadIdx.x;
+  const int wave = tid / 64;
+  const int lane = tid % 64;
+  const int h = lane / 32;
+  const int li = lane % 32;
+  const bool vec_ok = (T % 8) == 0;
+
+  for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
+    const int w_item = xcd * per_xcd_items + it;
+    if (w_item >= work) break;
+    const int kb = w_item % n_kb;
+    const int sp = w_item / n_kb;
+    const long long sub0 = (long long)sp * plan.n_sub / n_sp;
+    const long long sub1 = (long long)(sp + 1) * plan.n_sub / n_sp;
+    const long long t_begin = sub0 * 32;
+    long long t_end = sub1 * 32;
+    if (t_end > T) t_end = T;
+
+    bf16x8 breg[WK][NP / 16], blo[WK][NP / 16];
+    int pos[WK];
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      pos[w] = kb * KWG + wave * WK * 32 + w * 32 + li;
+      int row = -1;
+      if (pos[w] < kact) row = act ? act[pos[w]] : pos[w];
+#pragma unroll
+      for (int s = 0; s < NP / 16; ++s) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int n = 16 * s + 8 * h + j;
+          const float b = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
+          const __bf16 hi = (__bf16)b;
+          breg[w][s][j] = hi;
+          blo[w][s][j] = (__bf16)(b - (float)hi);
+        }
+      }
+    }
+
+    f32x16 gacc[WK][NP / 32];
+    float s4acc[WK];
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      s4acc[w] = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
+    }
+
+    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT) {
+      __syncthreads();
+      // fill: 8 consecutive samples of one feature row per thread-iteration
+      for (int e = tid; e < NP * (BT / 8); e += WAVES * 64) {
+        const int n = e / (BT / 8);
+        const int mc = (e % (BT / 8)) * 8;
+        const long long gm = m_tile + mc;
+        bf16x8 v;
+        if (n < N && vec_ok && gm + 8 <= t_end) {
+          v = *reinterpret_cast<const bf16x8 *>(X + (size_t)n * (size_t)T + (size_t)gm);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            v[j] = (n < N && gm + j < t_end) ? X[(size_t)n * (size_t)T + (size_t)(gm + j)]
+                                             : (__bf16)0.f;
+        }
+        *reinterpret_cast<bf16x8 *>(&xs[n * BSX + mc]) = v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xt[(mc + j) * XTS + n] = v[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sub = 0; sub < BT / 32; ++sub) {
+        if (m_tile + sub * 32 >= t_end) break;
+        const int m0 = sub * 32;
+        f32x16 zacc[WK];
+#pragma unroll
+        for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
+#pragma unroll
+        for (int s = 0; s < NP / 16; ++s) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&xt[(m0 + li) * XTS + 16 * s + 8 * h]);
+#pragma unroll
+          for (int w = 0; w < WK; ++w) {
+            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, breg[w][s], zacc[w], 0, 0, 0);
+            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[w][s], zacc[w], 0, 0, 0);
+          }
+        }
+        bf16x8 p3[WK][2];
+#pragma unroll
+        for (int w = 0; w < WK; ++w) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float z = zacc[w][v];
+            const float z2 = z * z;
+            p3[w][v / 8][v % 8] = (__bf16)(z2 * z);
+            s4acc[w] = fmaf(z2, z2, s4acc[w]);
+          }
+        }
+#pragma unroll
+        for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const __bf16 *src = &xs[(nb * 32 + li) * BSX + m0 + 16 * q + 4 * h];
+            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(src);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(src + 8);
+            bf16x8 a;
+            a[0] = lo[0]; a[1] = lo[1]; a[2] = lo[2]; a[3] = lo[3];
+            a[4] = hi[0]; a[5] = hi[1]; a[6] = hi[2]; a[7] = hi[3];
+#pragma unroll
+            for (int w = 0; w < WK; ++w)
+              gacc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, p3[w][q], gacc[w][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
+      if (pos[w] < kact) {
+        if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
+        float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
+#pragma unroll
+        for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            f32x4 v4;
+            v4[0] = gacc[w][nb][4 * q + 0];
+            v4[1] = gacc[w][nb][4 * q + 1];
+            v4[2] = gacc[w][nb][4 * q + 2];
+            v4[3] = gacc[w][nb][4 * q + 3];
+            *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Wave reductions (64 lanes).
 // ---------------------------------------------------------------------------
 __device__ inline double wave_sum(double v) {
@@ -407,6 +592,19 @@ __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *_
   }
 }
 
+// Active set of the FP32 phase after a BF16 loop, built in `dst`: the rows that
+// converged on BF16 data (status reset to NOTCONV until they pass the FP32
+// test) and the `left` rows still active when the BF16 loop ended.
+__global__ void k_refine_select(int K, uint8_t *__restrict__ status, int *__restrict__ dst,
+                                FpControl *ctl, const int *__restrict__ left_list, int left) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K && status[i] == OICA_ROW_CONV) {
+    status[i] = OICA_ROW_NOTCONV;
+    dst[atomicAdd(&ctl->kact[0], 1)] = i;
+  }
+  if (i < left) dst[atomicAdd(&ctl->kact[0], 1)] = left_list[i];
+}
+
 // G = sum_sp gpart / T - 3 B and s4 = sum_sp s4part / T for rows 0..K-1
 // (positions equal rows).
 template <int NP>
@@ -470,8 +668,16 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
                                bool bf16, const float *B, const int *act, const int *kact_dev,
                                int kact_host, float *gpart, float *s4part, FpControl *ctl,
                                int pass) {
-  if (bf16) return hipErrorInvalidValue;  // BF16 data use the BF16 kernel family
   const int np = fused_np(N);
+  if (bf16) {
+    OICA_NP_SWITCH(np, {
+      constexpr int WK_ = NP_ <= 64 ? 2 : 1;
+      hipLaunchKernelGGL((k_fused_bf16<NP_, WK_>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                         (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
+                         s4part, ctl, pass);
+    });
+    return hipGetLastError();
+  }
   OICA_NP_SWITCH(np, {
     constexpr int WK_ = NP_ <= 64 ? 2 : 1;
     hipLaunchKernelGGL((k_fused_f32<NP_, WK_, false>), dim3(p.grid), dim3(WAVES * 64), 0, st,
@@ -493,6 +699,13 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                        (long long)T, B, act_cur, act_next, ctl, pass, (const double *)red, tol,
                        iters, status, traj, traj_iters);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,
+                                const int *left_list, int left) {
+  hipLaunchKernelGGL(k_refine_select, dim3((K + 255) / 256), dim3(256), 0, st, K, status, dst, ctl,
+                     left_list, left);
   return hipGetLastError();
 }
 

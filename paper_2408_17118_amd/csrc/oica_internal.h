@@ -50,15 +50,6 @@ hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_d
 size_t whiten_workspace_bytes(int N, int64_t T);
 
 // fixed_point.hip
-struct FpBuffers {
-  float *B;          // K x N current rows (FP32), output order = row order
-  int *act[2];       // active lists, double buffered
-  float *gpart;      // splits x K_cap x NP partial G
-  float *s4part;     // splits x K_cap partial sum z^4 (update mode)
-  double *s4part64;  // splits x K_cap partial sum z^4 (kurtosis mode)
-  FpControl *ctl;
-};
-
 int fused_np(int N);  // padded feature count used by the kernels for N
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16);
 size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
@@ -81,9 +72,8 @@ hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t 
 hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            const float *X, int K, const float *W, double *s4part64,
                            double *kurt);
-hipError_t launch_finish_rows(hipStream_t st, int K, int N, const float *B, float *W_out);
-hipError_t launch_refine_select(hipStream_t st, int K, const uint8_t *status, int *act0,
-                                FpControl *ctl, uint8_t *status_out);
+hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,
+                                const int *left_list, int left);
 
 // unique.hip
 size_t unique_workspace_bytes(int K);

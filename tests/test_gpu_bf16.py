@@ -1,0 +1,126 @@
+"""BF16 precision form: X stored in BF16, BF16 MFMA with FP32 sums, z^3 rounded
+to BF16, then FP32 refinement passes on the converged rows.  Everything goes
+through the C ABI; the comparisons are against the FP64 oracle.
+
+* One BF16 update: the oracle runs on the same BF16-rounded data (exactly
+  representable in FP64) and the FP32 rows.  The kernel carries each row as
+  bf16 hi + lo parts (relative error <= 2^-17 per entry), so the remaining
+  difference is the nearest-even rounding of z^3 to BF16 (relative <= 2^-9):
+  |dG_n| <= 2^-9 mean_m(|x_nm| |z_m|^3) + 2^-16 mean_m(|x_nm| 3 z_m^2 |x|.|b|)
+  + FP32 summation error.
+* After refinement the unique set must meet the FP32 contract: |cos| >= 1-1e-6
+  against the oracle, kurtosis within 1e-5 max(|alpha|, 0.1).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ica
+from paper_2408_17118_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def bf16_round(x):
+    """Nearest-even rounding of float64 values to bfloat16 (returned as float64)."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                       # x = m 2^e, 0.5 <= |m| < 1
+    r = np.round(m * 256.0)                  # 8 significant bits; half to even
+    out = np.ldexp(r / 256.0, e)
+    out[x == 0] = 0.0
+    return out
+
+
+def test_bf16_round_helper():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 1e-3, 3.14159])
+    r = bf16_round(vals)
+    t = torch.tensor(vals, dtype=torch.float64).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(r, t)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2408_17118_amd import oica
+    c = oica.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.mark.parametrize("N,T,K", [(8, 10_000, 256), (64, 20_000, 300), (128, 12_347, 129),
+                                   (40, 5_003, 77)])
+def test_update_bf16_within_rounding_bound(ctx, N, T, K):
+    p = synth.make_problem(synth.eeg_kinds(N), T=T, K=K, seed=N * 3 + 1)
+    Xw, *_ = ica.whiten(p.X)
+    Xb = bf16_round(Xw)
+    B32 = ica.normalise_rows(p.W0).astype(np.float32)
+    Bb = B32.astype(np.float64)
+    G, s4 = ctx.update(dev(Xb.astype(np.float32), torch.bfloat16), dev(B32))
+    Gr, s4r = ica.update(Xb, Bb)
+    Z = Bb @ Xb
+    dz = 2.0 ** -16 * (np.abs(Bb) @ np.abs(Xb))        # error of z from the hi/lo split
+    bound = (2.0 ** -9 * (np.abs(Z) ** 3 @ np.abs(Xb).T) + 3.0 * ((Z ** 2 * dz) @ np.abs(Xb).T)) / T \
+        + 2e-5 + 1e-5 * np.abs(Gr)
+    err = np.abs(G.cpu().numpy() - Gr)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    # s4 uses the FP32 z; its error comes from the hi/lo split of b
+    s4b = 4.0 * (np.abs(Z) ** 3 * dz).mean(axis=1) + 2e-5 + 1e-5 * np.abs(s4r)
+    assert np.all(np.abs(s4.cpu().numpy() - s4r) <= s4b)
+
+
+def _run(ctx, p, precision):
+    from paper_2408_17118_amd import oica
+    return oica.ordering_ica(ctx, dev(p.X), dev(p.W0.astype(np.float32)), tol=1e-6, max_iter=1000,
+                             precision=precision, tol_bf16=1e-5, refine_iters=5)
+
+
+def _check_against(res, Ur_raw, ar, upsr, n_acc, label):
+    V = res["V"].cpu().numpy()
+    U = res["U"].cpu().numpy()[: res["n_accepted"]] @ V
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    a = res["alpha"].cpu().numpy()[: res["n_accepted"]]
+    assert res["n_accepted"] == n_acc, (label, res["n_accepted"], n_acc)
+    cos = np.abs(U @ Ur_raw[:n_acc].T)
+    match = cos.argmax(axis=1)
+    best = cos.max(axis=1)
+    print(f"{label}: min |cos| {best.min():.12f}, max |dalpha|/max(|a|,0.1) "
+          f"{np.max(np.abs(a - ar[match]) / np.maximum(np.abs(ar[match]), 0.1)):.3e}")
+    assert np.all(best >= 1 - 1e-6)
+    assert len(set(match)) == n_acc
+    assert np.all(np.abs(a - ar[match]) <= 1e-5 * np.maximum(np.abs(ar[match]), 0.1))
+    for r in range(n_acc):
+        j = match[r]
+        if j != r:
+            assert abs(upsr[j] - upsr[r]) <= 1e-5 * max(upsr[r], 1e-3)
+
+
+def test_bf16_small_mixture_end_to_end(ctx):
+    p = synth.small_mixture()
+    res = _run(ctx, p, "bf16")
+    ref = ica.ordering_ica(p.X, p.W0, tol=1e-10, max_iter=1000)
+    assert res["fp"]["refine_thread_iters"] > 0
+    _check_against(res, ref["U_raw"], ref["alpha"], ref["upsilon"], ref["n_accepted"], "bf16 n8")
+
+
+def test_bf16_eeg_shaped_matches_oracle():
+    """Full EEG-shaped size: BF16 + refinement gives the oracle's unique set."""
+    from paper_2408_17118_amd import oica
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "eeg_shaped_n64_oracle.json")))
+    p = synth.eeg_shaped()
+    c = oica.Context(0)
+    res = _run(c, p, "bf16")
+    print(f"bf16 eeg: passes {res['fp']['passes']}, thread-iterations {res['fp']['thread_iters']}, "
+          f"refinement {res['fp']['refine_thread_iters']}")
+    _check_against(res, np.array(ref["U_raw"]), np.array(ref["alpha"]), np.array(ref["upsilon"]),
+                   ref["n_accepted"], "bf16 eeg")
+    c.close()
