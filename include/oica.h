@@ -141,6 +141,14 @@ typedef struct {
                             passes (>= 1; 0 = default 4)                   */
   int profile;           /* 1: time every fused update launch with HIP
                             events on the context's stream (stats below)   */
+  int refine_groups;     /* BF16 only.  0: every row that converged on BF16
+                            data takes the FP32 passes.  1: those rows are
+                            first grouped (greedy, 1 - |cos| <= 1e-6, i.e.
+                            numerically the same BF16 fixed point); only the
+                            lowest-index row of each group takes the FP32
+                            passes and the kurtosis pass, and the other
+                            members receive its row (with their own sign),
+                            status and kurtosis.                           */
 } oica_fp_params;
 
 typedef struct {         /* host */

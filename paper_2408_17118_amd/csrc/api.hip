@@ -277,8 +277,9 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
   const size_t red_n = fp_reduce_doubles(plan, N, K);
   need += red_n * sizeof(double) + 256;         // split-group sums
-  need += 3 * ((size_t)K * sizeof(int) + 256);  // act lists
-  need += 2 * (sizeof(FpControl) + 256);
+  need += 4 * ((size_t)K * sizeof(int) + 256);  // act lists + kurtosis list
+  need += 3 * (sizeof(FpControl) + 256);
+  need += unique_workspace_bytes(K) + 256;      // grouping of BF16 fixed points
   rc = ensure_ws(ctx, need);
   if (rc) return rc;
   Carve cv{(char *)ctx->ws};
@@ -289,11 +290,14 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   int *act0 = cv.take<int>(K);
   int *act1 = cv.take<int>(K);
   int *act2 = cv.take<int>(K);
+  int *kurt_list = cv.take<int>(K);
   FpControl *ctl = cv.take<FpControl>(1);
   FpControl *ctl2 = cv.take<FpControl>(1);
+  (void)cv.take<FpControl>(1);  // third control block (kurtosis list), ctl2 + 256 bytes
+  void *gwork = cv.take<char>(unique_workspace_bytes(K));
 
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 2 * 256, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 3 * 256, ctx->stream));
   HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj,
                                 params->traj_iters));
   const int check_every = params->check_every > 0 ? params->check_every : 4;
@@ -316,29 +320,55 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   const FpControl main_ctl = *(const FpControl *)ctx->small_host;
   long long refine_ti = 0;
+  bool kurt_done = false;
   if (bf16) {
-    // FP32 passes for every row that converged on BF16 data or is still moving
     const int left_rows = main_ctl.kact[launched & 1];
+    const int *left_list = (launched & 1) ? act1 : act0;
     const int budget_left = params->max_iter - launched;
     const int fp32_passes = budget_left > params->refine_iters ? budget_left : params->refine_iters;
     const FusedPlan plan32 = make_plan(N, T, K, false);
-    HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2,
-                                      (launched & 1) ? act1 : act0, left_rows));
     int l2 = 0;
     double ms2 = 0.0;
-    if (fp32_passes > 0) {
-      rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
-                      ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
-                      false, &l2, &ms2);
-      if (rc) return rc;
+    if (params->refine_groups) {
+      // group rows that sit at numerically the same BF16 fixed point; one row
+      // per group takes the FP32 passes and the kurtosis pass
+      int *cluster = nullptr, *reps = nullptr;
+      HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 4 * sizeof(int), ctx->stream));
+      HIP_TRY(ctx, launch_groups(ctx->stream, N, K, W_out, status, 1e-6, gwork, ctx->small_dev,
+                                 ctx->small_host, &cluster, &reps));
+      const int n_groups = ctx->small_host[1];
+      FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
+      HIP_TRY(ctx, hipMemsetAsync(ctl3, 0, sizeof(FpControl), ctx->stream));
+      HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, n_groups, status, act2, ctl2,
+                                      left_list, left_rows, kurt_list, ctl3));
+      if (fp32_passes > 0) {
+        rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
+                        ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
+                        false, &l2, &ms2);
+        if (rc) return rc;
+      }
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, Xw_f32, K, W_out, s4part64, kurt,
+                                   kurt_list, &ctl3->kact[0]));
+      HIP_TRY(ctx, launch_propagate(ctx->stream, K, N, cluster, reps, W_out, status, kurt));
+      kurt_done = true;
+    } else {
+      // FP32 passes for every row that converged on BF16 data or is still moving
+      HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2, left_list, left_rows));
+      if (fp32_passes > 0) {
+        rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
+                        ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
+                        false, &l2, &ms2);
+        if (rc) return rc;
+      }
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl2, sizeof(FpControl), hipMemcpyDeviceToHost,
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     refine_ti = ((const FpControl *)ctx->small_host)->thread_iters;
   }
-  HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
-                               s4part64, kurt));
+  if (!kurt_done)
+    HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
+                                 s4part64, kurt));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
     stats->thread_iters = main_ctl.thread_iters;

@@ -632,15 +632,18 @@ __global__ void k_update_out(FusedPlan plan, int N, long long T, int K, const fl
 
 template <int NP>
 __global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__restrict__ s4part64,
-                           double *__restrict__ kurt) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= K) return;
+                           double *__restrict__ kurt, const int *__restrict__ act,
+                           const int *__restrict__ kact_dev) {
+  const int posn = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kact = kact_dev ? kact_dev[0] : K;
+  if (posn >= kact) return;
+  const int row = act ? act[posn] : posn;
   const int kwg = plan.kwg;
-  const int n_kb = (K + kwg - 1) / kwg;
+  const int n_kb = (kact + kwg - 1) / kwg;
   const int n_sp = plan_splits(plan, n_kb);
   const int rows_pad = n_kb * kwg;
   double s = 0.0;
-  for (int sp = 0; sp < n_sp; ++sp) s += s4part64[(size_t)sp * rows_pad + row];
+  for (int sp = 0; sp < n_sp; ++sp) s += s4part64[(size_t)sp * rows_pad + posn];
   kurt[row] = s / (double)T - 3.0;
 }
 
@@ -721,16 +724,79 @@ hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t 
 }
 
 hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T, const float *X,
-                           int K, const float *W, double *s4part64, double *kurt) {
+                           int K, const float *W, double *s4part64, double *kurt, const int *act,
+                           const int *kact_dev) {
   const int np = fused_np(N);
   OICA_NP_SWITCH(np, {
     constexpr int WK_ = NP_ <= 64 ? 2 : 1;
     hipLaunchKernelGGL((k_fused_f32<NP_, WK_, true>), dim3(p.grid), dim3(WAVES * 64), 0, st, X, N,
-                       (long long)T, p, W, (const int *)nullptr, (const int *)nullptr, K,
-                       (float *)nullptr, (float *)nullptr, s4part64, (FpControl *)nullptr, 0);
+                       (long long)T, p, W, act, kact_dev, K, (float *)nullptr, (float *)nullptr,
+                       s4part64, (FpControl *)nullptr, 0);
     hipLaunchKernelGGL((k_kurt_out<NP_>), dim3((K + 255) / 256), dim3(256), 0, st, p,
-                       (long long)T, K, s4part64, kurt);
+                       (long long)T, K, s4part64, kurt, act, kact_dev);
   });
+  return hipGetLastError();
+}
+
+// Lists for the grouped FP32 finish: the representative of every group (status
+// reset to NOTCONV until it passes the FP32 test) plus the `left` rows still
+// active after the BF16 loop go to refine_list; every row that is not a
+// non-representative group member goes to kurt_list.
+__global__ void k_group_lists(int K, const int *__restrict__ cluster, const int *__restrict__ reps,
+                              int n_groups, uint8_t *__restrict__ status,
+                              int *__restrict__ refine_list, FpControl *ctl_refine,
+                              const int *__restrict__ left_list, int left,
+                              int *__restrict__ kurt_list, FpControl *ctl_kurt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_groups) {
+    const int r = reps[i];
+    status[r] = OICA_ROW_NOTCONV;
+    refine_list[atomicAdd(&ctl_refine->kact[0], 1)] = r;
+  }
+  if (i < left) refine_list[atomicAdd(&ctl_refine->kact[0], 1)] = left_list[i];
+  if (i < K) {
+    const int c = cluster[i];
+    if (c < 0 || reps[c] == i) kurt_list[atomicAdd(&ctl_kurt->kact[0], 1)] = i;
+  }
+}
+
+// Group members take their representative's refined row (with their own
+// sign), status and kurtosis.  One wave per row.
+__global__ void k_propagate(int K, int N, const int *__restrict__ cluster,
+                            const int *__restrict__ reps, float *__restrict__ W,
+                            uint8_t *__restrict__ status, double *__restrict__ kurt) {
+  const int lane = threadIdx.x % 64;
+  const int l = blockIdx.x * 4 + threadIdx.x / 64;
+  if (l >= K) return;
+  const int c = cluster[l];
+  if (c < 0) return;
+  const int r = reps[c];
+  if (r == l) return;
+  float *wl = W + (size_t)l * N;
+  const float *wr = W + (size_t)r * N;
+  double dot = 0.0;
+  for (int n = lane; n < N; n += 64) dot += (double)wl[n] * (double)wr[n];
+  dot = wave_sum(dot);
+  const float sg = dot < 0.0 ? -1.f : 1.f;
+  for (int n = lane; n < N; n += 64) wl[n] = sg * wr[n];
+  if (lane == 0) {
+    status[l] = status[r];
+    kurt[l] = kurt[r];
+  }
+}
+
+hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
+                              int n_groups, uint8_t *status, int *refine_list, FpControl *ctl_refine,
+                              const int *left_list, int left, int *kurt_list, FpControl *ctl_kurt) {
+  hipLaunchKernelGGL(k_group_lists, dim3((K + 255) / 256), dim3(256), 0, st, K, cluster, reps,
+                     n_groups, status, refine_list, ctl_refine, left_list, left, kurt_list, ctl_kurt);
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(hipStream_t st, int K, int N, const int *cluster, const int *reps,
+                            float *W, uint8_t *status, double *kurt) {
+  hipLaunchKernelGGL(k_propagate, dim3((K + 3) / 4), dim3(256), 0, st, K, N, cluster, reps, W,
+                     status, kurt);
   return hipGetLastError();
 }
 

@@ -71,12 +71,20 @@ hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t 
                              double *s4);
 hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            const float *X, int K, const float *W, double *s4part64,
-                           double *kurt);
+                           double *kurt, const int *act = nullptr, const int *kact_dev = nullptr);
+hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
+                              int n_groups, uint8_t *status, int *refine_list, FpControl *ctl_refine,
+                              const int *left_list, int left, int *kurt_list, FpControl *ctl_kurt);
+hipError_t launch_propagate(hipStream_t st, int K, int N, const int *cluster, const int *reps,
+                            float *W, uint8_t *status, double *kurt);
 hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,
                                 const int *left_list, int left);
 
 // unique.hip
 size_t unique_workspace_bytes(int K);
+hipError_t launch_groups(hipStream_t st, int N, int K, const float *W, const uint8_t *status,
+                         double tau, void *ws, int *ctl_dev, int *ctl_host, int **cluster_out,
+                         int **reps_out);
 hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W,
                          const double *kurt, const uint8_t *status, double tau, int gtest,
                          int n_top, int cap, double *U, double *kurt_u, double *ups_u,

@@ -209,6 +209,70 @@ __global__ void k_finalize(int N, long long T, const float *__restrict__ W,
   }
 }
 
+// Greedy leader clustering of the candidates (cluster[l] == -1 on entry) in
+// (key descending, row index) order; writes cluster ids, the representative of
+// every cluster (reps[0..n)), and n into ctl_dev[1] / ctl_host[1].
+// ctl_dev (4 ints) must be zero on entry except ctl_dev[0].  Synchronises.
+hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const double *key,
+                          int *cluster, int *reps, int *part_idx, double tau, int *ctl_dev,
+                          int *ctl_host) {
+  const int nb = (K + U_BLOCK - 1) / U_BLOCK;
+  // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left
+  hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, key, cluster, reps, -1,
+                     tau, part_idx, ctl_dev);
+  hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, -1,
+                     ctl_dev);  // writes reps[0]
+  const int BATCH = 16;
+  for (int r0 = 0; r0 <= K; r0 += BATCH) {
+    for (int r = r0; r < r0 + BATCH && r <= K; ++r) {
+      hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, key, cluster, reps, r,
+                         tau, part_idx, ctl_dev);
+      hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, r,
+                         ctl_dev);
+    }
+    hipError_t e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (ctl_host[2]) break;
+  }
+  return hipGetLastError();
+}
+
+size_t cluster_workspace_bytes(int K) { return unique_workspace_bytes(K); }
+
+// Candidates for grouping the rows that converged on BF16 data: every CONV row,
+// all with the same key, so the lowest row index of a group represents it.
+__global__ void k_prep_groups(int K, const uint8_t *__restrict__ status, double *__restrict__ key,
+                              int *__restrict__ cluster) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= K) return;
+  const bool cand = status[l] == OICA_ROW_CONV;
+  key[l] = cand ? 0.0 : -INFINITY;
+  cluster[l] = cand ? -1 : -2;
+}
+
+hipError_t launch_groups(hipStream_t st, int N, int K, const float *W, const uint8_t *status,
+                         double tau, void *ws, int *ctl_dev, int *ctl_host, int **cluster_out,
+                         int **reps_out) {
+  const int nb = (K + U_BLOCK - 1) / U_BLOCK;
+  char *p = (char *)ws;
+  auto take = [&](size_t bytes) {
+    char *r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  double *key = (double *)take((size_t)K * 8);
+  int *cluster = (int *)take((size_t)K * 4);
+  int *part_idx = (int *)take((size_t)nb * 4);
+  int *reps = (int *)take((size_t)(K + 1) * 4);
+  hipLaunchKernelGGL(k_prep_groups, dim3(nb), dim3(U_BLOCK), 0, st, K, status, key, cluster);
+  hipError_t e = launch_cluster(st, N, K, W, key, cluster, reps, part_idx, tau, ctl_dev, ctl_host);
+  *cluster_out = cluster;
+  *reps_out = reps;
+  return e;
+}
+
 hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W,
                          const double *kurt, const uint8_t *status, double tau, int gtest,
                          int n_top, int cap, double *U, double *kurt_u, double *ups_u,
@@ -232,30 +296,14 @@ hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W
   hipLaunchKernelGGL(k_any_conv, dim3(nb), dim3(U_BLOCK), 0, st, K, status, w.ctl);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(U_BLOCK), 0, st, K, kurt, status, w.ctl, w.key,
                      w.cluster, w.sizes);
-  // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left
-  hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, w.key, w.cluster, w.reps,
-                     -1, tau, w.part_idx, w.ctl);
-  hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, w.key, w.part_idx, w.reps,
-                     -1, w.ctl);  // writes reps[0]
-  const int BATCH = 16;
-  for (int r0 = 0; r0 <= K; r0 += BATCH) {
-    for (int r = r0; r < r0 + BATCH && r <= K; ++r) {
-      hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, w.key, w.cluster,
-                         w.reps, r, tau, w.part_idx, w.ctl);
-      hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, w.key, w.part_idx, w.reps, r,
-                         w.ctl);
-    }
-    hipError_t e = hipMemcpyAsync(counts_host, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    if (counts_host[2]) break;
-  }
+  hipError_t e = launch_cluster(st, N, K, W, w.key, w.cluster, w.reps, w.part_idx, tau, w.ctl,
+                                counts_host);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sizes, dim3(nb), dim3(U_BLOCK), 0, st, K, w.cluster, w.sizes);
   hipLaunchKernelGGL(k_finalize, dim3(64), dim3(128), 0, st, N, (long long)T, W, kurt, w.key,
                      w.reps, w.sizes, gtest, n_top, cap, U, kurt_u, ups_u, rep_thread,
                      cluster_size, w.ctl);
-  hipError_t e = hipMemcpyAsync(counts_host, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+  e = hipMemcpyAsync(counts_host, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;

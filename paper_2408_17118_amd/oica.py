@@ -35,7 +35,7 @@ class OicaError(RuntimeError):
 class FpParams(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("tol_bf16", C.c_double), ("refine_iters", C.c_int), ("traj_iters", C.c_int),
-                ("check_every", C.c_int), ("profile", C.c_int)]
+                ("check_every", C.c_int), ("profile", C.c_int), ("refine_groups", C.c_int)]
 
 
 class FpStats(C.Structure):
@@ -160,7 +160,8 @@ class Context:
 
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
-                    tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False):
+                    tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
+                    refine_groups=True):
         _dev(Xw, "Xw")
         _dev(W0, "W0")
         if W0.dtype != torch.float32:
@@ -177,7 +178,8 @@ class Context:
         status = torch.empty(K, dtype=torch.uint8, device=dev)
         traj = torch.empty((K, traj_iters, 2), dtype=torch.float32, device=dev) if traj_iters else None
         p = FpParams(max_iter, tol, OICA_BF16 if precision == "bf16" else OICA_F32, tol_bf16,
-                     refine_iters, traj_iters, check_every, 1 if profile else 0)
+                     refine_iters, traj_iters, check_every, 1 if profile else 0,
+                     1 if refine_groups else 0)
         st = FpStats()
         rc = self.lib.oica_fixed_point(self.h, N, T, _ptr(Xw), _DT[Xw.dtype], _ptr(Xw_f32), K,
                                        _ptr(W0), C.byref(p), _ptr(W), _ptr(kurt), _ptr(iters),
@@ -233,12 +235,13 @@ class Context:
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
                  tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
-                 profile=False):
+                 profile=False, refine_groups=True):
     """Whole hot path on device-resident raw data: whiten -> fixed point -> unique."""
     xw_dtype = torch.bfloat16 if precision == "bf16" else torch.float32
     Xw, Xw32, V, mean, eig = ctx.whiten(X, out_dtype=xw_dtype)
     fp = ctx.fixed_point(Xw, W0, Xw_f32=Xw32, max_iter=max_iter, tol=tol, precision=precision,
-                         tol_bf16=tol_bf16, refine_iters=refine_iters, profile=profile)
+                         tol_bf16=tol_bf16, refine_iters=refine_iters, profile=profile,
+                         refine_groups=refine_groups)
     res = ctx.unique(fp["W"], fp["kurt"], fp["status"], X.shape[1], tau=tau,
                      gaussianity_test=gaussianity_test)
     res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)

@@ -124,3 +124,23 @@ def test_bf16_eeg_shaped_matches_oracle():
     _check_against(res, np.array(ref["U_raw"]), np.array(ref["alpha"]), np.array(ref["upsilon"]),
                    ref["n_accepted"], "bf16 eeg")
     c.close()
+
+
+def test_grouped_and_full_fp32_finish_agree(ctx):
+    """Finishing one row per group of identical BF16 fixed points gives the same
+    unique set as finishing every converged row, with far fewer FP32 updates."""
+    from paper_2408_17118_amd import oica
+    p = synth.make_problem(synth.eeg_kinds(32), T=40_000, K=2048, seed=21)
+    X, W0 = dev(p.X), dev(p.W0.astype(np.float32))
+    rg = oica.ordering_ica(ctx, X, W0, precision="bf16", refine_groups=True)
+    ra = oica.ordering_ica(ctx, X, W0, precision="bf16", refine_groups=False)
+    assert rg["n_unique"] == ra["n_unique"] and rg["n_accepted"] == ra["n_accepted"]
+    n = rg["n_accepted"]
+    cos = np.abs(rg["U"].cpu().numpy()[:n] @ ra["U"].cpu().numpy()[:n].T)
+    assert np.all(cos.max(axis=1) >= 1 - 1e-6)
+    assert np.allclose(rg["alpha"].cpu().numpy()[:n], ra["alpha"].cpu().numpy()[:n], rtol=1e-5)
+    assert rg["fp"]["refine_thread_iters"] < ra["fp"]["refine_thread_iters"] / 4
+    # members carry their representative's row up to sign
+    W = rg["fp"]["W"].cpu().numpy()
+    st = rg["fp"]["status"].cpu().numpy()
+    assert np.allclose(np.linalg.norm(W[st == ica.CONV], axis=1), 1.0, atol=1e-6)
