@@ -189,6 +189,59 @@ int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
                   const float *W, double *kurt);
 
 /* ---------------------------------------------------------------------------
+ * Batched form: D independent problems of uneven N, T and K run the passes of
+ * oica_fixed_point together, one persistent kernel launch per pass for the
+ * whole batch (a work queue of (problem, row block, sample split) items).
+ * Each problem's sample partition depends on its own T only and the tuned tile
+ * shape only regroups independent rows, so every problem's results are the
+ * same alone (D = 1) or in any batch and under any tuner choice.
+ * ------------------------------------------------------------------------- */
+typedef struct {          /* host array of D entries; all pointers DEVICE   */
+  int N;                  /* [1, OICA_MAX_N]                                */
+  int64_t T;              /* > N                                            */
+  int K;                  /* >= 1                                           */
+  const void *Xw;         /* N x T of xw_t                                  */
+  const float *Xw_f32;    /* N x T FP32 (may equal Xw for FP32 data)        */
+  const float *W0;        /* K x N                                          */
+  float *W_out;           /* K x N unit rows, original row order            */
+  double *kurt;           /* K                                              */
+  int32_t *iters;         /* K                                              */
+  uint8_t *status;        /* K                                              */
+} oica_problem;
+
+typedef struct {
+  int autotune;           /* 1: time the candidate tile shapes (rows per wave
+                             per padded-N bucket, persistent grid size) on
+                             the first pass unless the choice is cached     */
+  const char *cache_path; /* host string: JSON-lines file of tuned choices,
+                             read and appended (NULL: context memory only)  */
+  int force_wk;           /* 0: tuned or default; 1 or 2: rows per wave of
+                             32-row blocks for padded N <= 64              */
+  int force_grid;         /* 0: tuned or default; else work-groups          */
+} oica_batch_params;
+
+typedef struct {          /* host */
+  int64_t thread_iters;   /* all problems, main loop                        */
+  int64_t refine_thread_iters; /* all problems, FP32 passes after BF16      */
+  int passes;             /* batched passes with at least one active row    */
+  double ms;              /* wall time of the call                          */
+  double update_ms;       /* params->profile = 1: persistent-kernel time    */
+  int update_launches;
+  int grid;               /* work-groups of the persistent kernel           */
+  int wk32, wk64;         /* rows-per-wave choice for padded N 32 and 64    */
+  int tuned;              /* 1: chosen by timing in this call; 2: from cache */
+} oica_batch_stats;
+
+/* D in [1, 1024].  params as for oica_fixed_point (traj_iters must be 0;
+ * refine_groups is ignored: in BF16 mode every row that converged on BF16 data
+ * or is still moving takes the FP32 passes).  bparams and stats may be NULL.
+ * Synchronises.  Errors: OICA_E_ARG (naming the problem index),
+ * OICA_E_UNSUPPORTED, OICA_E_NOMEM, OICA_E_DEVICE. */
+int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *problems, oica_dtype xw_t,
+                             const oica_fp_params *params, const oica_batch_params *bparams,
+                             oica_batch_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * Unique components (generalises Algorithm 2's argmax over the random starts
  * and its Gaussianity test, eq. 3, to the whole ordered set):
  *   candidates = rows with status CONV (if none: every non-degenerate row),

@@ -6,7 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,7 @@ struct oica_ctx {
   int *small_dev = nullptr;    // 64 ints of device bookkeeping
   int *small_host = nullptr;   // 64 ints of pinned host memory
   std::vector<hipEvent_t> events;  // start/stop pairs for kernel timing
+  std::map<std::string, std::vector<int>> tune;  // batched tile choices: {wk32, wk64, grid}
   std::string err;
 };
 
@@ -421,6 +424,337 @@ int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K, c
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan, N, T, Xw_f32, K, W, (double *)ctx->ws, kurt));
+  return OICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+int variant_of(int np, int wk, bool bf16) { return (bf16 ? 8 : 0) + (np / 32 - 1) * 2 + (wk - 1); }
+
+std::string tune_key(int D, const oica_problem *pr, bool bf16) {
+  // data type, and per padded-N bucket the problem count and log2 of sum K T
+  double kt[5] = {0, 0, 0, 0, 0};
+  int cnt[5] = {0, 0, 0, 0, 0};
+  for (int d = 0; d < D; ++d) {
+    const int b = fused_np(pr[d].N) / 32;
+    kt[b] += (double)pr[d].K * (double)pr[d].T;
+    cnt[b] += 1;
+  }
+  char buf[256];
+  int o = snprintf(buf, sizeof buf, "gfx950|%s", bf16 ? "bf16" : "f32");
+  for (int b = 1; b <= 4; ++b)
+    if (cnt[b])
+      o += snprintf(buf + o, sizeof buf - o, "|np%d:%d:%d", 32 * b, cnt[b],
+                    (int)lround(log2(kt[b])));
+  return std::string(buf);
+}
+
+void tune_cache_load(oica_ctx *ctx, const char *path) {
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char line[512], key[300];
+  int a, b, g;
+  while (fgets(line, sizeof line, f))
+    if (sscanf(line, "{\"key\": \"%299[^\"]\", \"wk32\": %d, \"wk64\": %d, \"grid\": %d}", key, &a,
+               &b, &g) == 4)
+      ctx->tune[key] = {a, b, g};
+  fclose(f);
+}
+
+void tune_cache_store(const char *path, const std::string &key, const std::vector<int> &v) {
+  if (!path) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"wk32\": %d, \"wk64\": %d, \"grid\": %d}\n", key.c_str(), v[0], v[1],
+          v[2]);
+  fclose(f);
+}
+
+void set_shapes(std::vector<BatchDesc> &hd, int wk32, int wk64, bool bf16) {
+  for (auto &b : hd) {
+    b.wk = b.np == 32 ? wk32 : (b.np == 64 ? wk64 : 1);
+    b.kwg = WAVES_PER_WG * b.wk * 32;
+    b.variant = variant_of(b.np, b.wk, bf16);
+  }
+}
+
+}  // namespace
+
+int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_dtype xw_t,
+                             const oica_fp_params *params, const oica_batch_params *bparams,
+                             oica_batch_stats *stats) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  if (D < 1 || D > batch_max_datasets())
+    return fail(ctx, OICA_E_ARG, "D must be in [1, %d] (got %d)", batch_max_datasets(), D);
+  if (!pr) return fail(ctx, OICA_E_ARG, "problems must be non-null");
+  int rc = check_fp_params(ctx, params);
+  if (rc) return rc;
+  if (params->traj_iters != 0) return fail(ctx, OICA_E_ARG, "traj_iters must be 0 in the batched form");
+  const bool bf16 = params->precision == OICA_BF16;
+  if (bf16 != (xw_t == OICA_BF16)) return fail(ctx, OICA_E_ARG, "xw_t must match params->precision");
+  for (int d = 0; d < D; ++d) {
+    const oica_problem &q = pr[d];
+    rc = check_dims(ctx, q.N, q.T);
+    if (rc) return fail(ctx, rc, "problem %d: %s", d, ctx->err.c_str());
+    if (q.K < 1 || q.K > (1 << 24)) return fail(ctx, OICA_E_ARG, "problem %d: K=%d out of range", d, q.K);
+    if (!q.Xw || !q.Xw_f32 || !q.W0 || !q.W_out || !q.kurt || !q.iters || !q.status)
+      return fail(ctx, OICA_E_ARG, "problem %d: null pointer", d);
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool profile = params->profile != 0;
+  const int check_every = params->check_every > 0 ? params->check_every : 4;
+
+  // ---- layout --------------------------------------------------------------
+  std::vector<BatchDesc> hd(D);
+  size_t need = 0;
+  auto add = [&](size_t bytes) { need += (bytes + 255) & ~(size_t)255; };
+  long long ktot = 0;
+  size_t kurt_rows = 0;
+  for (int d = 0; d < D; ++d) {
+    const oica_problem &q = pr[d];
+    BatchDesc &b = hd[d];
+    b.N = q.N; b.T = q.T; b.K = q.K;
+    b.np = fused_np(q.N);
+    b.n_sp = batch_splits(q.T);
+    b.n_sub = (int)((q.T + 31) / 32);
+    const size_t rows_cap = (size_t)q.K + 256;
+    add((size_t)b.n_sp * rows_cap * b.np * 4);                              // gpart
+    add((size_t)b.n_sp * rows_cap * 4);                                     // s4part
+    add((size_t)((b.n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) * q.K * (b.np + 1) * 8);  // red
+    add((size_t)q.K * 4 * 3);                                               // act lists
+    ktot += q.K;
+    const FusedPlan kp = make_plan(q.N, q.T, q.K, false);
+    kurt_rows = std::max(kurt_rows, fp_workspace_floats(kp, q.N, q.K) / (size_t)fused_np(q.N));
+  }
+  add((size_t)D * sizeof(BatchDesc));
+  add(sizeof(BatchCtl));
+  add((size_t)(D + 1) * 4 * 2 + (size_t)(D + 1) * 8);
+  add((size_t)D * 256 * 2);  // two control blocks per problem
+  add(kurt_rows * 8);
+  rc = ensure_ws(ctx, need + 4096);
+  if (rc) return rc;
+  Carve cv{(char *)ctx->ws};
+  BatchDesc *ddesc = cv.take<BatchDesc>(D);
+  BatchCtl *bctl = cv.take<BatchCtl>(1);
+  int *item_start = cv.take<int>(D + 1);
+  int *epi_start = cv.take<int>(D + 1);
+  long long *red_start = cv.take<long long>(D + 1);
+  char *ctl_base = cv.take<char>((size_t)D * 256 * 2);
+  double *s4part64 = cv.take<double>(kurt_rows);
+  std::vector<int *> act2(D);
+  for (int d = 0; d < D; ++d) {
+    const oica_problem &q = pr[d];
+    BatchDesc &b = hd[d];
+    const size_t rows_cap = (size_t)q.K + 256;
+    b.gpart = cv.take<float>((size_t)b.n_sp * rows_cap * b.np);
+    b.s4part = cv.take<float>((size_t)b.n_sp * rows_cap);
+    b.red = cv.take<double>((size_t)((b.n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) * q.K * (b.np + 1));
+    b.act0 = cv.take<int>(q.K);
+    b.act1 = cv.take<int>(q.K);
+    act2[d] = cv.take<int>(q.K);
+    b.ctl = (FpControl *)(ctl_base + (size_t)d * 256);
+    b.X = q.Xw;
+    b.X32 = q.Xw_f32;
+    b.B = q.W_out;
+    b.iters = q.iters;
+    b.status = q.status;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(ctl_base, 0, (size_t)D * 256 * 2, ctx->stream));
+  for (int d = 0; d < D; ++d)
+    HIP_TRY(ctx, launch_init_rows(ctx->stream, pr[d].K, pr[d].N, pr[d].W0, pr[d].W_out, pr[d].iters,
+                                  pr[d].status, hd[d].act0, hd[d].ctl, nullptr, 0));
+
+  // ---- tile shapes: forced, cached, tuned or default -------------------------
+  int wk32 = 2, wk64 = 2, grid = 1024, tuned = 0;
+  const oica_batch_params bp0 = {0, nullptr, 0, 0};
+  const oica_batch_params &bp = bparams ? *bparams : bp0;
+  const std::string key = tune_key(D, pr, bf16);
+  if (bp.force_wk == 1 || bp.force_wk == 2) {
+    wk32 = wk64 = bp.force_wk;
+  } else if (bp.autotune) {
+    tune_cache_load(ctx, bp.cache_path);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) {
+      wk32 = it->second[0];
+      wk64 = it->second[1];
+      grid = it->second[2];
+      tuned = 2;
+    } else {
+      // time pass 0 (all rows active; it only writes partial buffers) for each
+      // candidate shape, best of two runs
+      bool has32 = false, has64 = false;
+      for (auto &b : hd) {
+        has32 |= b.np == 32;
+        has64 |= b.np == 64;
+      }
+      std::vector<std::vector<int>> cands;
+      for (int a : {1, 2})
+        for (int c : {1, 2})
+          for (int g : {512, 1024, 2048}) {
+            if ((!has32 && a == 2) || (!has64 && c == 2)) continue;
+            cands.push_back({a, c, g});
+          }
+      while ((int)ctx->events.size() < 2) {
+        hipEvent_t e;
+        HIP_TRY(ctx, hipEventCreate(&e));
+        ctx->events.push_back(e);
+      }
+      float best = 1e30f;
+      std::vector<int> pick = {2, 2, 1024};
+      for (const auto &c : cands) {
+        set_shapes(hd, c[0], c[1], bf16);
+        HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
+                                    hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // hd is reused next
+        float tbest = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(ctx, launch_batch_plan(ctx->stream, ddesc, D, bctl, item_start, red_start, epi_start,
+                                         0, true));
+          HIP_TRY(ctx, hipEventRecord(ctx->events[0], ctx->stream));
+          HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, 0, c[2]));
+          HIP_TRY(ctx, hipEventRecord(ctx->events[1], ctx->stream));
+          HIP_TRY(ctx, hipEventSynchronize(ctx->events[1]));
+          float ms = 0.f;
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]));
+          tbest = std::min(tbest, ms);
+        }
+        if (tbest < best) {
+          best = tbest;
+          pick = c;
+        }
+      }
+      wk32 = pick[0];
+      wk64 = pick[1];
+      grid = pick[2];
+      tuned = 1;
+      ctx->tune[key] = pick;
+      tune_cache_store(bp.cache_path, key, pick);
+    }
+  }
+  if (bp.force_grid > 0) grid = ((bp.force_grid + 7) / 8) * 8;
+  set_shapes(hd, wk32, wk64, bf16);
+  HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc), hipMemcpyHostToDevice,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+
+  // ---- passes -----------------------------------------------------------------
+  std::vector<char> ctl_host((size_t)D * 256 * 2);
+  auto run = [&](int max_passes, double tol, int exit_below, int stall_polls, int *launched,
+                 double *kernel_ms) -> int {
+    long long kmax = ktot;
+    int stalled = 0;
+    *launched = 0;
+    *kernel_ms = 0.0;
+    for (int pass = 0; pass < max_passes; ++pass) {
+      HIP_TRY(ctx, launch_batch_plan(ctx->stream, ddesc, D, bctl, item_start, red_start, epi_start,
+                                     pass, false));
+      if (profile) {
+        while ((int)ctx->events.size() < 2 * (pass + 1)) {
+          hipEvent_t e;
+          HIP_TRY(ctx, hipEventCreate(&e));
+          ctx->events.push_back(e);
+        }
+        HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass], ctx->stream));
+      }
+      HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, pass, grid));
+      if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
+      HIP_TRY(ctx, launch_epilogue_batched(ctx->stream, ddesc, D, bctl, red_start, epi_start, pass,
+                                           tol, (int)kmax));
+      *launched = pass + 1;
+      if ((pass + 1) % check_every == 0 || pass + 1 == max_passes) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data(), hd[0].ctl, (size_t)D * 256, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        long long left = 0;
+        for (int d = 0; d < D; ++d)
+          left += ((const FpControl *)(ctl_host.data() + (size_t)d * 256))->kact[(pass + 1) & 1];
+        if (left == 0) break;
+        stalled = (left >= kmax) ? stalled + 1 : 0;
+        kmax = left;
+        if (exit_below > 0 && left <= exit_below) break;
+        if (stall_polls > 0 && stalled >= stall_polls) break;
+      }
+    }
+    if (profile)
+      for (int i = 0; i < *launched; ++i) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+        *kernel_ms += ms;
+      }
+    return OICA_OK;
+  };
+  int launched = 0;
+  double kernel_ms = 0.0;
+  rc = run(params->max_iter, bf16 ? params->tol_bf16 : params->tol,
+           bf16 ? (int)std::max<long long>(ktot / 64, 1) : 0, bf16 ? 2 : 0, &launched, &kernel_ms);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data(), hd[0].ctl, (size_t)D * 256, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  long long main_ti = 0, refine_ti = 0;
+  int main_passes = 0;
+  for (int d = 0; d < D; ++d) {
+    const FpControl *c = (const FpControl *)(ctl_host.data() + (size_t)d * 256);
+    main_ti += c->thread_iters;
+    main_passes = std::max(main_passes, c->passes);
+  }
+  if (bf16) {
+    // FP32 passes for every row that converged on BF16 data or is still moving
+    for (int d = 0; d < D; ++d) {
+      const FpControl *c = (const FpControl *)(ctl_host.data() + (size_t)d * 256);
+      BatchDesc &b = hd[d];
+      FpControl *c2 = (FpControl *)(ctl_base + (size_t)(D + d) * 256);
+      HIP_TRY(ctx, launch_refine_select(ctx->stream, b.K, b.status, act2[d], c2,
+                                        (launched & 1) ? b.act1 : b.act0, c->kact[launched & 1]));
+      int *old0 = b.act0;
+      b.act0 = act2[d];
+      b.act1 = old0;
+      b.ctl = c2;
+      b.X = b.X32;
+    }
+    set_shapes(hd, wk32, wk64, false);
+    HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int budget = params->max_iter - launched;
+    const int passes32 = std::max(budget, params->refine_iters);
+    int l2 = 0;
+    double ms2 = 0.0;
+    if (passes32 > 0) {
+      rc = run(passes32, params->tol, 0, 0, &l2, &ms2);
+      if (rc) return rc;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data() + (size_t)D * 256, ctl_base + (size_t)D * 256,
+                                (size_t)D * 256, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int d = 0; d < D; ++d)
+      refine_ti += ((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->thread_iters;
+  }
+  // final kurtosis of every row, FP32 data, FP64 sums
+  for (int d = 0; d < D; ++d) {
+    const oica_problem &q = pr[d];
+    HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T, q.Xw_f32,
+                                 q.K, q.W_out, s4part64, q.kurt));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    stats->thread_iters = main_ti;
+    stats->refine_thread_iters = refine_ti;
+    stats->passes = main_passes;
+    stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->update_ms = profile ? kernel_ms : 0.0;
+    stats->update_launches = profile ? launched : 0;
+    stats->grid = grid;
+    stats->wk32 = wk32;
+    stats->wk64 = wk64;
+    stats->tuned = tuned;
+  }
   return OICA_OK;
 }
 

@@ -1,0 +1,268 @@
+// Many independent datasets in one persistent launch per pass.
+//
+// Every dataset keeps its own rows, active lists, control block and partial
+// buffers (BatchDesc).  A pass is four launches for the whole batch:
+//   k_batch_plan      one work-group: reads every dataset's active count,
+//                     does the per-dataset bookkeeping and builds prefix sums
+//                     of the work items of the three batched kernels;
+//   k_fused_batched   persistent work-groups pull (dataset, row block, sample
+//                     split) items from an atomic queue and run the same
+//                     per-item device code as the single-dataset kernels,
+//                     dispatching on the dataset's padded N, rows per wave and
+//                     data type;
+//   k_split_reduce_batched, k_epilogue_batched   the split reduction and the
+//                     per-row update of every dataset, grid-stride over the
+//                     concatenated items.
+// A dataset's sample partition depends on its own T only (splits of about
+// BATCH_SPLIT samples), and rows per wave only regroup independent rows, so a
+// dataset's arithmetic is the same alone or in any batch and under any tile
+// choice the tuner makes.
+#include "fused_items.h"
+
+#include <math.h>
+
+namespace oica {
+
+constexpr int BATCH_SPLIT = 4096;   // samples per split in the batched form
+constexpr int MAX_D = 1024;         // datasets per call
+constexpr int BUF_BYTES = 36 * 1024;
+
+int batch_splits(int64_t T) {
+  int64_t s = (T + BATCH_SPLIT / 2) / BATCH_SPLIT;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+__global__ __launch_bounds__(1024) void k_batch_plan(const BatchDesc *__restrict__ descs, int D,
+                                                     BatchCtl *bctl, int *__restrict__ item_start,
+                                                     long long *__restrict__ red_start,
+                                                     int *__restrict__ epi_start, int pass,
+                                                     int dry) {
+  __shared__ int s_items[MAX_D], s_epi[MAX_D];
+  __shared__ long long s_red[MAX_D];
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    const BatchDesc &b = descs[d];
+    FpControl *c = b.ctl;
+    const int kact = c->kact[pass & 1];
+    if (!dry) {
+      c->kact[(pass + 1) & 1] = 0;
+      if (kact > 0) {
+        c->passes = pass + 1;
+        c->thread_iters += kact;
+      }
+    }
+    int items = 0, epi = 0;
+    long long red = 0;
+    if (kact > 0) {
+      const int n_kb = (kact + b.kwg - 1) / b.kwg;
+      items = n_kb * b.n_sp;
+      const int groups = (b.n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
+      red = (long long)groups * kact * (b.np + 1);
+      epi = kact;
+    }
+    s_items[d] = items;
+    s_red[d] = red;
+    s_epi[d] = epi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int it = 0, ep = 0;
+    long long rd = 0;
+    for (int d = 0; d < D; ++d) {
+      item_start[d] = it;
+      red_start[d] = rd;
+      epi_start[d] = ep;
+      it += s_items[d];
+      rd += s_red[d];
+      ep += s_epi[d];
+    }
+    item_start[D] = it;
+    red_start[D] = rd;
+    epi_start[D] = ep;
+    bctl->total_items = it;
+    bctl->total_red = rd;
+    bctl->total_epi = ep;
+    bctl->counter[pass & 1] = 0;
+  }
+}
+
+// largest d with start[d] <= x (start non-decreasing, start[0] = 0 <= x)
+template <typename I>
+__device__ inline int find_dataset(const I *start, int D, I x) {
+  int lo = 0, hi = D;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc *__restrict__ descs,
+                                                                 int D, BatchCtl *bctl,
+                                                                 const int *__restrict__ item_start,
+                                                                 int pass) {
+  __shared__ __attribute__((aligned(16))) char buf[BUF_BYTES];
+  __shared__ int s_start[MAX_D + 1];
+  __shared__ int s_item;
+  for (int d = threadIdx.x; d <= D; d += blockDim.x) s_start[d] = item_start[d];
+  const int total = bctl->total_items;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(&bctl->counter[pass & 1], 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= total) break;
+    const int d = find_dataset(s_start, D, item);
+    const BatchDesc &b = descs[d];
+    const int kact = b.ctl->kact[pass & 1];
+    const int n_kb = (kact + b.kwg - 1) / b.kwg;
+    const int local = item - s_start[d];
+    const int kb = local % n_kb, sp = local / n_kb;
+    const ItemCtx c{b.X, b.N, b.T, b.n_sub, b.n_sp, n_kb * b.kwg, b.B,
+                    (pass & 1) ? b.act1 : b.act0, kact, b.gpart, b.s4part, nullptr};
+    float *xs32 = reinterpret_cast<float *>(buf);
+    __bf16 *xs16 = reinterpret_cast<__bf16 *>(buf);
+    __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 18432);
+    switch (b.variant) {
+      case 0: item_f32<32, 1, false>(c, kb, sp, xs32); break;
+      case 1: item_f32<32, 2, false>(c, kb, sp, xs32); break;
+      case 2: item_f32<64, 1, false>(c, kb, sp, xs32); break;
+      case 3: item_f32<64, 2, false>(c, kb, sp, xs32); break;
+      case 4: item_f32<96, 1, false>(c, kb, sp, xs32); break;
+      case 6: item_f32<128, 1, false>(c, kb, sp, xs32); break;
+      case 8: item_bf16<32, 1>(c, kb, sp, xs16, xt16); break;
+      case 9: item_bf16<32, 2>(c, kb, sp, xs16, xt16); break;
+      case 10: item_bf16<64, 1>(c, kb, sp, xs16, xt16); break;
+      case 11: item_bf16<64, 2>(c, kb, sp, xs16, xt16); break;
+      case 12: item_bf16<96, 1>(c, kb, sp, xs16, xt16); break;
+      case 14: item_bf16<128, 1>(c, kb, sp, xs16, xt16); break;
+      default: break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_split_reduce_batched(const BatchDesc *__restrict__ descs,
+                                                              int D, const BatchCtl *bctl,
+                                                              const long long *__restrict__ red_start,
+                                                              int pass) {
+  __shared__ long long s_start[MAX_D + 1];
+  for (int d = threadIdx.x; d <= D; d += blockDim.x) s_start[d] = red_start[d];
+  __syncthreads();
+  const long long total = bctl->total_red;
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * 256) {
+    const int d = find_dataset(s_start, D, idx);
+    const BatchDesc &b = descs[d];
+    const int kact = b.ctl->kact[pass & 1];
+    const int n_kb = (kact + b.kwg - 1) / b.kwg;
+    const int rows_pad = n_kb * b.kwg;
+    const int RS = b.np + 1;
+    const long long local = idx - s_start[d];
+    const long long per_group = (long long)kact * RS;
+    const int g = (int)(local / per_group);
+    const int rem = (int)(local - (long long)g * per_group);
+    const int posn = rem / RS;
+    const int n = rem - posn * RS;
+    const int sp0 = g * SPLIT_GROUP;
+    float v[SPLIT_GROUP];
+#pragma unroll
+    for (int u = 0; u < SPLIT_GROUP; ++u) {
+      const int sp = sp0 + u;
+      v[u] = 0.f;
+      if (sp < b.n_sp)
+        v[u] = n < b.np ? b.gpart[((size_t)sp * rows_pad + posn) * b.np + n]
+                        : b.s4part[(size_t)sp * rows_pad + posn];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPLIT_GROUP; ++u) acc += (double)v[u];
+    b.red[local] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_epilogue_batched(const BatchDesc *__restrict__ descs, int D,
+                                                          const int *__restrict__ epi_start,
+                                                          int pass, double tol) {
+  __shared__ int s_start[MAX_D + 1];
+  for (int d = threadIdx.x; d <= D; d += blockDim.x) s_start[d] = epi_start[d];
+  __syncthreads();
+  const int lane = threadIdx.x % 64;
+  const int wid = blockIdx.x * 4 + threadIdx.x / 64;
+  if (wid >= s_start[D]) return;
+  const int d = find_dataset(s_start, D, wid);
+  const BatchDesc &b = descs[d];
+  FpControl *ctl = b.ctl;
+  const int kact = ctl->kact[pass & 1];
+  const int posn = wid - s_start[d];
+  const int N = b.N, NP = b.np, RS = b.np + 1;
+  const int groups = (b.n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
+  const int *act_cur = (pass & 1) ? b.act1 : b.act0;
+  int *act_next = (pass & 1) ? b.act0 : b.act1;
+  const int row = act_cur[posn];
+  const int n0 = lane, n1 = lane + 64;
+  double g0 = 0.0, g1 = 0.0, s4 = 0.0;
+  for (int q = 0; q < groups; ++q) {
+    const double *src = b.red + ((size_t)q * kact + posn) * RS;
+    if (n0 < NP) g0 += src[n0];
+    if (n1 < NP) g1 += src[n1];
+    if (lane == 0) s4 += src[NP];
+  }
+  float *brow = b.B + (size_t)row * N;
+  const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
+  const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
+  const double invT = 1.0 / (double)b.T;
+  g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
+  g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+  const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
+  if (!(gn > 0.0) || !isfinite(gn)) {
+    if (lane == 0) b.status[row] = OICA_ROW_DEGENERATE;
+    return;
+  }
+  const double b0 = g0 / gn, b1 = g1 / gn;
+  const double dm = wave_sum((b0 - bp0) * (b0 - bp0) + (b1 - bp1) * (b1 - bp1));
+  const double dp = wave_sum((b0 + bp0) * (b0 + bp0) + (b1 + bp1) * (b1 + bp1));
+  const double dd = sqrt(dm < dp ? dm : dp);
+  if (n0 < N) brow[n0] = (float)b0;
+  if (n1 < N) brow[n1] = (float)b1;
+  if (lane == 0) {
+    b.iters[row] += 1;
+    if (dd < tol) {
+      b.status[row] = OICA_ROW_CONV;
+    } else {
+      const int slot = atomicAdd(&ctl->kact[(pass + 1) & 1], 1);
+      act_next[slot] = row;
+    }
+  }
+}
+
+hipError_t launch_batch_plan(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
+                             int *item_start, long long *red_start, int *epi_start, int pass,
+                             bool dry) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, st, descs, D, bctl, item_start,
+                     red_start, epi_start, pass, dry ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_batched(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
+                                const int *item_start, int pass, int grid) {
+  hipLaunchKernelGGL(k_fused_batched, dim3(grid), dim3(WAVES * 64), 0, st, descs, D, bctl,
+                     item_start, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue_batched(hipStream_t st, const BatchDesc *descs, int D,
+                                   const BatchCtl *bctl, const long long *red_start,
+                                   const int *epi_start, int pass, double tol, int kmax_total) {
+  hipLaunchKernelGGL(k_split_reduce_batched, dim3(RED_GRID), dim3(256), 0, st, descs, D, bctl,
+                     red_start, pass);
+  hipLaunchKernelGGL(k_epilogue_batched, dim3((kmax_total + 3) / 4), dim3(256), 0, st, descs, D,
+                     epi_start, pass, tol);
+  return hipGetLastError();
+}
+
+int batch_max_datasets() { return MAX_D; }
+
+}  // namespace oica

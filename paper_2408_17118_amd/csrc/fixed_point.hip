@@ -10,27 +10,12 @@
 // partial G that the epilogue kernel sums in a fixed order, so results are
 // deterministic.  The epilogue normalises, measures the step, updates the
 // per-row state and appends still-moving rows to the next active list.
-//
-// MFMA v_mfma_f32_32x32x2f32 operand layout (wave64, lane l, h = l / 32,
-// i = l % 32):  A[i][h], B[h][i]  (one float each);  D[r][i] in vgpr v with
-// r = 8 (v / 4) + 4 h + (v % 4).  GEMM1 produces Z^T with the rows of B on the
-// lane index, so the same registers are directly the B operand of GEMM2 with
-// the samples permuted by r(v, h); GEMM2's A operand reads X with the same
-// permutation.
-#include "oica_internal.h"
+// The per-item device code is in fused_items.h.
+#include "fused_items.h"
 
 #include <math.h>
 
 namespace oica {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int WAVES = 4;        // waves per work-group
-constexpr int TT = 64;          // samples per LDS tile (two 32-sample sub-tiles)
-constexpr int SX = TT + 1;      // LDS row stride in floats; odd, so column reads hit 32 banks
-constexpr int MIN_SUB = 8;      // each sample split covers >= 8 sub-tiles (256 samples)
-constexpr int GRID = 1024;      // work-groups per fused launch (multiple of 8)
 
 int fused_np(int N) { return ((N + 31) / 32) * 32; }
 
@@ -70,11 +55,6 @@ size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax) {
   return worst * (size_t)np;
 }
 
-// ---------------------------------------------------------------------------
-// Fused pass kernel.
-//   KURT = false: writes partial G (NP floats per row) and partial sum z^4.
-//   KURT = true : skips GEMM2 and writes partial sum z^4 in FP64.
-// ---------------------------------------------------------------------------
 template <int NP, int WK, bool KURT>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
     const float *__restrict__ X, int N, long long T, FusedPlan plan,
@@ -82,7 +62,6 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
     int kact_host, float *__restrict__ gpart, float *__restrict__ s4part,
     double *__restrict__ s4part64, FpControl *ctl, int pass) {
   constexpr int KWG = WAVES * WK * 32;
-  constexpr int HALF = NP / 2;
   __shared__ float xs[NP * SX];
 
   const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
@@ -103,160 +82,13 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
   const int per_xcd_wgs = plan.grid / 8;
   const int xcd = blockIdx.x % 8;
   const int local = blockIdx.x / 8;
-
-  const int tid = threadIdx.x;
-  const int wave = tid / 64;
-  const int lane = tid % 64;
-  const int h = lane / 32;
-  const int li = lane % 32;
-
+  const ItemCtx c{X, N, T, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part, s4part64};
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
-    const int kb = w_item % n_kb;
-    const int sp = w_item / n_kb;
-    const long long sub0 = (long long)sp * plan.n_sub / n_sp;
-    const long long sub1 = (long long)(sp + 1) * plan.n_sub / n_sp;
-    const long long t_begin = sub0 * 32;
-    long long t_end = sub1 * 32;
-    if (t_end > T) t_end = T;
-
-    // B rows of this wave into registers: column block w covers positions
-    // kb*KWG + wave*WK*32 + w*32 + li; feature n = HALF*h + s.
-    float breg[WK][HALF];
-    int pos[WK];
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      pos[w] = kb * KWG + wave * WK * 32 + w * 32 + li;
-      int row = -1;
-      if (pos[w] < kact) row = act ? act[pos[w]] : pos[w];
-#pragma unroll
-      for (int s = 0; s < HALF; ++s) {
-        const int n = HALF * h + s;
-        breg[w][s] = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
-      }
-    }
-
-    f32x16 gacc[WK][NP / 32];
-    float s4acc[WK];
-    double s4acc64[WK];
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      s4acc[w] = 0.f;
-      s4acc64[w] = 0.0;
-#pragma unroll
-      for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
-    }
-
-    for (long long m_tile = t_begin; m_tile < t_end; m_tile += TT) {
-      __syncthreads();
-      for (int e = tid; e < NP * TT; e += WAVES * 64) {
-        const int n = e / TT;
-        const int m = e % TT;
-        const long long gm = m_tile + m;
-        xs[n * SX + m] = (n < N && gm < t_end) ? X[(size_t)n * (size_t)T + (size_t)gm] : 0.f;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int sub = 0; sub < TT / 32; ++sub) {
-        if (m_tile + sub * 32 >= t_end) break;
-        const int m0 = sub * 32;
-        f32x16 zacc[WK];
-#pragma unroll
-        for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
-#pragma unroll
-        for (int s = 0; s < HALF; ++s) {
-          const float a = xs[(HALF * h + s) * SX + m0 + li];
-#pragma unroll
-          for (int w = 0; w < WK; ++w)
-            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, breg[w][s], zacc[w], 0, 0, 0);
-        }
-        if constexpr (KURT) {
-#pragma unroll
-          for (int w = 0; w < WK; ++w) {
-            float t4 = 0.f;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const float z2 = zacc[w][v] * zacc[w][v];
-              t4 = fmaf(z2, z2, t4);
-            }
-            s4acc64[w] += (double)t4;
-          }
-        } else {
-          f32x16 p3[WK];
-#pragma unroll
-          for (int w = 0; w < WK; ++w) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const float z = zacc[w][v];
-              const float z2 = z * z;
-              p3[w][v] = z2 * z;
-              s4acc[w] = fmaf(z2, z2, s4acc[w]);
-            }
-          }
-#pragma unroll
-          for (int nb = 0; nb < NP / 32; ++nb) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const int m = m0 + 8 * (v / 4) + 4 * h + (v % 4);
-              const float a = xs[(nb * 32 + li) * SX + m];
-#pragma unroll
-              for (int w = 0; w < WK; ++w)
-                gacc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, p3[w][v], gacc[w][nb], 0, 0, 0);
-            }
-          }
-        }
-      }
-    }
-
-    // Write this item's partials.
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      if constexpr (KURT) {
-        const double tot = s4acc64[w] + __shfl_xor(s4acc64[w], 32);
-        if (h == 0 && pos[w] < kact) s4part64[(size_t)sp * rows_pad + pos[w]] = tot;
-      } else {
-        const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
-        if (pos[w] < kact) {
-          if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
-          float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
-#pragma unroll
-          for (int nb = 0; nb < NP / 32; ++nb) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              f32x4 v4;
-              v4[0] = gacc[w][nb][4 * q + 0];
-              v4[1] = gacc[w][nb][4 * q + 1];
-              v4[2] = gacc[w][nb][4 * q + 2];
-              v4[3] = gacc[w][nb][4 * q + 3];
-              *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
-            }
-          }
-        }
-      }
-    }
+    item_f32<NP, WK, KURT>(c, w_item % n_kb, w_item / n_kb, xs);
   }
 }
-
-// ---------------------------------------------------------------------------
-// BF16 pass kernel: X stored in BF16, both contractions on
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation; z^3 rounded to BF16
-// (nearest even) to feed GEMM2.  Each row b is split once per work item into
-// b_hi = bf16(b) and b_lo = bf16(b - b_hi), and GEMM1 runs on both, so z carries
-// b to ~2^-17 relative: rounding b itself to BF16 would make the update map
-// piecewise constant in b and leave the step stuck near 1e-4.  Operand layout (lane l, h = l / 32, i = l % 32): A[i][8h + j],
-// B[8h + j][i] for j = 0..7 (8 bf16 per lane); D as in the FP32 kernel.
-// GEMM1 reads the transposed LDS copy xt[m][n] (8 consecutive features, one
-// 16-byte read); GEMM2 reads xs[n][m] (two runs of 4 consecutive samples).
-// With v = 8q + j for MFMA q of a 32-sample sub-tile, GEMM1's accumulator
-// lane holds sample m = 16q + 8(j/4) + 4h + j%4 at k-index 8h + j, so the
-// cubed registers are GEMM2's B operand directly.
-// ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-constexpr int BT = 64;          // samples per LDS tile
-constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
-template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
 
 template <int NP, int WK>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
@@ -286,150 +118,12 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
   const int per_xcd_wgs = plan.grid / 8;
   const int xcd = blockIdx.x % 8;
   const int local = blockIdx.x / 8;
-
-  const int tid = threadIdx.x;
-  const int wave = tid / 64;
-  const int lane = tid % 64;
-  const int h = lane / 32;
-  const int li = lane % 32;
-  const bool vec_ok = (T % 8) == 0;
-
+  const ItemCtx c{X, N, T, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part, nullptr};
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
-    const int kb = w_item % n_kb;
-    const int sp = w_item / n_kb;
-    const long long sub0 = (long long)sp * plan.n_sub / n_sp;
-    const long long sub1 = (long long)(sp + 1) * plan.n_sub / n_sp;
-    const long long t_begin = sub0 * 32;
-    long long t_end = sub1 * 32;
-    if (t_end > T) t_end = T;
-
-    bf16x8 breg[WK][NP / 16], blo[WK][NP / 16];
-    int pos[WK];
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      pos[w] = kb * KWG + wave * WK * 32 + w * 32 + li;
-      int row = -1;
-      if (pos[w] < kact) row = act ? act[pos[w]] : pos[w];
-#pragma unroll
-      for (int s = 0; s < NP / 16; ++s) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int n = 16 * s + 8 * h + j;
-          const float b = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
-          const __bf16 hi = (__bf16)b;
-          breg[w][s][j] = hi;
-          blo[w][s][j] = (__bf16)(b - (float)hi);
-        }
-      }
-    }
-
-    f32x16 gacc[WK][NP / 32];
-    float s4acc[WK];
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      s4acc[w] = 0.f;
-#pragma unroll
-      for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
-    }
-
-    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT) {
-      __syncthreads();
-      // fill: 8 consecutive samples of one feature row per thread-iteration
-      for (int e = tid; e < NP * (BT / 8); e += WAVES * 64) {
-        const int n = e / (BT / 8);
-        const int mc = (e % (BT / 8)) * 8;
-        const long long gm = m_tile + mc;
-        bf16x8 v;
-        if (n < N && vec_ok && gm + 8 <= t_end) {
-          v = *reinterpret_cast<const bf16x8 *>(X + (size_t)n * (size_t)T + (size_t)gm);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            v[j] = (n < N && gm + j < t_end) ? X[(size_t)n * (size_t)T + (size_t)(gm + j)]
-                                             : (__bf16)0.f;
-        }
-        *reinterpret_cast<bf16x8 *>(&xs[n * BSX + mc]) = v;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xt[(mc + j) * XTS + n] = v[j];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int sub = 0; sub < BT / 32; ++sub) {
-        if (m_tile + sub * 32 >= t_end) break;
-        const int m0 = sub * 32;
-        f32x16 zacc[WK];
-#pragma unroll
-        for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
-#pragma unroll
-        for (int s = 0; s < NP / 16; ++s) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&xt[(m0 + li) * XTS + 16 * s + 8 * h]);
-#pragma unroll
-          for (int w = 0; w < WK; ++w) {
-            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, breg[w][s], zacc[w], 0, 0, 0);
-            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[w][s], zacc[w], 0, 0, 0);
-          }
-        }
-        bf16x8 p3[WK][2];
-#pragma unroll
-        for (int w = 0; w < WK; ++w) {
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const float z = zacc[w][v];
-            const float z2 = z * z;
-            p3[w][v / 8][v % 8] = (__bf16)(z2 * z);
-            s4acc[w] = fmaf(z2, z2, s4acc[w]);
-          }
-        }
-#pragma unroll
-        for (int nb = 0; nb < NP / 32; ++nb) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const __bf16 *src = &xs[(nb * 32 + li) * BSX + m0 + 16 * q + 4 * h];
-            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(src);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(src + 8);
-            bf16x8 a;
-            a[0] = lo[0]; a[1] = lo[1]; a[2] = lo[2]; a[3] = lo[3];
-            a[4] = hi[0]; a[5] = hi[1]; a[6] = hi[2]; a[7] = hi[3];
-#pragma unroll
-            for (int w = 0; w < WK; ++w)
-              gacc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, p3[w][q], gacc[w][nb], 0, 0, 0);
-          }
-        }
-      }
-    }
-
-#pragma unroll
-    for (int w = 0; w < WK; ++w) {
-      const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
-      if (pos[w] < kact) {
-        if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
-        float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
-#pragma unroll
-        for (int nb = 0; nb < NP / 32; ++nb) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            f32x4 v4;
-            v4[0] = gacc[w][nb][4 * q + 0];
-            v4[1] = gacc[w][nb][4 * q + 1];
-            v4[2] = gacc[w][nb][4 * q + 2];
-            v4[3] = gacc[w][nb][4 * q + 3];
-            *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
-          }
-        }
-      }
-    }
+    item_bf16<NP, WK>(c, w_item % n_kb, w_item / n_kb, xs, xt);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Wave reductions (64 lanes).
-// ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -439,8 +133,6 @@ __device__ inline double wave_sum(double v) {
 // long-split tail passes (few rows, many splits) are as parallel as the
 // full-width passes.
 // ---------------------------------------------------------------------------
-constexpr int SPLIT_GROUP = 16;
-constexpr int RED_GRID = 2048;
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_split_reduce(FusedPlan plan, const FpControl *ctl, int pass,

@@ -11,6 +11,9 @@
 
 namespace oica {
 
+constexpr int WAVES_PER_WG = 4;      // waves per work-group of the fused kernels
+constexpr int SPLIT_GROUP_HOST = 16; // splits per first-stage reduction item
+
 // Device-side bookkeeping of one fixed-point run.  Written by single lanes of
 // the fixed-point kernels; read back by the host when it polls.
 struct FpControl {
@@ -39,6 +42,31 @@ __host__ __device__ inline int plan_splits(const FusedPlan &p, int n_kb) {
   if (s < 1) s = 1;
   return s;
 }
+
+// One dataset of the batched form (device array, one entry per dataset).
+struct BatchDesc {
+  const void *X;       // pass data, FP32 or BF16 (N x T)
+  const float *X32;    // FP32 copy
+  float *B;            // K x N rows (the caller's W_out)
+  int *act0;           // active list read on even passes
+  int *act1;           // active list read on odd passes
+  FpControl *ctl;
+  float *gpart;        // n_sp x (K + 256) x np partial G
+  float *s4part;       // n_sp x (K + 256) partial sum z^4
+  double *red;         // first-stage reduction sums
+  int32_t *iters;
+  uint8_t *status;
+  long long T;
+  int N, K, np, wk, kwg, n_sp, n_sub, variant;
+};
+
+// Batch-wide counters of one pass.
+struct BatchCtl {
+  int counter[2];      // work-queue heads, by pass parity
+  int total_items;
+  int total_epi;
+  long long total_red;
+};
 
 // ---- launchers (defined next to their kernels) ----------------------------
 
@@ -79,6 +107,18 @@ hipError_t launch_propagate(hipStream_t st, int K, int N, const int *cluster, co
                             float *W, uint8_t *status, double *kurt);
 hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,
                                 const int *left_list, int left);
+
+// batched.hip
+int batch_splits(int64_t T);
+int batch_max_datasets();
+hipError_t launch_batch_plan(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
+                             int *item_start, long long *red_start, int *epi_start, int pass,
+                             bool dry);
+hipError_t launch_fused_batched(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
+                                const int *item_start, int pass, int grid);
+hipError_t launch_epilogue_batched(hipStream_t st, const BatchDesc *descs, int D,
+                                   const BatchCtl *bctl, const long long *red_start,
+                                   const int *epi_start, int pass, double tol, int kmax_total);
 
 // unique.hip
 size_t unique_workspace_bytes(int K);

@@ -44,6 +44,24 @@ class FpStats(C.Structure):
                 ("update_ms", C.c_double), ("update_launches", C.c_int)]
 
 
+class Problem(C.Structure):
+    _fields_ = [("N", C.c_int), ("T", C.c_int64), ("K", C.c_int), ("Xw", C.c_void_p),
+                ("Xw_f32", C.c_void_p), ("W0", C.c_void_p), ("W_out", C.c_void_p),
+                ("kurt", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p)]
+
+
+class BatchParams(C.Structure):
+    _fields_ = [("autotune", C.c_int), ("cache_path", C.c_char_p), ("force_wk", C.c_int),
+                ("force_grid", C.c_int)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("thread_iters", C.c_int64), ("refine_thread_iters", C.c_int64),
+                ("passes", C.c_int), ("ms", C.c_double), ("update_ms", C.c_double),
+                ("update_launches", C.c_int), ("grid", C.c_int), ("wk32", C.c_int),
+                ("wk64", C.c_int), ("tuned", C.c_int)]
+
+
 class UniqueParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("gaussianity_test", C.c_int), ("n_top", C.c_int)]
 
@@ -61,6 +79,9 @@ _SIGS = {
                                    C.POINTER(FpParams), _P, _P, _P, _P, _P, C.POINTER(FpStats)]),
     "oica_update": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, C.c_int, _P, _P, _P]),
     "oica_kurtosis": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, _P]),
+    "oica_fixed_point_batched": (C.c_int, [_P, C.c_int, C.POINTER(Problem), C.c_int,
+                                           C.POINTER(FpParams), C.POINTER(BatchParams),
+                                           C.POINTER(BatchStats)]),
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
                               C.c_int, _P, _P, _P, _P, _P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
 }
@@ -189,6 +210,44 @@ class Context:
                 "thread_iters": int(st.thread_iters), "passes": int(st.passes),
                 "refine_thread_iters": int(st.refine_thread_iters), "ms": float(st.ms),
                 "update_ms": float(st.update_ms), "update_launches": int(st.update_launches)}
+
+    def fixed_point_batched(self, problems, max_iter=1000, tol=1e-6, precision="f32",
+                            tol_bf16=1e-5, refine_iters=5, check_every=4, profile=False,
+                            autotune=True, cache_path=None, force_wk=0, force_grid=0):
+        """problems: list of dicts with device tensors Xw (N x T), W0 (K x N float32) and,
+        for BF16 data, Xw_f32.  Returns (list of per-problem outputs, stats dict)."""
+        D = len(problems)
+        arr = (Problem * D)()
+        outs = []
+        dev = self._tdev()
+        for d, q in enumerate(problems):
+            Xw = _dev(q["Xw"], "Xw")
+            X32 = _dev(q.get("Xw_f32", Xw), "Xw_f32")
+            W0 = _dev(q["W0"], "W0")
+            N, T = Xw.shape
+            K = W0.shape[0]
+            o = {"W": torch.empty((K, N), dtype=torch.float32, device=dev),
+                 "kurt": torch.empty(K, dtype=torch.float64, device=dev),
+                 "iters": torch.empty(K, dtype=torch.int32, device=dev),
+                 "status": torch.empty(K, dtype=torch.uint8, device=dev)}
+            arr[d] = Problem(N, T, K, Xw.data_ptr(), X32.data_ptr(), W0.data_ptr(),
+                             o["W"].data_ptr(), o["kurt"].data_ptr(), o["iters"].data_ptr(),
+                             o["status"].data_ptr())
+            o["_keep"] = (Xw, X32, W0)
+            outs.append(o)
+        xw_t = OICA_BF16 if precision == "bf16" else OICA_F32
+        p = FpParams(max_iter, tol, xw_t, tol_bf16, refine_iters, 0, check_every,
+                     1 if profile else 0, 0)
+        bp = BatchParams(1 if autotune else 0, cache_path.encode() if cache_path else None,
+                         force_wk, force_grid)
+        st = BatchStats()
+        rc = self.lib.oica_fixed_point_batched(self.h, D, arr, xw_t, C.byref(p), C.byref(bp),
+                                               C.byref(st))
+        self._check(rc)
+        for o in outs:
+            o.pop("_keep")
+        stats = {k: getattr(st, k) for k, _ in BatchStats._fields_}
+        return outs, stats
 
     def update(self, Xw, B):
         _dev(Xw, "Xw")
