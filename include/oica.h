@@ -130,6 +130,8 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
  * traj: optional K x traj_iters x 2 FP32 record of (kurtosis of the row
  *   before pass t+1, step d of pass t+1); NaN once a row has stopped.
  * ------------------------------------------------------------------------- */
+typedef struct oica_pruner oica_pruner;
+
 typedef struct {
   int max_iter;          /* >= 1                                           */
   double tol;            /* > 0, FP32 threshold (1e-6 is the paper's)      */
@@ -149,6 +151,19 @@ typedef struct {
                             passes and the kurtosis pass, and the other
                             members receive its row (with their own sign),
                             status and kurtosis.                           */
+  const oica_pruner *pruner; /* NULL: plain run.  Else, after pass
+                            prune_pass the active rows whose predicted
+                            probability of ending in a top-ranked component
+                            is below the pruner's threshold become PRUNED
+                            (row and counts kept); after the run, if one of
+                            the top components (the first guard_top
+                            accepted ones and those whose criterion is
+                            within a relative 1e-3 of the guard_top-th) has
+                            fewer than guard_min rows, every pruned row is
+                            resumed from its saved state and finished.     */
+  int prune_pass;        /* pass after which to prune (8..16; 0 = 8)       */
+  int guard_top;         /* components checked by the guard (0 = 20)       */
+  int guard_min;         /* rows each of them must keep (0 = 4)            */
 } oica_fp_params;
 
 typedef struct {         /* host */
@@ -160,6 +175,8 @@ typedef struct {         /* host */
                             update launch (launches issued after the last
                             row stopped, before the next poll, exit at once) */
   int update_launches;   /* profile = 1: number of those launches          */
+  int pruned;            /* rows pruned (pruner set)                       */
+  int guard_tripped;     /* 1: the guard resumed the pruned rows           */
 } oica_fp_stats;
 
 /* N in [1, OICA_MAX_N], T > N, K >= 1.
@@ -187,6 +204,38 @@ int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t
  * FP32 products of FP32 data with FP64 sums over samples.  Does not synchronise. */
 int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
                   const float *W, double *kurt);
+
+/* ---------------------------------------------------------------------------
+ * Learned pruner (an extension beyond the paper, built on its trajectories):
+ * a 16 -> 64 -> 64 -> 1 network (ReLU, sigmoid) reads, for the first eight
+ * passes of a start vector, the kurtosis before the pass and log10 of the step
+ * (features interleaved per pass, standardised with fixed statistics) and
+ * predicts whether the vector ends in one of the top-ranked components.  The
+ * forward pass uses FP16 weights with FP32 arithmetic; training keeps FP32
+ * master weights and Adam moments.  Parameters are packed W1 (64 x 16, row
+ * major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1).
+ * ------------------------------------------------------------------------- */
+#define OICA_PRUNER_PARAMS 5313
+
+/* init_w: host, OICA_PRUNER_PARAMS FP32; feat_mean, feat_std: host, 16 each
+ * (std > 0).  The pruner lives on ctx's device.  Synchronises. */
+int oica_pruner_create(oica_ctx *ctx, const float *init_w, const float *feat_mean,
+                       const float *feat_std, oica_pruner **out);
+void oica_pruner_destroy(oica_pruner *p);
+/* FP32 master weights to host (OICA_PRUNER_PARAMS floats).  Synchronises. */
+int oica_pruner_get_weights(oica_ctx *ctx, const oica_pruner *p, float *host_w);
+int oica_pruner_set_threshold(oica_pruner *p, float theta);
+/* prob[r] = network output for traj rows r = 0..R-1 (traj: R x 8 x 2 FP32). */
+int oica_pruner_predict(oica_ctx *ctx, const oica_pruner *p, const float *traj, int64_t R,
+                        float *prob);
+/* Mean loss (host) and its gradient (device, OICA_PRUNER_PARAMS FP32) over R
+ * rows: binary cross-entropy with positive-class weight w_pos.  Synchronises. */
+int oica_pruner_grad(oica_ctx *ctx, const oica_pruner *p, const float *traj,
+                     const uint8_t *labels, int64_t R, float w_pos, float *grad, double *loss);
+/* One Adam step (lr; betas 0.9, 0.999; eps 1e-8) on the gradient of the rows
+ * given; the loss before the step goes to *loss (host, may be NULL). */
+int oica_pruner_train_step(oica_ctx *ctx, oica_pruner *p, const float *traj,
+                           const uint8_t *labels, int64_t R, float w_pos, float lr, double *loss);
 
 /* ---------------------------------------------------------------------------
  * Batched form: D independent problems of uneven N, T and K run the passes of
@@ -262,13 +311,15 @@ typedef struct {
 /* W: K x N FP32 unit rows; kurt: K FP64; status: K uint8 (as from oica_fixed_point).
  * Outputs (device) for the first min(n_unique, cap) clusters: U cap x N FP64,
  * kurt_u, ups_u (cap FP64), rep_thread, cluster_size (cap int32).
+ * row_cluster: optional K int32, the rank (0-based, output order) of the
+ * cluster each row joined, -1 for rows that were not candidates.
  * n_unique, n_accepted: host.  Synchronises.
  * Errors: OICA_E_ARG; OICA_E_SHAPE if cap < n_unique (the counts are still
  * written, and the first cap clusters). */
 int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const double *kurt,
                 const uint8_t *status, const oica_unique_params *params, int cap,
                 double *U, double *kurt_u, double *ups_u, int32_t *rep_thread,
-                int32_t *cluster_size, int *n_unique, int *n_accepted);
+                int32_t *cluster_size, int32_t *row_cluster, int *n_unique, int *n_accepted);
 
 #ifdef __cplusplus
 }

@@ -200,7 +200,8 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
                FpControl *ctl,
                int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
                float *traj, int traj_iters, bool profile, int *launched, double *kernel_ms,
-               int exit_below = 0, int stall_polls = 0) {
+               int exit_below = 0, int stall_polls = 0, const PrunerState *pruner = nullptr,
+               int prune_pass = 0, int *keep = nullptr, int *prune_counts = nullptr) {
   // exit_below > 0: stop once at most exit_below rows are active;
   // stall_polls > 0: stop once the active count has not shrunk over that many polls.
   int kmax = K;  // upper bound on the active count (it never grows)
@@ -224,6 +225,13 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
     *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, plan, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
                                  s4part, red, tol, iters, status, traj, traj_iters));
+    if (pruner && pass + 1 == prune_pass) {
+      // the list of pass prune_pass is nxt, its count kact[prune_pass & 1]
+      HIP_TRY(ctx, hipMemsetAsync(prune_counts, 0, sizeof(int), ctx->stream));
+      HIP_TRY(ctx, launch_prune(ctx->stream, pruner, traj, 2 * traj_iters, nxt,
+                                &ctl->kact[prune_pass & 1], kmax, status, keep, prune_counts,
+                                prune_counts + 1));
+    }
     if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                                   ctx->stream));
@@ -250,6 +258,11 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
 
 }  // namespace
 
+struct oica_pruner {
+  int device = 0;
+  PrunerState st;
+};
+
 int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
                      const float *Xw_f32, int K, const float *W0, const oica_fp_params *params,
                      float *W_out, double *kurt, int32_t *iters, uint8_t *status, float *traj,
@@ -268,21 +281,39 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   const bool bf16 = params->precision == OICA_BF16;
   if (bf16 && xw_t != OICA_BF16) return fail(ctx, OICA_E_ARG, "BF16 precision needs xw_t == OICA_BF16");
   if (!bf16 && xw_t != OICA_F32) return fail(ctx, OICA_E_ARG, "F32 precision needs xw_t == OICA_F32");
+  const PrunerState *pruner = params->pruner ? &params->pruner->st : nullptr;
+  const int prune_pass = params->prune_pass > 0 ? params->prune_pass : 8;
+  const int guard_top = params->guard_top > 0 ? params->guard_top : 20;
+  const int guard_min = params->guard_min > 0 ? params->guard_min : 4;
+  if (pruner) {
+    if (params->pruner->device != ctx->device)
+      return fail(ctx, OICA_E_ARG, "the pruner lives on another device");
+    if (prune_pass < 8 || prune_pass > 16)
+      return fail(ctx, OICA_E_ARG, "prune_pass must be in [8, 16] (the network reads passes 1-8)");
+    if (params->traj_iters > 0 && params->traj_iters < prune_pass)
+      return fail(ctx, OICA_E_ARG, "traj_iters must be 0 or >= prune_pass when pruning");
+  }
+  // the pruner reads the first prune_pass passes of the trajectory
+  const int traj_n = pruner ? (params->traj_iters > 0 ? params->traj_iters : prune_pass)
+                            : params->traj_iters;
 
   const auto t0 = std::chrono::steady_clock::now();
   const FusedPlan plan = make_plan(N, T, K, bf16);
   const size_t gfl = fp_workspace_floats(plan, N, K);
   const int np = fused_np(N);
   const size_t rows_max = gfl / np;
+  const int gcap = guard_top + 64;  // room for components tied with the guard_top-th
   size_t need = 0;
   need += gfl * sizeof(float) + 256;            // gpart
   need += rows_max * sizeof(float) + 256;       // s4part
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
   const size_t red_n = fp_reduce_doubles(plan, N, K);
   need += red_n * sizeof(double) + 256;         // split-group sums
-  need += 4 * ((size_t)K * sizeof(int) + 256);  // act lists + kurtosis list
-  need += 3 * (sizeof(FpControl) + 256);
-  need += unique_workspace_bytes(K) + 256;      // grouping of BF16 fixed points
+  need += 5 * ((size_t)K * sizeof(int) + 256);  // act lists, kurtosis list, prune survivors
+  need += 4 * (sizeof(FpControl) + 256);
+  need += unique_workspace_bytes(K) + 256;      // grouping of BF16 fixed points / guard
+  if (pruner && !traj) need += (size_t)K * traj_n * 2 * sizeof(float) + 256;
+  if (pruner) need += (size_t)gcap * (N * 8 + 8 + 8 + 4 + 4) + 5 * 256;
   rc = ensure_ws(ctx, need);
   if (rc) return rc;
   Carve cv{(char *)ctx->ws};
@@ -294,93 +325,249 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   int *act1 = cv.take<int>(K);
   int *act2 = cv.take<int>(K);
   int *kurt_list = cv.take<int>(K);
+  int *keep = cv.take<int>(K);
   FpControl *ctl = cv.take<FpControl>(1);
   FpControl *ctl2 = cv.take<FpControl>(1);
   (void)cv.take<FpControl>(1);  // third control block (kurtosis list), ctl2 + 256 bytes
+  int *prune_counts = (int *)cv.take<FpControl>(1);  // [0] survivors, [1] pruned
   void *gwork = cv.take<char>(unique_workspace_bytes(K));
+  float *traj_buf = traj;
+  if (pruner && !traj) traj_buf = cv.take<float>((size_t)K * traj_n * 2);
+  double *gU = nullptr, *gk = nullptr, *gu = nullptr;
+  int32_t *grep = nullptr, *gsize = nullptr;
+  if (pruner) {
+    gU = cv.take<double>((size_t)gcap * N);
+    gk = cv.take<double>(gcap);
+    gu = cv.take<double>(gcap);
+    grep = cv.take<int32_t>(gcap);
+    gsize = cv.take<int32_t>(gcap);
+  }
 
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 3 * 256, ctx->stream));
-  HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj,
-                                params->traj_iters));
+  HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 4 * 256, ctx->stream));
+  HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj_buf,
+                                traj_n));
   const int check_every = params->check_every > 0 ? params->check_every : 4;
-  int launched = 0;
-  double kernel_ms = 0.0;
   const bool profile = params->profile != 0;
-  // main loop: FP32 data at tol, or BF16 data at tol_bf16.  The BF16 loop ends
-  // early once at most K/64 rows are left or the active count stops shrinking
-  // (rows that sit at the BF16 rounding floor just above tol_bf16 would
-  // otherwise use up max_iter passes); those rows finish on FP32 data.
+  // The BF16 loop ends early once at most K/64 rows are left or the active
+  // count stops shrinking (rows that sit at the BF16 rounding floor just above
+  // tol_bf16 would otherwise use up max_iter passes); those rows finish on
+  // FP32 data.
   const int bf16_exit = bf16 ? (K / 64 > 0 ? K / 64 : 1) : 0;
   const int bf16_stall = bf16 ? 2 : 0;
-  rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
-                  params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
-                  status, traj, params->traj_iters, profile, &launched, &kernel_ms, bf16_exit,
-                  bf16_stall);
-  if (rc) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
-                              ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  const FpControl main_ctl = *(const FpControl *)ctx->small_host;
-  long long refine_ti = 0;
-  bool kurt_done = false;
-  if (bf16) {
-    const int left_rows = main_ctl.kact[launched & 1];
-    const int *left_list = (launched & 1) ? act1 : act0;
-    const int budget_left = params->max_iter - launched;
-    const int fp32_passes = budget_left > params->refine_iters ? budget_left : params->refine_iters;
-    const FusedPlan plan32 = make_plan(N, T, K, false);
-    int l2 = 0;
-    double ms2 = 0.0;
-    if (params->refine_groups) {
-      // group rows that sit at numerically the same BF16 fixed point; one row
-      // per group takes the FP32 passes and the kurtosis pass
-      int *cluster = nullptr, *reps = nullptr;
-      HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 4 * sizeof(int), ctx->stream));
-      HIP_TRY(ctx, launch_groups(ctx->stream, N, K, W_out, status, 1e-6, gwork, ctx->small_dev,
-                                 ctx->small_host, &cluster, &reps));
-      const int n_groups = ctx->small_host[1];
-      FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
-      HIP_TRY(ctx, hipMemsetAsync(ctl3, 0, sizeof(FpControl), ctx->stream));
-      HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, n_groups, status, act2, ctl2,
-                                      left_list, left_rows, kurt_list, ctl3));
-      if (fp32_passes > 0) {
-        rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
-                        ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
-                        false, &l2, &ms2);
-        if (rc) return rc;
-      }
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, Xw_f32, K, W_out, s4part64, kurt,
-                                   kurt_list, &ctl3->kact[0]));
-      HIP_TRY(ctx, launch_propagate(ctx->stream, K, N, cluster, reps, W_out, status, kurt));
-      kurt_done = true;
-    } else {
-      // FP32 passes for every row that converged on BF16 data or is still moving
-      HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2, left_list, left_rows));
-      if (fp32_passes > 0) {
-        rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
-                        ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
-                        false, &l2, &ms2);
-        if (rc) return rc;
-      }
-    }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl2, sizeof(FpControl), hipMemcpyDeviceToHost,
+  long long main_ti = 0, refine_ti = 0;
+  int main_passes = 0, launched_total = 0, pruned = 0, tripped = 0;
+  double kernel_ms_total = 0.0;
+
+  // attempt 0: every row (pruned at prune_pass when a pruner is set);
+  // attempt 1: only when the guard trips, the pruned rows resumed
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    int launched = 0;
+    double kernel_ms = 0.0;
+    const bool prune_now = pruner && attempt == 0;
+    rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
+                    params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
+                    status, attempt == 0 ? traj_buf : nullptr, attempt == 0 ? traj_n : 0, profile,
+                    &launched, &kernel_ms, bf16_exit, bf16_stall, prune_now ? pruner : nullptr,
+                    prune_pass, keep, prune_counts);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                                 ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 16, prune_counts, 2 * sizeof(int),
+                                hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    refine_ti = ((const FpControl *)ctx->small_host)->thread_iters;
+    const FpControl main_ctl = *(const FpControl *)ctx->small_host;
+    if (prune_now) pruned = ctx->small_host[17];
+    main_ti += main_ctl.thread_iters;
+    main_passes += main_ctl.passes;
+    launched_total += launched;
+    kernel_ms_total += kernel_ms;
+    bool kurt_done = false;
+    if (bf16) {
+      const int left_rows = main_ctl.kact[launched & 1];
+      const int *left_list = (launched & 1) ? act1 : act0;
+      const int budget_left = params->max_iter - launched;
+      const int fp32_passes = budget_left > params->refine_iters ? budget_left : params->refine_iters;
+      const FusedPlan plan32 = make_plan(N, T, K, false);
+      int l2 = 0;
+      double ms2 = 0.0;
+      HIP_TRY(ctx, hipMemsetAsync(ctl2, 0, 2 * 256, ctx->stream));
+      if (params->refine_groups) {
+        // group rows that sit at numerically the same BF16 fixed point; one row
+        // per group takes the FP32 passes and the kurtosis pass
+        int *cluster = nullptr, *reps = nullptr;
+        HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 4 * sizeof(int), ctx->stream));
+        HIP_TRY(ctx, launch_groups(ctx->stream, N, K, W_out, status, 1e-6, gwork, ctx->small_dev,
+                                   ctx->small_host, &cluster, &reps));
+        const int n_groups = ctx->small_host[1];
+        FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
+        HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, n_groups, status, act2, ctl2,
+                                        left_list, left_rows, kurt_list, ctl3));
+        if (fp32_passes > 0) {
+          rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
+                          ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
+                          false, &l2, &ms2);
+          if (rc) return rc;
+        }
+        HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, Xw_f32, K, W_out, s4part64, kurt,
+                                     kurt_list, &ctl3->kact[0]));
+        HIP_TRY(ctx, launch_propagate(ctx->stream, K, N, cluster, reps, W_out, status, kurt));
+        kurt_done = true;
+      } else {
+        // FP32 passes for every row that converged on BF16 data or is still moving
+        HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2, left_list, left_rows));
+        if (fp32_passes > 0) {
+          rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part,
+                          red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
+                          0, false, &l2, &ms2);
+          if (rc) return rc;
+        }
+      }
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl2, sizeof(FpControl), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      refine_ti += ((const FpControl *)ctx->small_host)->thread_iters;
+    }
+    if (!kurt_done)
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
+                                   s4part64, kurt));
+    if (!(prune_now && pruned > 0)) break;
+    // guard: every one of the first guard_top accepted components must keep
+    // guard_min rows in the pruned run, else the pruned rows are resumed
+    HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
+    HIP_TRY(ctx, launch_unique(ctx->stream, N, T, K, W_out, kurt, status, 1e-3, 1, 0, gcap, gU, gk,
+                               gu, grep, gsize, gwork, ctx->small_host, ctx->small_dev));
+    const int n_acc = ctx->small_host[3];
+    const int n_got = n_acc < gcap ? n_acc : gcap;
+    std::vector<int32_t> sizes(gcap);
+    std::vector<double> ups(gcap);
+    if (n_got > 0) {
+      HIP_TRY(ctx, hipMemcpy(sizes.data(), gsize, (size_t)n_got * sizeof(int32_t),
+                             hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpy(ups.data(), gu, (size_t)n_got * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    // the top components: the first guard_top accepted ones and every accepted
+    // one whose criterion is within a relative 1e-3 of the guard_top-th (ties)
+    bool ok = true;
+    if (n_got > 0) {
+      const double cut = ups[(guard_top < n_got ? guard_top : n_got) - 1];
+      for (int r = 0; r < n_got; ++r)
+        if (r < guard_top || ups[r] >= cut - 1e-3 * fabs(cut)) ok &= sizes[r] >= guard_min;
+    }
+    if (ok) break;
+    tripped = 1;
+    HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 256, ctx->stream));
+    HIP_TRY(ctx, launch_unprune(ctx->stream, K, status, act0, ctl));
   }
-  if (!kurt_done)
-    HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
-                                 s4part64, kurt));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
-    stats->thread_iters = main_ctl.thread_iters;
-    stats->passes = main_ctl.passes;
+    stats->thread_iters = main_ti;
+    stats->passes = main_passes;
     stats->refine_thread_iters = refine_ti;
     stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    stats->update_ms = profile ? kernel_ms : 0.0;
-    stats->update_launches = profile ? launched : 0;
+    stats->update_ms = profile ? kernel_ms_total : 0.0;
+    stats->update_launches = profile ? launched_total : 0;
+    stats->pruned = pruned;
+    stats->guard_tripped = tripped;
   }
+  return OICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned pruner
+// ---------------------------------------------------------------------------
+int oica_pruner_create(oica_ctx *ctx, const float *init_w, const float *feat_mean,
+                       const float *feat_std, oica_pruner **out) {
+  if (!ctx || !out) return OICA_E_ARG;
+  *out = nullptr;
+  ctx->err.clear();
+  if (!init_w || !feat_mean || !feat_std) return fail(ctx, OICA_E_ARG, "null argument");
+  for (int i = 0; i < 16; ++i)
+    if (!(feat_std[i] > 0.f) || !isfinite(feat_std[i]) || !isfinite(feat_mean[i]))
+      return fail(ctx, OICA_E_ARG, "feature statistics must be finite with std > 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  oica_pruner *p = new oica_pruner();
+  p->device = ctx->device;
+  hipError_t e = pruner_alloc(&p->st, init_w, feat_mean, feat_std);
+  if (e != hipSuccess) {
+    pruner_free(&p->st);
+    delete p;
+    return fail(ctx, OICA_E_DEVICE, "pruner allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return OICA_OK;
+}
+
+void oica_pruner_destroy(oica_pruner *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  pruner_free(&p->st);
+  delete p;
+}
+
+int oica_pruner_get_weights(oica_ctx *ctx, const oica_pruner *p, float *host_w) {
+  if (!ctx || !p || !host_w) return OICA_E_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipMemcpy(host_w, p->st.w32, OICA_PRUNER_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+  return OICA_OK;
+}
+
+int oica_pruner_set_threshold(oica_pruner *p, float theta) {
+  if (!p || !(theta >= 0.f && theta <= 1.f)) return OICA_E_ARG;
+  p->st.theta = theta;
+  return OICA_OK;
+}
+
+int oica_pruner_predict(oica_ctx *ctx, const oica_pruner *p, const float *traj, int64_t R,
+                        float *prob) {
+  if (!ctx || !p) return OICA_E_ARG;
+  ctx->err.clear();
+  if (!traj || !prob || R < 1) return fail(ctx, OICA_E_ARG, "traj, prob must be non-null and R >= 1");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_pruner_predict(ctx->stream, &p->st, traj, R, nullptr, nullptr, prob));
+  return OICA_OK;
+}
+
+static int pruner_grad_impl(oica_ctx *ctx, const oica_pruner *p, const float *traj,
+                            const uint8_t *labels, int64_t R, float w_pos, float *grad,
+                            double *loss) {
+  if (!traj || !labels || !grad || R < 1 || !(w_pos > 0.f))
+    return fail(ctx, OICA_E_ARG, "traj, labels, grad non-null, R >= 1, w_pos > 0 required");
+  int rc = ensure_ws(ctx, pruner_grad_workspace_bytes(R) + 512);
+  if (rc) return rc;
+  double *loss_dev = (double *)((char *)ctx->ws + ctx->ws_bytes - 256);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_pruner_grad(ctx->stream, &p->st, traj, labels, R, w_pos, ctx->ws, grad, loss_dev));
+  if (loss) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, loss_dev, sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    *loss = *(const double *)ctx->small_host / (double)R;
+  }
+  return OICA_OK;
+}
+
+int oica_pruner_grad(oica_ctx *ctx, const oica_pruner *p, const float *traj, const uint8_t *labels,
+                     int64_t R, float w_pos, float *grad, double *loss) {
+  if (!ctx || !p) return OICA_E_ARG;
+  ctx->err.clear();
+  return pruner_grad_impl(ctx, p, traj, labels, R, w_pos, grad, loss);
+}
+
+int oica_pruner_train_step(oica_ctx *ctx, oica_pruner *p, const float *traj, const uint8_t *labels,
+                           int64_t R, float w_pos, float lr, double *loss) {
+  if (!ctx || !p) return OICA_E_ARG;
+  ctx->err.clear();
+  if (!(lr > 0.f)) return fail(ctx, OICA_E_ARG, "lr must be > 0");
+  // gradient goes to the first bytes of the small device buffer region of the
+  // workspace tail; keep it separate from the partials
+  int rc = ensure_ws(ctx, pruner_grad_workspace_bytes(R) + OICA_PRUNER_PARAMS * 4 + 1024);
+  if (rc) return rc;
+  float *grad = (float *)((char *)ctx->ws + ctx->ws_bytes - 512 - OICA_PRUNER_PARAMS * 4);
+  rc = pruner_grad_impl(ctx, p, traj, labels, R, w_pos, grad, loss);
+  if (rc) return rc;
+  HIP_TRY(ctx, launch_pruner_adam(ctx->stream, &p->st, grad, lr));
   return OICA_OK;
 }
 
@@ -762,7 +949,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
 int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const double *kurt,
                 const uint8_t *status, const oica_unique_params *params, int cap, double *U,
                 double *kurt_u, double *ups_u, int32_t *rep_thread, int32_t *cluster_size,
-                int *n_unique, int *n_accepted) {
+                int32_t *row_cluster, int *n_unique, int *n_accepted) {
   if (!ctx) return OICA_E_ARG;
   ctx->err.clear();
   int rc = check_dims(ctx, N, T);
@@ -782,7 +969,8 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
   HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
   HIP_TRY(ctx, launch_unique(ctx->stream, N, T, K, W, kurt, status, params->tau,
                              params->gaussianity_test, params->n_top, cap, U, kurt_u, ups_u,
-                             rep_thread, cluster_size, ctx->ws, ctx->small_host, ctx->small_dev));
+                             rep_thread, cluster_size, ctx->ws, ctx->small_host, ctx->small_dev,
+                             row_cluster));
   *n_unique = ctx->small_host[1];
   *n_accepted = ctx->small_host[3];
   if (cap < *n_unique)

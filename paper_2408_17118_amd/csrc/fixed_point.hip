@@ -297,6 +297,23 @@ __global__ void k_refine_select(int K, uint8_t *__restrict__ status, int *__rest
   if (i < left) dst[atomicAdd(&ctl->kact[0], 1)] = left_list[i];
 }
 
+// Rows pruned earlier go back into the active set (status NOTCONV), their
+// rows and iteration counts as they were left.
+__global__ void k_unprune(int K, uint8_t *__restrict__ status, int *__restrict__ list,
+                          FpControl *ctl) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= K) return;
+  if (status[row] == OICA_ROW_PRUNED) {
+    status[row] = OICA_ROW_NOTCONV;
+    list[atomicAdd(&ctl->kact[0], 1)] = row;
+  }
+}
+
+hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpControl *ctl) {
+  hipLaunchKernelGGL(k_unprune, dim3((K + 255) / 256), dim3(256), 0, st, K, status, list, ctl);
+  return hipGetLastError();
+}
+
 // G = sum_sp gpart / T - 3 B and s4 = sum_sp s4part / T for rows 0..K-1
 // (positions equal rows).
 template <int NP>

@@ -43,6 +43,18 @@ __host__ __device__ inline int plan_splits(const FusedPlan &p, int n_kb) {
   return s;
 }
 
+// The learned pruner's device state.
+struct PrunerState {
+  float *w32 = nullptr;   // FP32 master weights
+  void *w16 = nullptr;    // FP16 copy used by every forward pass
+  float *m = nullptr;     // Adam moments
+  float *v = nullptr;
+  float mean[16];         // feature standardisation
+  float stdv[16];
+  float theta = 0.f;      // prune threshold on the predicted probability
+  int step = 0;           // Adam steps taken
+};
+
 // One dataset of the batched form (device array, one entry per dataset).
 struct BatchDesc {
   const void *X;       // pass data, FP32 or BF16 (N x T)
@@ -120,6 +132,21 @@ hipError_t launch_epilogue_batched(hipStream_t st, const BatchDesc *descs, int D
                                    const BatchCtl *bctl, const long long *red_start,
                                    const int *epi_start, int pass, double tol, int kmax_total);
 
+// pruner.hip
+hipError_t pruner_alloc(PrunerState *p, const float *init_w, const float *mean, const float *stdv);
+void pruner_free(PrunerState *p);
+hipError_t launch_pruner_predict(hipStream_t st, const PrunerState *p, const float *traj, long long R,
+                                 const int *list, const int *count_dev, float *prob);
+size_t pruner_grad_workspace_bytes(long long R);
+hipError_t launch_pruner_grad(hipStream_t st, const PrunerState *p, const float *traj,
+                              const uint8_t *labels, long long R, float w_pos, void *ws,
+                              float *grad, double *loss_dev);
+hipError_t launch_pruner_adam(hipStream_t st, PrunerState *p, const float *grad, float lr);
+hipError_t launch_prune(hipStream_t st, const PrunerState *p, const float *traj, int traj_stride,
+                        int *list, int *count_dev, int kmax, uint8_t *status, int *keep,
+                        int *keep_count, int *pruned_count);
+hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpControl *ctl);
+
 // unique.hip
 size_t unique_workspace_bytes(int K);
 hipError_t launch_groups(hipStream_t st, int N, int K, const float *W, const uint8_t *status,
@@ -129,6 +156,6 @@ hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W
                          const double *kurt, const uint8_t *status, double tau, int gtest,
                          int n_top, int cap, double *U, double *kurt_u, double *ups_u,
                          int32_t *rep_thread, int32_t *cluster_size, void *ws, int *counts_host,
-                         int *counts_dev);
+                         int *counts_dev, int32_t *row_cluster = nullptr);
 
 }  // namespace oica

@@ -152,9 +152,13 @@ __global__ __launch_bounds__(U_BLOCK) void k_pick(int nblocks, const double *__r
   }
 }
 
-__global__ void k_sizes(int K, const int *__restrict__ cluster, int *__restrict__ sizes) {
+__global__ void k_sizes(int K, const int *__restrict__ cluster, int *__restrict__ sizes,
+                        int32_t *__restrict__ row_cluster) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < K && cluster[l] >= 0) atomicAdd(&sizes[cluster[l]], 1);
+  if (l >= K) return;
+  const int c = cluster[l];
+  if (c >= 0) atomicAdd(&sizes[c], 1);
+  if (row_cluster) row_cluster[l] = c >= 0 ? c : -1;
 }
 
 // Output of the first min(U, cap) clusters, and the Gaussianity walk.
@@ -277,7 +281,7 @@ hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W
                          const double *kurt, const uint8_t *status, double tau, int gtest,
                          int n_top, int cap, double *U, double *kurt_u, double *ups_u,
                          int32_t *rep_thread, int32_t *cluster_size, void *ws, int *counts_host,
-                         int *counts_dev) {
+                         int *counts_dev, int32_t *row_cluster) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
   char *p = (char *)ws;
   auto take = [&](size_t bytes) {
@@ -299,7 +303,7 @@ hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W
   hipError_t e = launch_cluster(st, N, K, W, w.key, w.cluster, w.reps, w.part_idx, tau, w.ctl,
                                 counts_host);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sizes, dim3(nb), dim3(U_BLOCK), 0, st, K, w.cluster, w.sizes);
+  hipLaunchKernelGGL(k_sizes, dim3(nb), dim3(U_BLOCK), 0, st, K, w.cluster, w.sizes, row_cluster);
   hipLaunchKernelGGL(k_finalize, dim3(64), dim3(128), 0, st, N, (long long)T, W, kurt, w.key,
                      w.reps, w.sizes, gtest, n_top, cap, U, kurt_u, ups_u, rep_thread,
                      cluster_size, w.ctl);

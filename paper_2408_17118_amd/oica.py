@@ -35,13 +35,16 @@ class OicaError(RuntimeError):
 class FpParams(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("tol_bf16", C.c_double), ("refine_iters", C.c_int), ("traj_iters", C.c_int),
-                ("check_every", C.c_int), ("profile", C.c_int), ("refine_groups", C.c_int)]
+                ("check_every", C.c_int), ("profile", C.c_int), ("refine_groups", C.c_int),
+                ("pruner", C.c_void_p), ("prune_pass", C.c_int), ("guard_top", C.c_int),
+                ("guard_min", C.c_int)]
 
 
 class FpStats(C.Structure):
     _fields_ = [("thread_iters", C.c_int64), ("passes", C.c_int),
                 ("refine_thread_iters", C.c_int64), ("ms", C.c_double),
-                ("update_ms", C.c_double), ("update_launches", C.c_int)]
+                ("update_ms", C.c_double), ("update_launches", C.c_int),
+                ("pruned", C.c_int), ("guard_tripped", C.c_int)]
 
 
 class Problem(C.Structure):
@@ -82,8 +85,18 @@ _SIGS = {
     "oica_fixed_point_batched": (C.c_int, [_P, C.c_int, C.POINTER(Problem), C.c_int,
                                            C.POINTER(FpParams), C.POINTER(BatchParams),
                                            C.POINTER(BatchStats)]),
+    "oica_pruner_create": (C.c_int, [_P, _P, _P, _P, C.POINTER(_P)]),
+    "oica_pruner_destroy": (None, [_P]),
+    "oica_pruner_get_weights": (C.c_int, [_P, _P, _P]),
+    "oica_pruner_set_threshold": (C.c_int, [_P, C.c_float]),
+    "oica_pruner_predict": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "oica_pruner_grad": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, _P,
+                                   C.POINTER(C.c_double)]),
+    "oica_pruner_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float,
+                                         C.POINTER(C.c_double)]),
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
-                              C.c_int, _P, _P, _P, _P, _P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+                              C.c_int, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int),
+                              C.POINTER(C.c_int)]),
 }
 
 
@@ -182,7 +195,7 @@ class Context:
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
                     tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
-                    refine_groups=True):
+                    refine_groups=True, pruner=None, prune_pass=8, guard_top=20, guard_min=4):
         _dev(Xw, "Xw")
         _dev(W0, "W0")
         if W0.dtype != torch.float32:
@@ -200,7 +213,8 @@ class Context:
         traj = torch.empty((K, traj_iters, 2), dtype=torch.float32, device=dev) if traj_iters else None
         p = FpParams(max_iter, tol, OICA_BF16 if precision == "bf16" else OICA_F32, tol_bf16,
                      refine_iters, traj_iters, check_every, 1 if profile else 0,
-                     1 if refine_groups else 0)
+                     1 if refine_groups else 0, pruner.h if pruner is not None else None,
+                     prune_pass, guard_top, guard_min)
         st = FpStats()
         rc = self.lib.oica_fixed_point(self.h, N, T, _ptr(Xw), _DT[Xw.dtype], _ptr(Xw_f32), K,
                                        _ptr(W0), C.byref(p), _ptr(W), _ptr(kurt), _ptr(iters),
@@ -209,7 +223,8 @@ class Context:
         return {"W": W, "kurt": kurt, "iters": iters, "status": status, "traj": traj,
                 "thread_iters": int(st.thread_iters), "passes": int(st.passes),
                 "refine_thread_iters": int(st.refine_thread_iters), "ms": float(st.ms),
-                "update_ms": float(st.update_ms), "update_launches": int(st.update_launches)}
+                "update_ms": float(st.update_ms), "update_launches": int(st.update_launches),
+                "pruned": int(st.pruned), "guard_tripped": int(st.guard_tripped)}
 
     def fixed_point_batched(self, problems, max_iter=1000, tol=1e-6, precision="f32",
                             tol_bf16=1e-5, refine_iters=5, check_every=4, profile=False,
@@ -237,7 +252,7 @@ class Context:
             outs.append(o)
         xw_t = OICA_BF16 if precision == "bf16" else OICA_F32
         p = FpParams(max_iter, tol, xw_t, tol_bf16, refine_iters, 0, check_every,
-                     1 if profile else 0, 0)
+                     1 if profile else 0, 0, None, 0, 0, 0)
         bp = BatchParams(1 if autotune else 0, cache_path.encode() if cache_path else None,
                          force_wk, force_grid)
         st = BatchStats()
@@ -271,7 +286,8 @@ class Context:
         return kurt
 
     # ---- a12-a13 ----------------------------------------------------------------
-    def unique(self, W, kurt, status, T, tau=1e-3, gaussianity_test=True, n_top=0, cap=None):
+    def unique(self, W, kurt, status, T, tau=1e-3, gaussianity_test=True, n_top=0, cap=None,
+               row_cluster=False):
         _dev(W, "W")
         K, N = W.shape
         cap = K if cap is None else cap
@@ -281,26 +297,96 @@ class Context:
         uu = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
         rep = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         size = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        rc_rows = torch.empty(K, dtype=torch.int32, device=dev) if row_cluster else None
         nu, na = C.c_int(), C.c_int()
         p = UniqueParams(tau, 1 if gaussianity_test else 0, n_top)
         rc = self.lib.oica_unique(self.h, N, T, K, _ptr(W), _ptr(kurt), _ptr(status), C.byref(p), cap,
-                                  _ptr(U), _ptr(ku), _ptr(uu), _ptr(rep), _ptr(size), C.byref(nu),
-                                  C.byref(na))
+                                  _ptr(U), _ptr(ku), _ptr(uu), _ptr(rep), _ptr(size), _ptr(rc_rows),
+                                  C.byref(nu), C.byref(na))
         self._check(rc)
         n = nu.value
-        return {"U": U[:n], "alpha": ku[:n], "upsilon": uu[:n], "rep": rep[:n], "size": size[:n],
-                "n_unique": n, "n_accepted": na.value}
+        out = {"U": U[:n], "alpha": ku[:n], "upsilon": uu[:n], "rep": rep[:n], "size": size[:n],
+               "n_unique": n, "n_accepted": na.value}
+        if row_cluster:
+            out["row_cluster"] = rc_rows
+        return out
+
+
+class Pruner:
+    """The learned pruner (weights on the context's device)."""
+
+    N_PARAMS = 5313
+
+    def __init__(self, ctx: Context, init_w, feat_mean, feat_std):
+        import numpy as np
+        self.ctx = ctx
+        w = np.ascontiguousarray(init_w, dtype=np.float32)
+        m = np.ascontiguousarray(feat_mean, dtype=np.float32)
+        sd = np.ascontiguousarray(feat_std, dtype=np.float32)
+        if w.size != self.N_PARAMS or m.size != 16 or sd.size != 16:
+            raise ValueError("pruner needs 5313 weights and 16 feature means / stds")
+        h = C.c_void_p()
+        rc = ctx.lib.oica_pruner_create(ctx.h, w.ctypes.data, m.ctypes.data, sd.ctypes.data,
+                                        C.byref(h))
+        ctx._check(rc)
+        self.h = h
+        self.feat_mean, self.feat_std = m, sd
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.oica_pruner_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        import numpy as np
+        out = np.empty(self.N_PARAMS, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.oica_pruner_get_weights(self.ctx.h, self.h, out.ctypes.data))
+        return out
+
+    def set_threshold(self, theta: float):
+        self.ctx._check(self.ctx.lib.oica_pruner_set_threshold(self.h, float(theta)))
+        self.theta = float(theta)
+
+    def predict(self, traj):
+        _dev(traj, "traj")
+        R = traj.shape[0]
+        prob = torch.empty(R, dtype=torch.float32, device=traj.device)
+        self.ctx._check(self.ctx.lib.oica_pruner_predict(self.ctx.h, self.h, _ptr(traj), R,
+                                                         _ptr(prob)))
+        return prob
+
+    def grad(self, traj, labels, w_pos):
+        R = traj.shape[0]
+        g = torch.empty(self.N_PARAMS, dtype=torch.float32, device=traj.device)
+        loss = C.c_double()
+        self.ctx._check(self.ctx.lib.oica_pruner_grad(self.ctx.h, self.h, _ptr(traj), _ptr(labels),
+                                                      R, float(w_pos), _ptr(g), C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, traj, labels, w_pos, lr=1e-3):
+        R = traj.shape[0]
+        loss = C.c_double()
+        self.ctx._check(self.ctx.lib.oica_pruner_train_step(self.ctx.h, self.h, _ptr(traj),
+                                                            _ptr(labels), R, float(w_pos),
+                                                            float(lr), C.byref(loss)))
+        return loss.value
 
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
                  tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
-                 profile=False, refine_groups=True):
+                 profile=False, refine_groups=True, pruner=None, traj_iters=0):
     """Whole hot path on device-resident raw data: whiten -> fixed point -> unique."""
     xw_dtype = torch.bfloat16 if precision == "bf16" else torch.float32
     Xw, Xw32, V, mean, eig = ctx.whiten(X, out_dtype=xw_dtype)
     fp = ctx.fixed_point(Xw, W0, Xw_f32=Xw32, max_iter=max_iter, tol=tol, precision=precision,
                          tol_bf16=tol_bf16, refine_iters=refine_iters, profile=profile,
-                         refine_groups=refine_groups)
+                         refine_groups=refine_groups, pruner=pruner, traj_iters=traj_iters)
     res = ctx.unique(fp["W"], fp["kurt"], fp["status"], X.shape[1], tau=tau,
                      gaussianity_test=gaussianity_test)
     res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)

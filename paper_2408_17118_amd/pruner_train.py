@@ -1,0 +1,179 @@
+"""Train and calibrate the learned pruner on the GPU.
+
+For every seeded training dataset (EEG-shaped, N=64, T=2e5, K=65536 start
+vectors) the plain BF16 run records each row's first eight passes (kurtosis
+before the pass, step of the pass); a row is labelled positive when it ends in
+a top component: one of the accepted components whose ordering criterion is at
+least that of the ``r_top``-th one, less a relative 1e-3 (components tied with
+the ``r_top``-th, such as the sinusoids, which all have kurtosis -1.5, are all
+top or all not).  Only rows still moving after pass 8 are training rows (the
+others are never pruned).  The network is trained with the library's own
+forward/backward/Adam kernels (binary cross-entropy weighted by n_neg / n_pos).
+The threshold is the largest value that keeps, in every top component of every
+calibration dataset, min(``keep_min``, its size) rows, times a safety factor.
+
+Usage: python -m paper_2408_17118_amd.pruner_train --out model.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import oica, synth
+
+H = 64
+
+
+def simulate(ctx, seed: int, K: int = 65536, N: int = 64, T: int = 200_000, pruner=None,
+             precision: str = "bf16"):
+    """One dataset through the path with trajectories recorded; returns the
+    fixed-point outputs, the unique result with per-row clusters and timings."""
+    prob = synth.pruner_workload(seed, N=N, T=T, K=K)
+    dev = torch.device("cuda", ctx.device)
+    X = torch.from_numpy(prob.X).to(dev)
+    W0 = torch.from_numpy(prob.W0.astype(np.float32)).to(dev)
+    xdt = torch.bfloat16 if precision == "bf16" else torch.float32
+    Xw, X32, V, mean, eig = ctx.whiten(X, out_dtype=xdt)
+    del X
+    fp = ctx.fixed_point(Xw, W0, Xw_f32=X32, precision=precision, traj_iters=8, pruner=pruner)
+    un = ctx.unique(fp["W"], fp["kurt"], fp["status"], T, row_cluster=True)
+    return {"fp": fp, "unique": un, "T": T, "V": V}
+
+
+def top_clusters(un, r_top: int) -> int:
+    """Number of leading clusters that are top components (ties included)."""
+    n = un["n_accepted"]
+    if n == 0:
+        return 0
+    ups = un["upsilon"].cpu().numpy()[:n]
+    cut = ups[min(r_top, n) - 1]
+    return int((ups >= cut - 1e-3 * abs(cut)).sum())
+
+
+def labels_and_mask(sim, r_top: int):
+    """(labels uint8, prunable bool) per row, on the device."""
+    fp, un = sim["fp"], sim["unique"]
+    top = top_clusters(un, r_top)
+    rc = un["row_cluster"]
+    y = ((rc >= 0) & (rc < top)).to(torch.uint8)
+    prunable = torch.isfinite(fp["traj"][:, 7, 0]) & torch.isfinite(fp["traj"][:, 7, 1])
+    return y, prunable
+
+
+def feature_stats(traj: np.ndarray):
+    f = np.empty((traj.shape[0], 16))
+    f[:, 0::2] = traj[:, :, 0]
+    f[:, 1::2] = np.log10(np.maximum(traj[:, :, 1].astype(np.float64), 1e-12))
+    return f.mean(axis=0), np.maximum(f.std(axis=0), 1e-6)
+
+
+def init_weights(rng: np.random.Generator) -> np.ndarray:
+    """He-uniform weights for the ReLU layers, zero biases (W1, b1, W2, b2, w3, b3)."""
+    parts = [rng.uniform(-np.sqrt(6 / 16), np.sqrt(6 / 16), (H, 16)), np.zeros(H),
+             rng.uniform(-np.sqrt(6 / H), np.sqrt(6 / H), (H, H)), np.zeros(H),
+             rng.uniform(-np.sqrt(6 / H), np.sqrt(6 / H), H), np.zeros(1)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def collect(ctx, seeds, r_top, log=print):
+    trajs, labels, meta = [], [], []
+    for s in seeds:
+        t0 = time.time()
+        sim = simulate(ctx, s)
+        y, m = labels_and_mask(sim, r_top)
+        trajs.append(sim["fp"]["traj"][m].contiguous())
+        labels.append(y[m].contiguous())
+        meta.append({"seed": s, "rows": int(m.sum()), "pos": int(y[m].sum()),
+                     "accepted": sim["unique"]["n_accepted"], "s": time.time() - t0})
+        log(f"seed {s}: {meta[-1]}")
+        del sim
+    return torch.cat(trajs), torch.cat(labels), meta
+
+
+def train(ctx, traj, labels, epochs=4, batch=65536, lr=2e-3, seed=0, log=print):
+    th = traj.cpu().numpy()
+    mean, std = feature_stats(th)
+    pr = oica.Pruner(ctx, init_weights(np.random.default_rng(seed)), mean, std)
+    n = traj.shape[0]
+    n_pos = int(labels.sum())
+    w_pos = float((n - n_pos) / max(n_pos, 1))
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(traj.device)
+        losses = []
+        for i in range(0, n, batch):
+            idx = perm[i:i + batch]
+            losses.append(pr.train_step(traj[idx].contiguous(), labels[idx].contiguous(), w_pos, lr))
+        hist.append(float(np.mean(losses)))
+        log(f"epoch {ep}: mean loss {hist[-1]:.4f}")
+    return pr, {"w_pos": w_pos, "rows": n, "pos": n_pos, "loss": hist}
+
+
+def calibrate(ctx, pr, seeds, r_top, keep_min, safety=0.5, log=print):
+    """Largest threshold keeping min(keep_min, size) rows in every top component."""
+    theta = 1.0
+    for s in seeds:
+        sim = simulate(ctx, s)
+        y, m = labels_and_mask(sim, r_top)
+        p = torch.ones_like(sim["fp"]["kurt"], dtype=torch.float32)
+        if int(m.sum()):
+            p[m] = pr.predict(sim["fp"]["traj"][m].contiguous())
+        rc = sim["unique"]["row_cluster"]
+        top = top_clusters(sim["unique"], r_top)
+        for c in range(top):
+            members = rc == c
+            fixed = int((members & ~m).sum())         # converged before pass 8: never pruned
+            size = int(members.sum())
+            need = min(keep_min, size) - fixed
+            if need <= 0:
+                continue
+            pc = torch.sort(p[members & m], descending=True).values
+            theta = min(theta, float(pc[need - 1]))
+        log(f"calibration seed {s}: theta so far {theta:.4g}")
+        del sim
+    return theta * safety
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--train", default="5000:5200")
+    ap.add_argument("--calib", default="5200:5240")
+    ap.add_argument("--r-top", type=int, default=20)
+    ap.add_argument("--keep-min", type=int, default=16)
+    ap.add_argument("--guard-min", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    args = ap.parse_args(argv)
+    a, b = map(int, args.train.split(":"))
+    c, d = map(int, args.calib.split(":"))
+    ctx = oica.Context(0)
+    t0 = time.time()
+    traj, labels, meta = collect(ctx, range(a, b), args.r_top, log=lambda m: print(m, flush=True))
+    t1 = time.time()
+    pr, tinfo = train(ctx, traj, labels, epochs=args.epochs, lr=args.lr,
+                      log=lambda m: print(m, flush=True))
+    t2 = time.time()
+    theta = calibrate(ctx, pr, range(c, d), args.r_top, args.keep_min,
+                      log=lambda m: print(m, flush=True))
+    t3 = time.time()
+    model = {"weights": [float(x) for x in pr.weights()],
+             "feat_mean": [float(x) for x in pr.feat_mean], "feat_std": [float(x) for x in pr.feat_std],
+             "theta": theta, "r_top": args.r_top, "keep_min": args.keep_min,
+             "guard_min": args.guard_min,
+             "train_seeds": [a, b], "calib_seeds": [c, d], "train": tinfo,
+             "seconds": {"collect": t1 - t0, "train": t2 - t1, "calibrate": t3 - t2},
+             "datasets": meta}
+    with open(args.out, "w") as f:
+        json.dump(model, f)
+    print(f"wrote {args.out}: theta {theta:.4g}, rows {tinfo['rows']}, pos {tinfo['pos']}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -57,7 +57,7 @@ def test_null_context_is_an_argument_error():
                                 None, None, None) == -1
     nu, na = C.c_int(), C.c_int()
     assert lib.oica_unique(None, 4, 100, 8, None, None, None, None, 0, None, None, None, None, None,
-                           C.byref(nu), C.byref(na)) == -1
+                           None, C.byref(nu), C.byref(na)) == -1
     assert lib.oica_create(None, 0, None) == -1
     assert lib.oica_last_error(None) == b""
     lib.oica_destroy(None)

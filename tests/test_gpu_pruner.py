@@ -1,0 +1,130 @@
+"""Learned pruner on the GPU, through the C ABI.
+
+* Gradient, loss, prediction and one Adam step against the FP64 reference
+  (oracle/mlp.py) on the same inputs.  The GPU forward pass uses the FP16 copy
+  of the weights, so the reference runs on those FP16-rounded values (exact in
+  FP64); the remaining difference is FP32 arithmetic:
+  |g - g_ref| <= 1e-3 |g_ref| + 1e-4 max|g_ref|.
+* Pruning inside the fixed point: threshold 0 prunes nothing (results equal
+  the plain run bitwise); threshold 1 prunes every row still moving at pass 8,
+  the guard then resumes them and the unique set equals the plain run's.
+"""
+import numpy as np
+import pytest
+
+from oracle import ica, mlp
+from paper_2408_17118_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2408_17118_amd import oica
+    c = oica.Context(0)
+    yield c
+    c.close()
+
+
+def _traj(R, seed):
+    rng = np.random.default_rng(seed)
+    t = np.empty((R, 8, 2), np.float32)
+    t[:, :, 0] = rng.normal(1.0, 2.0, (R, 8))
+    t[:, :, 1] = 10.0 ** rng.uniform(-9, 0, (R, 8))
+    y = (t[:, 7, 0] + rng.normal(0, 1, R) > 1.5).astype(np.uint8)
+    return t, y
+
+
+def _stats(t):
+    f = np.empty((t.shape[0], 16))
+    f[:, 0::2] = t[:, :, 0]
+    f[:, 1::2] = np.log10(np.maximum(t[:, :, 1].astype(np.float64), 1e-12))
+    return f.mean(axis=0), f.std(axis=0)
+
+
+def _make(ctx, seed=0):
+    from paper_2408_17118_amd import oica
+    t, y = _traj(3000, seed)
+    mean, std = _stats(t)
+    w0 = mlp.init_params(np.random.default_rng(seed)).astype(np.float32)
+    return oica.Pruner(ctx, w0, mean, std), t, y, w0, mean, std
+
+
+def _ref_features(t, mean, std):
+    # the GPU standardises with FP32 copies of the statistics
+    return mlp.features(t.astype(np.float64), mean.astype(np.float32).astype(np.float64),
+                        std.astype(np.float32).astype(np.float64))
+
+
+def test_gradient_and_loss_match_reference(ctx):
+    pr, t, y, w0, mean, std = _make(ctx)
+    w16 = w0.astype(np.float16).astype(np.float64)
+    w_pos = float((y == 0).sum() / max((y == 1).sum(), 1))
+    g, loss = pr.grad(torch.from_numpy(t).cuda(), torch.from_numpy(y).cuda(), w_pos)
+    lr, gr = mlp.loss_and_grad(w16, _ref_features(t, mean, std), y.astype(np.float64), w_pos)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - lr) <= 1e-5 * abs(lr)
+    assert np.all(np.abs(g - gr) <= 1e-3 * np.abs(gr) + 1e-4 * np.abs(gr).max()), \
+        float(np.max(np.abs(g - gr)))
+
+
+def test_predict_matches_reference(ctx):
+    pr, t, y, w0, mean, std = _make(ctx, seed=1)
+    p = pr.predict(torch.from_numpy(t).cuda()).cpu().numpy()
+    z, _ = mlp.forward(w0.astype(np.float16).astype(np.float64), _ref_features(t, mean, std))
+    assert np.allclose(p, mlp.sigmoid(z), atol=2e-5)
+
+
+def test_adam_step_matches_reference(ctx):
+    pr, t, y, w0, mean, std = _make(ctx, seed=2)
+    w_pos = 2.0
+    T, Y = torch.from_numpy(t).cuda(), torch.from_numpy(y).cuda()
+    loss0 = pr.train_step(T, Y, w_pos, lr=1e-3)
+    w1 = pr.weights().astype(np.float64)
+    _, g = mlp.loss_and_grad(w0.astype(np.float16).astype(np.float64), _ref_features(t, mean, std),
+                             y.astype(np.float64), w_pos)
+    ref, _, _ = mlp.adam_step(w0.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g, 1)
+    # first Adam step moves every weight by ~lr sign(g); allow the FP32 gradient error
+    assert np.all(np.abs(w1 - ref) <= 2e-5 + 1e-3 * np.abs(ref - w0))
+    assert loss0 > 0
+
+
+def test_training_reduces_loss(ctx):
+    pr, t, y, w0, mean, std = _make(ctx, seed=3)
+    T, Y = torch.from_numpy(t).cuda(), torch.from_numpy(y).cuda()
+    w_pos = float((y == 0).sum() / max((y == 1).sum(), 1))
+    first = pr.train_step(T, Y, w_pos, lr=3e-3)
+    for _ in range(300):
+        last = pr.train_step(T, Y, w_pos, lr=3e-3)
+    assert last < 0.6 * first, (first, last)
+    p = pr.predict(T).cpu().numpy()
+    acc = ((p > 0.5) == (y == 1)).mean()
+    assert acc > 0.85
+
+
+def test_pruning_paths(ctx):
+    from paper_2408_17118_amd import oica
+    prob = synth.make_problem(synth.eeg_kinds(16), T=20_000, K=2048, seed=4)
+    Xw, *_ = ica.whiten(prob.X)
+    X = torch.from_numpy(Xw.astype(np.float32)).cuda()
+    W0 = torch.from_numpy(prob.W0.astype(np.float32)).cuda()
+    pr, *_ = _make(ctx, seed=5)
+    plain = ctx.fixed_point(X, W0, tol=1e-6)
+    pr.set_threshold(0.0)
+    none = ctx.fixed_point(X, W0, tol=1e-6, pruner=pr)
+    assert none["pruned"] == 0 and none["guard_tripped"] == 0
+    for k in ("W", "kurt", "iters", "status"):
+        assert torch.equal(plain[k], none[k]), k
+    pr.set_threshold(1.0)
+    allp = ctx.fixed_point(X, W0, tol=1e-6, pruner=pr, guard_top=20, guard_min=16)
+    assert allp["pruned"] > 0
+    ua = ctx.unique(plain["W"], plain["kurt"], plain["status"], prob.T)
+    ub = ctx.unique(allp["W"], allp["kurt"], allp["status"], prob.T)
+    if allp["guard_tripped"]:
+        assert ua["n_accepted"] == ub["n_accepted"]
+        n = ua["n_accepted"]
+        cos = np.abs(ua["U"].cpu().numpy()[:n] @ ub["U"].cpu().numpy()[:n].T)
+        assert np.all(cos.max(axis=1) >= 1 - 1e-6)
+    st = allp["status"].cpu().numpy()
+    assert not np.any(st == ica.PRUNED) or not allp["guard_tripped"]

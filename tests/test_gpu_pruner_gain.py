@@ -1,0 +1,83 @@
+"""What the trained pruner gains, on held-out seeds of the pruner workload
+(EEG-shaped, N=64, T=2e5, K=65536; seeds 5300-5319 were used neither for
+training nor for calibration).
+
+For each dataset three GPU runs from the same data and start vectors:
+  plain FP32, BF16 + FP32 finish without the pruner, BF16 + FP32 finish with
+  the pruner (model shipped in paper_2408_17118_amd/pruner_model.json).
+Required: the top components (the first 20 accepted ones and those tied with
+the 20th) of the pruned run are those of the plain FP32 run (|cos| >= 1 - 1e-6,
+kurtosis within 1e-5 max(|alpha|, 0.1)); the pruner removes rows and the pruned
+run needs fewer thread-iterations than the unpruned BF16 run (unless the guard
+resumed the pruned rows).  Timings and counts are printed (pytest -s).
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_2408_17118_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2408_17118_amd",
+                     "pruner_model.json")
+
+
+def _top(un, r_top=20):
+    n = un["n_accepted"]
+    ups = un["upsilon"].cpu().numpy()[:n]
+    cut = ups[min(r_top, n) - 1]
+    k = int((ups >= cut - 1e-3 * abs(cut)).sum())
+    return un["U"].cpu().numpy()[:k], un["alpha"].cpu().numpy()[:k]
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) * 1e3
+
+
+@pytest.mark.parametrize("seed", [5300, 5301, 5302])
+def test_pruned_run_keeps_top_components_and_saves_work(seed):
+    from paper_2408_17118_amd import oica
+    m = json.load(open(MODEL))
+    ctx = oica.Context(0)
+    pr = oica.Pruner(ctx, np.array(m["weights"], np.float32), m["feat_mean"], m["feat_std"])
+    pr.set_threshold(m["theta"])
+    prob = synth.pruner_workload(seed)
+    X = torch.from_numpy(prob.X).cuda()
+    W0 = torch.from_numpy(prob.W0.astype(np.float32)).cuda()
+    # warm-up of every kernel family on this context
+    oica.ordering_ica(ctx, X, W0[:4096].contiguous(), precision="bf16", pruner=pr)
+    plain, t_plain = _timed(lambda: oica.ordering_ica(ctx, X, W0, precision="f32"))
+    b16, t_b16 = _timed(lambda: oica.ordering_ica(ctx, X, W0, precision="bf16"))
+    prn, t_prn = _timed(lambda: oica.ordering_ica(ctx, X, W0, precision="bf16", pruner=pr))
+    fp = prn["fp"]
+    print(f"seed {seed}: plain f32 {t_plain:.1f} ms ({plain['fp']['thread_iters']} thread-its), "
+          f"bf16 {t_b16:.1f} ms ({b16['fp']['thread_iters']}), bf16+pruner {t_prn:.1f} ms "
+          f"({fp['thread_iters']}, pruned {fp['pruned']}, guard {fp['guard_tripped']}); "
+          f"speedup vs plain f32 {t_plain / t_prn:.2f}x")
+    Ua, aa = _top(plain)
+    Ub, ab = _top(prn)
+    assert len(Ua) == len(Ub)
+    Va, Vb = plain["V"].cpu().numpy(), prn["V"].cpu().numpy()
+    Ra = Ua @ Va
+    Rb = Ub @ Vb
+    Ra /= np.linalg.norm(Ra, axis=1, keepdims=True)
+    Rb /= np.linalg.norm(Rb, axis=1, keepdims=True)
+    cos = np.abs(Ra @ Rb.T)
+    assert np.all(cos.max(axis=1) >= 1 - 1e-6)
+    j = cos.argmax(axis=1)
+    assert len(set(j)) == len(j)
+    assert np.all(np.abs(aa - ab[j]) <= 1e-5 * np.maximum(np.abs(aa), 0.1))
+    assert fp["pruned"] > 0
+    if not fp["guard_tripped"]:
+        assert fp["thread_iters"] < b16["fp"]["thread_iters"]
+    pr.close()
+    ctx.close()
