@@ -11,10 +11,17 @@ Prints one JSON line.  ``value`` is thread-iterations per second over the whole
 step (a thread-iteration is one update of one start vector: 2 N T MACs);
 ``ms_per_step`` is the time from raw data in HBM to the unique list on the host.
 
+After the timed region the same workload runs in the mixed-precision form
+(BF16 data, BF16 MFMA, FP32 finish of one row per group of identical BF16
+fixed points) and the line reports its time to unique components, the speedup
+over the plain FP32 step and whether the accepted components are the same.
+
 ``--workload precision_n128`` times the precision form instead (N=128, T=1e6,
 K=16384): BF16 data and BF16 MFMA with FP32 sums, then FP32 passes until the
 FP32 threshold; its roofline entry is the BF16 fused kernel against the BF16
-MFMA peak.
+MFMA peak.  ``--workload pruner_n64`` times the learned-pruner workload (N=64,
+T=2e5, K=65536, held-out seed 5300): BF16 with the shipped pruner, reported
+against the plain FP32 and the unpruned BF16 runs.
 """
 from __future__ import annotations
 
@@ -59,7 +66,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="eeg_shaped_n64",
-                    choices=["eeg_shaped_n64", "precision_n128"])
+                    choices=["eeg_shaped_n64", "precision_n128", "pruner_n64"])
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -124,13 +131,23 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda", 0)
-    bf16 = args.workload == "precision_n128"
-    prob = synth.precision_workload() if bf16 else synth.eeg_shaped()
+    bf16 = args.workload in ("precision_n128", "pruner_n64")
+    if args.workload == "precision_n128":
+        prob = synth.precision_workload()
+    elif args.workload == "pruner_n64":
+        prob = synth.pruner_workload(5300)
+    else:
+        prob = synth.eeg_shaped()
     N, T, K = prob.N, prob.T, prob.K
     precision = "bf16" if bf16 else "f32"
     X = torch.from_numpy(prob.X).to(dev)
     W0 = torch.from_numpy(prob.W0.astype(np.float32)).to(dev)
     ctx = oica.Context(0)
+    pruner = None
+    if args.workload == "pruner_n64":
+        m = json.load(open(os.path.join(ROOT, "paper_2408_17118_amd", "pruner_model.json")))
+        pruner = oica.Pruner(ctx, np.array(m["weights"], np.float32), m["feat_mean"], m["feat_std"])
+        pruner.set_threshold(m["theta"])
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -140,7 +157,7 @@ def main():
 
     def step(profile=False):
         return oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, tau=1e-3, profile=profile,
-                                 precision=precision, tol_bf16=1e-5, refine_iters=5)
+                                 precision=precision, tol_bf16=1e-5, refine_iters=5, pruner=pruner)
 
     for i in range(args.warmup):
         r = step()
@@ -166,8 +183,10 @@ def main():
     flops = 4.0 * N * T * ti
     achieved_tflops = flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None
     peak = PEAK_BF16_MFMA_TFLOPS if bf16 else PEAK_FP32_MFMA_TFLOPS
-    kname = ("k_fused_bf16<128,1> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA)" if bf16
-             else "k_fused_f32<64,2> (GEMM1 + cube + GEMM2, FP32 MFMA)")
+    np_ = ((N + 31) // 32) * 32
+    wk_ = 2 if np_ <= 64 else 1
+    kname = (f"k_fused_bf16<{np_},{wk_}> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA)"
+             if bf16 else f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA)")
     last = runs[-1]
     out = {
         "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",
@@ -183,7 +202,8 @@ def main():
         "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "T": T, "K": K, "tol": 1e-6,
-                   "max_iter": 1000, "precision": precision, "seed": 3 if bf16 else 1,
+                   "max_iter": 1000, "precision": precision,
+                   "seed": {"eeg_shaped_n64": 1, "precision_n128": 3, "pruner_n64": 5300}[args.workload],
                    "passes": last["fp"]["passes"], "thread_iters_per_step": last["fp"]["thread_iters"],
                    "fp32_thread_iters_per_step": last["fp"]["refine_thread_iters"],
                    "n_unique": last["n_unique"], "n_accepted": last["n_accepted"],
@@ -202,6 +222,39 @@ def main():
             "update_share_of_step": (upd_ms / args.steps) / ms_per_step if ms_per_step else None,
         },
     }
+    # the comparison runs (outside the timed region): the same workload in the
+    # other form(s), same data and start vectors
+    def compare(name, **kw):
+        oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, **kw)   # warm-up
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            r = oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - c0) * 1e3 / reps
+        n = min(r["n_accepted"], last["n_accepted"])
+        Ua = last["U"].cpu().numpy()[:n] @ last["V"].cpu().numpy()
+        Ub = r["U"].cpu().numpy()[:n] @ r["V"].cpu().numpy()
+        Ua /= np.linalg.norm(Ua, axis=1, keepdims=True)
+        Ub /= np.linalg.norm(Ub, axis=1, keepdims=True)
+        cos = np.abs(Ua @ Ub.T).max(axis=1) if n else np.zeros(0)
+        return {"form": name, "time_to_unique_ms": ms, "thread_iters": r["fp"]["thread_iters"],
+                "fp32_thread_iters": r["fp"]["refine_thread_iters"], "n_accepted": r["n_accepted"],
+                "same_accepted_count": r["n_accepted"] == last["n_accepted"],
+                "min_abs_cos_vs_timed": float(cos.min()) if n else None,
+                "pruned": r["fp"].get("pruned", 0)}
+    if args.workload == "eeg_shaped_n64":
+        mp = compare("bf16 + fp32 finish (mixed precision)", precision="bf16", tol_bf16=1e-5)
+        mp["speedup_vs_plain_fp32"] = ms_per_step / mp["time_to_unique_ms"]
+        out["mixed_precision"] = mp
+    elif args.workload == "pruner_n64":
+        pf = compare("plain fp32", precision="f32")
+        ub = compare("bf16 without pruner", precision="bf16", tol_bf16=1e-5)
+        out["plain_fp32"] = pf
+        out["bf16_unpruned"] = ub
+        out["speedup_vs_plain_fp32"] = pf["time_to_unique_ms"] / ms_per_step
+        out["pruner_thread_iter_saving"] = 1.0 - (ti / args.steps) / ub["thread_iters"]
     if not args.no_cpu_baseline and not bf16:
         cb = cpu_baseline(prob, args.cpu_rows, args.cpu_passes)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
