@@ -45,8 +45,9 @@ HBM_PROFILE = os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_co
 
 def counted_traffic():
     """HBM bytes per launch of the fused update from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source has
-    changed since those counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel's sources (the
+    listed files, hashed in order as one byte string) have changed since those
+    counters were taken."""
     import hashlib
     try:
         fields = {}
@@ -54,8 +55,10 @@ def counted_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        src = os.path.join(ROOT, fields["source_file"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["source_sha256"]:
+        h = hashlib.sha256()
+        for name in fields["source_files"].split(","):
+            h.update(open(os.path.join(ROOT, name.strip()), "rb").read())
+        if h.hexdigest() != fields["source_sha256"]:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -73,6 +76,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=4096,
                     help="start rows in the CPU-oracle sample")
     ap.add_argument("--cpu-passes", type=int, default=5)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison runs of the other precision forms (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -244,7 +249,9 @@ def main():
                 "same_accepted_count": r["n_accepted"] == last["n_accepted"],
                 "min_abs_cos_vs_timed": float(cos.min()) if n else None,
                 "pruned": r["fp"].get("pruned", 0)}
-    if args.workload == "eeg_shaped_n64":
+    if args.no_compare:
+        pass
+    elif args.workload == "eeg_shaped_n64":
         mp = compare("bf16 + fp32 finish (mixed precision)", precision="bf16", tol_bf16=1e-5)
         mp["speedup_vs_plain_fp32"] = ms_per_step / mp["time_to_unique_ms"]
         out["mixed_precision"] = mp

@@ -804,7 +804,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
           HIP_TRY(ctx, launch_batch_plan(ctx->stream, ddesc, D, bctl, item_start, red_start, epi_start,
                                          0, true));
           HIP_TRY(ctx, hipEventRecord(ctx->events[0], ctx->stream));
-          HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, 0, c[2]));
+          HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, 0, c[2], bf16));
           HIP_TRY(ctx, hipEventRecord(ctx->events[1], ctx->stream));
           HIP_TRY(ctx, hipEventSynchronize(ctx->events[1]));
           float ms = 0.f;
@@ -832,8 +832,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
 
   // ---- passes -----------------------------------------------------------------
   std::vector<char> ctl_host((size_t)D * 256 * 2);
-  auto run = [&](int max_passes, double tol, int exit_below, int stall_polls, int *launched,
-                 double *kernel_ms) -> int {
+  auto run = [&](int max_passes, double tol, int exit_below, int stall_polls, bool data_bf16,
+                 int *launched, double *kernel_ms) -> int {
     long long kmax = ktot;
     int stalled = 0;
     *launched = 0;
@@ -849,7 +849,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
         }
         HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass], ctx->stream));
       }
-      HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, pass, grid));
+      HIP_TRY(ctx, launch_fused_batched(ctx->stream, ddesc, D, bctl, item_start, pass, grid,
+                                        data_bf16));
       if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
       HIP_TRY(ctx, launch_epilogue_batched(ctx->stream, ddesc, D, bctl, red_start, epi_start, pass,
                                            tol, (int)kmax));
@@ -879,7 +880,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   int launched = 0;
   double kernel_ms = 0.0;
   rc = run(params->max_iter, bf16 ? params->tol_bf16 : params->tol,
-           bf16 ? (int)std::max<long long>(ktot / 64, 1) : 0, bf16 ? 2 : 0, &launched, &kernel_ms);
+           bf16 ? (int)std::max<long long>(ktot / 64, 1) : 0, bf16 ? 2 : 0, bf16, &launched,
+           &kernel_ms);
   if (rc) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data(), hd[0].ctl, (size_t)D * 256, hipMemcpyDeviceToHost,
                               ctx->stream));
@@ -914,7 +916,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     int l2 = 0;
     double ms2 = 0.0;
     if (passes32 > 0) {
-      rc = run(passes32, params->tol, 0, 0, &l2, &ms2);
+      rc = run(passes32, params->tol, 0, 0, false, &l2, &ms2);
       if (rc) return rc;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data() + (size_t)D * 256, ctl_base + (size_t)D * 256,

@@ -100,6 +100,23 @@ __device__ inline int find_dataset(const I *start, int D, I x) {
   return lo;
 }
 
+// Persistent pass kernel of one data type (every dataset of a call uses the
+// same one): work-groups pull (dataset, row block, sample split) items from the
+// pass's atomic queue until it is empty.
+// Each variant is its own (not inlined) function, so each gets the register
+// budget of its single-dataset kernel instead of the union of all variants.
+// FP32 items run without the next-tile register prefetch, which spills under
+// the call convention's reserved registers at NP = 64, WK = 2.
+template <int NP, int WK>
+__device__ __noinline__ void call_f32(const ItemCtx &c, int kb, int sp, float *xs) {
+  item_f32<NP, WK, false, false>(c, kb, sp, xs);
+}
+template <int NP, int WK>
+__device__ __noinline__ void call_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs, __bf16 *xt) {
+  item_bf16<NP, WK>(c, kb, sp, xs, xt);
+}
+
+template <bool BF16>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc *__restrict__ descs,
                                                                  int D, BatchCtl *bctl,
                                                                  const int *__restrict__ item_start,
@@ -123,23 +140,29 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
     const int kb = local % n_kb, sp = local / n_kb;
     const ItemCtx c{b.X, b.N, b.T, b.n_sub, b.n_sp, n_kb * b.kwg, b.B,
                     (pass & 1) ? b.act1 : b.act0, kact, b.gpart, b.s4part, nullptr};
-    float *xs32 = reinterpret_cast<float *>(buf);
-    __bf16 *xs16 = reinterpret_cast<__bf16 *>(buf);
-    __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 18432);
-    switch (b.variant) {
-      case 0: item_f32<32, 1, false>(c, kb, sp, xs32); break;
-      case 1: item_f32<32, 2, false>(c, kb, sp, xs32); break;
-      case 2: item_f32<64, 1, false>(c, kb, sp, xs32); break;
-      case 3: item_f32<64, 2, false>(c, kb, sp, xs32); break;
-      case 4: item_f32<96, 1, false>(c, kb, sp, xs32); break;
-      case 6: item_f32<128, 1, false>(c, kb, sp, xs32); break;
-      case 8: item_bf16<32, 1>(c, kb, sp, xs16, xt16); break;
-      case 9: item_bf16<32, 2>(c, kb, sp, xs16, xt16); break;
-      case 10: item_bf16<64, 1>(c, kb, sp, xs16, xt16); break;
-      case 11: item_bf16<64, 2>(c, kb, sp, xs16, xt16); break;
-      case 12: item_bf16<96, 1>(c, kb, sp, xs16, xt16); break;
-      case 14: item_bf16<128, 1>(c, kb, sp, xs16, xt16); break;
-      default: break;
+    if constexpr (!BF16) {
+      float *xs32 = reinterpret_cast<float *>(buf);
+      switch (b.variant) {
+        case 0: call_f32<32, 1>(c, kb, sp, xs32); break;
+        case 1: call_f32<32, 2>(c, kb, sp, xs32); break;
+        case 2: call_f32<64, 1>(c, kb, sp, xs32); break;
+        case 3: call_f32<64, 2>(c, kb, sp, xs32); break;
+        case 4: call_f32<96, 1>(c, kb, sp, xs32); break;
+        case 6: call_f32<128, 1>(c, kb, sp, xs32); break;
+        default: break;
+      }
+    } else {
+      __bf16 *xs16 = reinterpret_cast<__bf16 *>(buf);
+      __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 18432);
+      switch (b.variant) {
+        case 8: call_bf16<32, 1>(c, kb, sp, xs16, xt16); break;
+        case 9: call_bf16<32, 2>(c, kb, sp, xs16, xt16); break;
+        case 10: call_bf16<64, 1>(c, kb, sp, xs16, xt16); break;
+        case 11: call_bf16<64, 2>(c, kb, sp, xs16, xt16); break;
+        case 12: call_bf16<96, 1>(c, kb, sp, xs16, xt16); break;
+        case 14: call_bf16<128, 1>(c, kb, sp, xs16, xt16); break;
+        default: break;
+      }
     }
   }
 }
@@ -247,9 +270,13 @@ hipError_t launch_batch_plan(hipStream_t st, const BatchDesc *descs, int D, Batc
 }
 
 hipError_t launch_fused_batched(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
-                                const int *item_start, int pass, int grid) {
-  hipLaunchKernelGGL(k_fused_batched, dim3(grid), dim3(WAVES * 64), 0, st, descs, D, bctl,
-                     item_start, pass);
+                                const int *item_start, int pass, int grid, bool bf16) {
+  if (bf16)
+    hipLaunchKernelGGL(k_fused_batched<true>, dim3(grid), dim3(WAVES * 64), 0, st, descs, D, bctl,
+                       item_start, pass);
+  else
+    hipLaunchKernelGGL(k_fused_batched<false>, dim3(grid), dim3(WAVES * 64), 0, st, descs, D, bctl,
+                       item_start, pass);
   return hipGetLastError();
 }
 

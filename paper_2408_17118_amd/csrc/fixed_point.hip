@@ -62,7 +62,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
     int kact_host, float *__restrict__ gpart, float *__restrict__ s4part,
     double *__restrict__ s4part64, FpControl *ctl, int pass) {
   constexpr int KWG = WAVES * WK * 32;
-  __shared__ float xs[NP * SX];
+  __shared__ float xs[NP * TileF32<NP>::sx];
 
   const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
   if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {

@@ -20,8 +20,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WAVES = WAVES_PER_WG;  // waves per work-group
-constexpr int TT = 64;          // samples per LDS tile (two 32-sample sub-tiles)
-constexpr int SX = TT + 1;      // LDS row stride in floats; odd, so column reads hit 32 banks
+// FP32 X tile in LDS: tt samples (32-sample sub-tiles) x NP features with an
+// odd row stride, so column reads hit distinct banks.  The widest variant
+// uses 32-sample tiles to leave registers for the one-tile-ahead prefetch.
+template <int NP> struct TileF32 {
+  static constexpr int tt = NP <= 96 ? 64 : 32;
+  static constexpr int sx = tt + 1;
+};
 constexpr int MIN_SUB = 8;      // each sample split covers >= 8 sub-tiles (256 samples)
 constexpr int GRID = 1024;      // work-groups per fused launch (multiple of 8)
 constexpr int SPLIT_GROUP = SPLIT_GROUP_HOST;  // splits per first-stage reduction item
@@ -48,11 +53,15 @@ struct ItemCtx {
 // over the samples of split sp.
 //   KURT = false: writes partial G (NP floats per row) and partial sum z^4.
 //   KURT = true : skips GEMM2 and writes partial sum z^4 in FP64.
+//   PF = true   : prefetches the next X tile into registers during the MFMA
+//                 work of the current one (PF = false: load, stage, compute).
 // ---------------------------------------------------------------------------
-template <int NP, int WK, bool KURT>
+template <int NP, int WK, bool KURT, bool PF = true>
 __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float *xs) {
   constexpr int KWG = WAVES * WK * 32;
   constexpr int HALF = NP / 2;
+  constexpr int TT = TileF32<NP>::tt;
+  constexpr int SX = TileF32<NP>::sx;
   const float *__restrict__ X = (const float *)c.X;
   const int N = c.N;
   const long long T = c.T;
@@ -103,15 +112,42 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
       for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
     }
 
+    // X tiles go through registers (4 consecutive samples of one feature row
+    // per load); with PF they are fetched one tile ahead, so the global-load
+    // latency of tile i+1 overlaps the MFMA work of tile i.
+    constexpr int F4 = NP * TT / 4 / (WAVES * 64);
+    const bool vec4 = (T % 4) == 0;
+    f32x4 pre[F4];
+    auto fetch = [&](long long mt) {
+#pragma unroll
+      for (int q = 0; q < F4; ++q) {
+        const int e = tid + q * WAVES * 64;
+        const int n = e / (TT / 4);
+        const long long gm = mt + (e % (TT / 4)) * 4;
+        const float *src = X + (size_t)n * (size_t)T + (size_t)gm;
+        if (n < N && vec4 && gm + 4 <= t_end) {
+          pre[q] = *reinterpret_cast<const f32x4 *>(src);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pre[q][j] = (n < N && gm + j < t_end) ? src[j] : 0.f;
+        }
+      }
+    };
+    if constexpr (PF) fetch(t_begin);
     for (long long m_tile = t_begin; m_tile < t_end; m_tile += TT) {
       __syncthreads();
-      for (int e = tid; e < NP * TT; e += WAVES * 64) {
-        const int n = e / TT;
-        const int m = e % TT;
-        const long long gm = m_tile + m;
-        xs[n * SX + m] = (n < N && gm < t_end) ? X[(size_t)n * (size_t)T + (size_t)gm] : 0.f;
+      if constexpr (!PF) fetch(m_tile);
+#pragma unroll
+      for (int q = 0; q < F4; ++q) {
+        const int e = tid + q * WAVES * 64;
+        const int n = e / (TT / 4);
+        const int m4 = (e % (TT / 4)) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[n * SX + m4 + j] = pre[q][j];
       }
       __syncthreads();
+      if constexpr (PF)
+        if (m_tile + TT < t_end) fetch(m_tile + TT);
 #pragma unroll
       for (int sub = 0; sub < TT / 32; ++sub) {
         if (m_tile + sub * 32 >= t_end) break;
@@ -213,7 +249,7 @@ constexpr int BT = 64;          // samples per LDS tile
 constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
 template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
 
-template <int NP, int WK>
+template <int NP, int WK, bool PF = true>
 __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs,
                                           __bf16 *xt) {
   constexpr int KWG = WAVES * WK * 32;
@@ -270,27 +306,41 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
     }
 
-    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT) {
-      __syncthreads();
-      // fill: 8 consecutive samples of one feature row per thread-iteration
-      for (int e = tid; e < NP * (BT / 8); e += WAVES * 64) {
+    // X tiles go through registers (8 consecutive samples of one feature row
+    // per load; one tile ahead with PF) and are staged into both LDS layouts.
+    constexpr int F8 = NP * BT / 8 / (WAVES * 64);
+    bf16x8 pre[F8];
+    auto fetch = [&](long long mt) {
+#pragma unroll
+      for (int q = 0; q < F8; ++q) {
+        const int e = tid + q * WAVES * 64;
         const int n = e / (BT / 8);
-        const int mc = (e % (BT / 8)) * 8;
-        const long long gm = m_tile + mc;
-        bf16x8 v;
+        const long long gm = mt + (e % (BT / 8)) * 8;
+        const __bf16 *src = X + (size_t)n * (size_t)T + (size_t)gm;
         if (n < N && vec_ok && gm + 8 <= t_end) {
-          v = *reinterpret_cast<const bf16x8 *>(X + (size_t)n * (size_t)T + (size_t)gm);
+          pre[q] = *reinterpret_cast<const bf16x8 *>(src);
         } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j)
-            v[j] = (n < N && gm + j < t_end) ? X[(size_t)n * (size_t)T + (size_t)(gm + j)]
-                                             : (__bf16)0.f;
+          for (int j = 0; j < 8; ++j) pre[q][j] = (n < N && gm + j < t_end) ? src[j] : (__bf16)0.f;
         }
-        *reinterpret_cast<bf16x8 *>(&xs[n * BSX + mc]) = v;
+      }
+    };
+    if constexpr (PF) fetch(t_begin);
+    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT) {
+      __syncthreads();
+      if constexpr (!PF) fetch(m_tile);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xt[(mc + j) * XTS + n] = v[j];
+      for (int q = 0; q < F8; ++q) {
+        const int e = tid + q * WAVES * 64;
+        const int n = e / (BT / 8);
+        const int mc = (e % (BT / 8)) * 8;
+        *reinterpret_cast<bf16x8 *>(&xs[n * BSX + mc]) = pre[q];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xt[(mc + j) * XTS + n] = pre[q][j];
       }
       __syncthreads();
+      if constexpr (PF)
+        if (m_tile + BT < t_end) fetch(m_tile + BT);
 #pragma unroll
       for (int sub = 0; sub < BT / 32; ++sub) {
         if (m_tile + sub * 32 >= t_end) break;

@@ -127,7 +127,7 @@ hipError_t launch_batch_plan(hipStream_t st, const BatchDesc *descs, int D, Batc
                              int *item_start, long long *red_start, int *epi_start, int pass,
                              bool dry);
 hipError_t launch_fused_batched(hipStream_t st, const BatchDesc *descs, int D, BatchCtl *bctl,
-                                const int *item_start, int pass, int grid);
+                                const int *item_start, int pass, int grid, bool bf16);
 hipError_t launch_epilogue_batched(hipStream_t st, const BatchDesc *descs, int D,
                                    const BatchCtl *bctl, const long long *red_start,
                                    const int *epi_start, int pass, double tol, int kmax_total);
