@@ -69,7 +69,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="eeg_shaped_n64",
-                    choices=["eeg_shaped_n64", "precision_n128", "pruner_n64"])
+                    choices=["eeg_shaped_n64", "precision_n128", "pruner_n64", "batched_n16_128"])
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -135,6 +135,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "batched_n16_128":
+        return bench_batched(args)
     dev = torch.device("cuda", 0)
     bf16 = args.workload in ("precision_n128", "pruner_n64")
     if args.workload == "precision_n128":
@@ -265,6 +267,111 @@ def main():
     if not args.no_cpu_baseline and not bf16:
         cb = cpu_baseline(prob, args.cpu_rows, args.cpu_passes)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    ctx.close()
+    print(json.dumps(out))
+    return 0
+
+
+def bench_batched(args):
+    """Many-dataset workload: 64 datasets (N uniform over 16..128 in steps of 8,
+    T log-uniform in [2e4, 5e5], K = 1024 each), raw data resident on the GPU.
+    A step is whitening of every dataset, one batched fixed point (BF16 data,
+    FP32 finish) and the unique set of every dataset.  Compared with the same
+    datasets run one call at a time, and with the batched FP32 form."""
+    import torch
+
+    from paper_2408_17118_amd import oica, synth
+    dev = torch.device("cuda", 0)
+    Xs, W0s, NT = [], [], []
+    for N, T, rng in synth.batched_shapes():
+        p = synth.batched_problem(N, T, rng)
+        Xs.append(torch.from_numpy(p.X).to(dev))
+        W0s.append(torch.from_numpy(p.W0.astype(np.float32)).to(dev))
+        NT.append((N, T))
+        del p
+        if len(Xs) % 16 == 0:
+            print(f"generated {len(Xs)} datasets", file=sys.stderr, flush=True)
+    ctx = oica.Context(0)
+    kw = dict(tol=1e-6, max_iter=1000, tau=1e-3, precision="bf16", tol_bf16=1e-5, refine_iters=5)
+
+    def step(profile=False, **over):
+        return oica.ordering_ica_batched(ctx, Xs, W0s, profile=profile, **{**kw, **over})
+
+    for i in range(args.warmup):
+        res, st = step()
+        print(f"warmup {i}: {st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(profile=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ti = sum(st["thread_iters"] + st["refine_thread_iters"] for _, st in runs)
+    upd_ms = sum(st["update_ms"] for _, st in runs)
+    flops = sum(st["update_flops"] for _, st in runs)
+    launches = sum(st["update_launches"] for _, st in runs)
+    achieved = flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None
+    last, lst = runs[-1]
+    accepted = [r["n_accepted"] for r in last]
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - c0) * 1e3 / reps, out
+
+    def seq():
+        return [oica.ordering_ica(ctx, X, W0, **kw) for X, W0 in zip(Xs, W0s)]
+    seq_ms, seq_res = timed(seq)
+    f32_ms, (f32_res, f32_st) = timed(lambda: step(precision="f32"))
+    out = {
+        "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",
+        "value": ti / (t1 - t0),
+        "unit": "thread-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "batched_n16_128", "datasets": len(Xs), "K_each": 1024,
+                   "sum_NT": int(sum(n * t for n, t in NT)), "tol": 1e-6, "max_iter": 1000,
+                   "precision": "bf16", "seed": 4, "passes": lst["passes"],
+                   "thread_iters_per_step": lst["thread_iters"],
+                   "fp32_thread_iters_per_step": lst["refine_thread_iters"],
+                   "grid": lst["grid"], "wk32": lst["wk32"], "wk64": lst["wk64"],
+                   "n_accepted_total": int(sum(accepted)), "time_to_unique_ms": ms_per_step},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_fused_batched<bf16> (persistent; GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA)",
+            "achieved": achieved,
+            "peak": PEAK_BF16_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_MFMA_TFLOPS if achieved else None,
+            "traffic": None,
+            "avg_launch_ms": upd_ms / launches if launches else None,
+            "update_share_of_step": (upd_ms / args.steps) / ms_per_step,
+        },
+        "one_call_per_dataset": {
+            "form": "bf16 + fp32 finish, one ordering_ica call per dataset",
+            "time_to_unique_ms": seq_ms,
+            "speedup_of_batched": seq_ms / ms_per_step,
+            "n_accepted_total": int(sum(r["n_accepted"] for r in seq_res)),
+        },
+        "batched_fp32": {
+            "form": "batched, fp32 data",
+            "time_to_unique_ms": f32_ms,
+            "thread_iters": f32_st["thread_iters"],
+            "n_accepted_total": int(sum(r["n_accepted"] for r in f32_res)),
+            "speedup_of_bf16": f32_ms / ms_per_step,
+        },
+    }
     ctx.close()
     print(json.dumps(out))
     return 0

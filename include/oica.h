@@ -105,6 +105,30 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
                 void *Xw, oica_dtype out_t, float *Xw_f32,
                 double *V, double *mean, double *eigval);
 
+/* Batched whitening: D problems, each exactly as in oica_whiten (same outputs,
+ * same arithmetic), with every covariance eigenproblem solved in one launch
+ * (one work-group per problem) instead of D.  The statistics and apply passes
+ * run problem after problem on the stream.
+ *
+ * problems: host array of D (1..1024) descriptors; every pointer in it is a
+ * device pointer as in oica_whiten.  out_t applies to every problem.  status
+ * is written for every problem: OICA_OK, OICA_E_NONFINITE or OICA_E_RANK.
+ * Synchronises.  Returns OICA_OK if every problem succeeded, else the first
+ * failing problem's code (argument errors before any device work, naming the
+ * problem index in oica_last_error). */
+typedef struct {
+  int N;
+  int64_t T;
+  const void *X_raw;
+  oica_dtype raw_t;
+  void *Xw;
+  float *Xw_f32;        /* nullable */
+  double *V, *mean, *eigval;  /* nullable */
+  int status;           /* out */
+} oica_whiten_problem;
+
+int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oica_dtype out_t);
+
 /* ---------------------------------------------------------------------------
  * The batched kurtosis fixed point with removal of converged rows (Sec. 3.1,
  * eqs. 4-5 in the order of Algorithm 2, and Sec. 3.2), followed by the
@@ -279,6 +303,8 @@ typedef struct {          /* host */
   int grid;               /* work-groups of the persistent kernel           */
   int wk32, wk64;         /* rows-per-wave choice for padded N 32 and 64    */
   int tuned;              /* 1: chosen by timing in this call; 2: from cache */
+  double update_flops;    /* algorithmic flops of the main-loop passes:
+                             sum over problems of 4 N T thread_iters        */
 } oica_batch_stats;
 
 /* D in [1, 1024].  params as for oica_fixed_point (traj_iters must be 0;

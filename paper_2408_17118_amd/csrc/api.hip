@@ -176,6 +176,52 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
   return OICA_OK;
 }
 
+int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oica_dtype out_t) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  if (D < 1 || D > 1024) return fail(ctx, OICA_E_ARG, "D must be in [1, 1024]");
+  if (!problems) return fail(ctx, OICA_E_ARG, "problems must be non-null");
+  if (out_t != OICA_F32 && out_t != OICA_BF16)
+    return fail(ctx, OICA_E_UNSUPPORTED, "out_t must be OICA_F32 or OICA_BF16");
+  std::vector<oica::WhitenJob> jobs(D);
+  for (int d = 0; d < D; ++d) {
+    oica_whiten_problem &q = problems[d];
+    q.status = OICA_OK;
+    int rc = check_dims(ctx, q.N, q.T);
+    if (rc) {
+      const std::string why = ctx->err;
+      return fail(ctx, rc, "problem %d: %s", d, why.c_str());
+    }
+    if (!q.X_raw || !q.Xw) return fail(ctx, OICA_E_ARG, "problem %d: X_raw and Xw must be non-null", d);
+    if (q.raw_t != OICA_F64 && q.raw_t != OICA_F32)
+      return fail(ctx, OICA_E_UNSUPPORTED, "problem %d: raw_t must be OICA_F64 or OICA_F32", d);
+    jobs[d] = oica::WhitenJob{q.N, q.T, q.X_raw, q.raw_t, q.Xw, out_t, q.Xw_f32, q.V, q.mean, q.eigval};
+  }
+  const size_t main_bytes = whiten_batched_workspace_bytes(D, jobs.data());
+  int rc = ensure_ws(ctx, main_bytes + (size_t)D * sizeof(int) + 256);
+  if (rc) return rc;
+  int *flags = (int *)((char *)ctx->ws + ((main_bytes + 255) & ~(size_t)255));
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(flags, 0, (size_t)D * sizeof(int), ctx->stream));
+  HIP_TRY(ctx, launch_whiten_batched(ctx->stream, D, jobs.data(), ctx->ws, flags));
+  std::vector<int> hf(D);
+  HIP_TRY(ctx, hipMemcpyAsync(hf.data(), flags, (size_t)D * sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  int first = OICA_OK;
+  for (int d = 0; d < D; ++d) {
+    const int st = (hf[d] & 1) ? OICA_E_NONFINITE : (hf[d] & 2) ? OICA_E_RANK : OICA_OK;
+    problems[d].status = st;
+    if (st != OICA_OK && first == OICA_OK) {
+      first = st;
+      fail(ctx, st, "problem %d: %s", d,
+           st == OICA_E_NONFINITE ? "X_raw contains NaN or Inf"
+                                  : "covariance is rank deficient (eigenvalue ratio <= 1e-12)");
+    }
+  }
+  return first;
+}
+
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -887,10 +933,12 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
                               ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   long long main_ti = 0, refine_ti = 0;
+  double main_flops = 0.0;
   int main_passes = 0;
   for (int d = 0; d < D; ++d) {
     const FpControl *c = (const FpControl *)(ctl_host.data() + (size_t)d * 256);
     main_ti += c->thread_iters;
+    main_flops += 4.0 * pr[d].N * (double)pr[d].T * (double)c->thread_iters;
     main_passes = std::max(main_passes, c->passes);
   }
   if (bf16) {
@@ -943,6 +991,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     stats->wk32 = wk32;
     stats->wk64 = wk64;
     stats->tuned = tuned;
+    stats->update_flops = main_flops;
   }
   return OICA_OK;
 }

@@ -83,6 +83,30 @@ struct BatchCtl {
 // ---- launchers (defined next to their kernels) ----------------------------
 
 // whiten.hip
+struct JacJob {        // one symmetric eigenproblem of the Jacobi solver
+  int N;
+  const double *C;     // N x N, symmetric
+  double *E;           // out: N x N eigenvectors (column j = vector j), then N eigenvalues
+  double2 *rot;        // rotation log (c, s), jacobi_log_entries(N)
+  int *pq;             // rotation log p | q << 16 (q = 0xFFFF: padding index)
+  int *sweeps;         // out: sweeps that rotated
+};
+size_t jacobi_log_entries(int N);
+struct WhitenJob {     // one problem of the batched whitening
+  int N;
+  int64_t T;
+  const void *X;
+  oica_dtype raw_t;
+  void *Xw;
+  oica_dtype out_t;
+  float *Xw_f32;
+  double *V, *mean, *eig;  // nullable outputs
+};
+size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs);
+hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, void *ws,
+                                 int *flags_dev);
+hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
+                         int n_max);
 hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t,
                          void *Xw, oica_dtype out_t, float *Xw_f32, double *V_out,
                          double *mean_out, double *eig_out, void *ws, size_t ws_bytes,

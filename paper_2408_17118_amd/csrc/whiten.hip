@@ -4,8 +4,9 @@
 //
 //   k_mean_part / k_mean_final   mu = X 1 / T          (two-level, fixed order)
 //   k_cov_part  / k_cov_final    C = Xc Xc^T / T       (split over T, fixed order)
-//   k_jacobi                     C = E D E^T            (cyclic Jacobi, one work-group,
-//                                                        C in LDS, E in LDS when it fits)
+//   k_jacobi_values / _vectors   C = E D E^T            (cyclic Jacobi: eigenvalues in one
+//                                                        work-group with A in LDS, then E
+//                                                        from the logged rotations)
 //   k_canon                      descending order, sign rule, rank check,
 //                                Wh = D^(-1/2) E^T
 //   k_apply                      Xw = Wh (X - mu)       (FP64 tiles; FP32 / BF16 out)
@@ -13,6 +14,9 @@
 #include "oica_internal.h"
 
 #include <math.h>
+
+#include <algorithm>
+#include <vector>
 
 namespace oica {
 
@@ -148,49 +152,68 @@ __global__ void k_cov_final(int N, long long T, int chunks, const double *__rest
 }
 
 // Cyclic Jacobi with round-robin pairing: each round applies N/2 disjoint
-// rotations at once (rows first, then columns), a sweep is N-1 rounds
-// (N rounded up to even; the padding index is never rotated).  A rotation is
-// applied only while |a_pq| exceeds both N eps sqrt(|a_pp a_qq|) and
-// eps max_i |a_ii| (the rounding floor that rotations themselves leave in every
-// element, the absolute accuracy a dense symmetric eigensolver reaches); a
-// sweep without rotations ends the solve.
-// A lives in LDS; the accumulated rotations E live in LDS too when both fit
-// (E_LDS), else in global memory.
+// rotations at once, a sweep is N-1 rounds (N rounded up to even; the padding
+// index is never rotated).  A rotation is applied only while |a_pq| exceeds
+// both N eps sqrt(|a_pp a_qq|) and eps max_i |a_ii| (the rounding floor that
+// rotations themselves leave in every element, the absolute accuracy a dense
+// symmetric eigensolver reaches); a sweep without rotations ends the solve.
+//
+// Two kernels:
+//   k_jacobi_values   one work-group per matrix; the upper triangle of A in
+//                     LDS.  Rotations of one round act on disjoint index pairs,
+//                     so A <- J^T A J splits into independent 2 x 2 blocks
+//                     (pair k rows, pair l columns): each block is updated in
+//                     one step from the round's (c, s), and only blocks with
+//                     k <= l are touched (A stays symmetric).  Two barriers per
+//                     round.  Every round's rotations are appended to a log.
+//   k_jacobi_vectors  E = product of the logged rotations.  Rows of E evolve
+//                     independently (E <- E J acts on columns p, q of each row),
+//                     so work-groups own row blocks of E in LDS and replay the
+//                     log round by round.
+// Several matrices (the batched whitening) run in one launch, one job each.
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAX_SWEEPS = 30;
 constexpr double JAC_EPS = 2.220446049250313e-16;
+constexpr int JV_ROWS = 8;       // rows of E per work-group
+constexpr int JV_THREADS = 256;
+constexpr int JV_CHUNK = 32;     // logged rounds staged in LDS at a time
 
-template <bool E_LDS>
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__restrict__ C,
-                                                         double *__restrict__ Eg,
-                                                         int *__restrict__ sweeps_out) {
+size_t jacobi_log_entries(int N) {
+  const int ne = N + (N & 1);
+  return (size_t)JAC_MAX_SWEEPS * (size_t)(ne > 1 ? ne - 1 : 1) * (size_t)(ne / 2 > 0 ? ne / 2 : 1);
+}
+
+__device__ inline int jac_sym(int i, int j, int LD) { return i <= j ? i * LD + j : j * LD + i; }
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__restrict__ jobs,
+                                                               JacJob one) {
   extern __shared__ double jac_smem[];
   __shared__ double rc[NMAX / 2], rs[NMAX / 2];
   __shared__ int rp[NMAX / 2], rq[NMAX / 2];
   __shared__ int rotated;
+  __shared__ double dscale;
+  const JacJob jb = jobs ? jobs[blockIdx.x] : one;
+  const int N = jb.N;
   const int LD = N + 1;
   double *a = jac_smem;
-  double *E = E_LDS ? jac_smem + N * LD : Eg;
   const int tid = threadIdx.x;
-  __shared__ double dscale;
   const double thr = JAC_EPS * (double)N;
   for (int e = tid; e < N * N; e += JAC_THREADS) {
     const int i = e / N, j = e % N;
-    a[i * LD + j] = C[e];
-    E[e] = (i == j) ? 1.0 : 0.0;
+    if (i <= j) a[i * LD + j] = jb.C[e];
   }
   if (tid == 0) {
     double m = 0.0;
-    for (int i = 0; i < N; ++i) m = fmax(m, fabs(C[i * N + i]));
+    for (int i = 0; i < N; ++i) m = fmax(m, fabs(jb.C[i * N + i]));
     dscale = JAC_EPS * m;
   }
   __syncthreads();
-  // element loops: thread (k = tid / 16, jj = tid % 16) owns pair k, columns jj, jj+16, ...
-  const int tk = tid / 16, tj = tid % 16;
   const int ne = N + (N & 1);
   const int npair = ne / 2;
+  const int H = npair / 2;
+  const int units = npair * (H + 1);
   int sweep = 0;
-  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+  for (; sweep < JAC_MAX_SWEEPS && ne > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < ne - 1; ++r) {
@@ -200,15 +223,17 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__r
           p = ne - 1;
           q = r;
         } else {
-          p = (r + tid) % (ne - 1);
-          q = (r - tid + ne - 1) % (ne - 1);
+          p = r + tid;
+          if (p >= ne - 1) p -= ne - 1;
+          q = r - tid;
+          if (q < 0) q += ne - 1;
         }
         if (p > q) {
           const int t = p;
           p = q;
           q = t;
         }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (q < N) {
           const double apq = a[p * LD + q];
           const double app = a[p * LD + p], aqq = a[q * LD + q];
@@ -220,38 +245,48 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__r
             else
               t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
             rotated = 1;
           }
         }
         rc[tid] = c;
-        rs[tid] = s;
+        rs[tid] = sn;
         rp[tid] = p;
         rq[tid] = q < N ? q : -1;
+        const size_t li = ((size_t)sweep * (ne - 1) + r) * npair + tid;
+        jb.rot[li] = make_double2(c, sn);
+        jb.pq[li] = p | ((q < N ? q : 0xFFFF) << 16);
       }
       __syncthreads();
-      // rows p, q of A  <-  J^T A
-      if (tk < npair && rq[tk] >= 0 && rs[tk] != 0.0) {
-        const int p = rp[tk], q = rq[tk];
-        const double c = rc[tk], s = rs[tk];
-        for (int j = tj; j < N; j += 16) {
-          const double apj = a[p * LD + j], aqj = a[q * LD + j];
-          a[p * LD + j] = c * apj - s * aqj;
-          a[q * LD + j] = s * apj + c * aqj;
-        }
-      }
-      __syncthreads();
-      // columns p, q of A and of E  <-  (.) J
-      if (tk < npair && rq[tk] >= 0 && rs[tk] != 0.0) {
-        const int p = rp[tk], q = rq[tk];
-        const double c = rc[tk], s = rs[tk];
-        for (int i = tj; i < N; i += 16) {
-          const double aip = a[i * LD + p], aiq = a[i * LD + q];
-          a[i * LD + p] = c * aip - s * aiq;
-          a[i * LD + q] = s * aip + c * aiq;
-          const double eip = E[i * N + p], eiq = E[i * N + q];
-          E[i * N + p] = c * eip - s * eiq;
-          E[i * N + q] = s * eip + c * eiq;
+      // block (k, l), l = k + m (mod npair): every unordered pair of index
+      // pairs once (m = H twice when npair is even: keep k < H)
+      for (int u = tid; u < units; u += JAC_THREADS) {
+        const int m = u / npair, k = u - m * npair;
+        if (m == H && !((npair & 1) || k < H)) continue;
+        int l = k + m;
+        if (l >= npair) l -= npair;
+        const double sk = rs[k], sl = rs[l];
+        if (sk == 0.0 && sl == 0.0) continue;
+        const double ck = rc[k], cl = rc[l];
+        const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
+        const double b00 = a[jac_sym(pk, pl, LD)];
+        const double b01 = ql >= 0 ? a[jac_sym(pk, ql, LD)] : 0.0;
+        const double b10 = qk >= 0 ? a[jac_sym(qk, pl, LD)] : 0.0;
+        const double b11 = (qk >= 0 && ql >= 0) ? a[jac_sym(qk, ql, LD)] : 0.0;
+        // rows of pair k, then columns of pair l
+        const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+        const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+        const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
+        const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
+        if (k == l) {  // diagonal block, pk < qk
+          a[pk * LD + pk] = n00;
+          a[pk * LD + qk] = n01;
+          a[qk * LD + qk] = n11;
+        } else {
+          a[jac_sym(pk, pl, LD)] = n00;
+          if (ql >= 0) a[jac_sym(pk, ql, LD)] = n01;
+          if (qk >= 0) a[jac_sym(qk, pl, LD)] = n10;
+          if (qk >= 0 && ql >= 0) a[jac_sym(qk, ql, LD)] = n11;
         }
       }
       __syncthreads();
@@ -259,17 +294,72 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(int N, const double *__r
     if (rotated == 0) break;
     __syncthreads();
   }
-  if (E_LDS)
-    for (int e = tid; e < N * N; e += JAC_THREADS) Eg[e] = E[e];
   // eigenvalues: the diagonal, stored after E
-  for (int i = tid; i < N; i += JAC_THREADS) Eg[N * N + i] = a[i * LD + i];
-  if (tid == 0) sweeps_out[0] = sweep;
+  for (int i = tid; i < N; i += JAC_THREADS) jb.E[N * N + i] = a[i * LD + i];
+  if (tid == 0) jb.sweeps[0] = sweep;  // sweeps that rotated (all logged)
 }
 
-static size_t jacobi_lds_bytes(int N, bool e_lds) {
-  return (size_t)N * (N + 1) * sizeof(double) + (e_lds ? (size_t)N * N * sizeof(double) : 0);
+__global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__restrict__ jobs,
+                                                               JacJob one) {
+  __shared__ double e[JV_ROWS][NMAX + 1];
+  __shared__ double2 cs[JV_CHUNK * (NMAX / 2)];
+  __shared__ int pqs[JV_CHUNK * (NMAX / 2)];
+  const JacJob jb = jobs ? jobs[blockIdx.x] : one;
+  const int N = jb.N;
+  const int row0 = blockIdx.y * JV_ROWS;
+  if (row0 >= N) return;  // uniform over the work-group
+  const int rows = N - row0 < JV_ROWS ? N - row0 : JV_ROWS;
+  const int tid = threadIdx.x;
+  for (int x = tid; x < rows * N; x += JV_THREADS) {
+    const int i = x / N, j = x % N;
+    e[i][j] = (row0 + i == j) ? 1.0 : 0.0;
+  }
+  const int ne = N + (N & 1);
+  const int npair = ne / 2;
+  const long long rounds = (long long)jb.sweeps[0] * (ne - 1);
+  for (long long r0 = 0; r0 < rounds; r0 += JV_CHUNK) {
+    const int nr = rounds - r0 < JV_CHUNK ? (int)(rounds - r0) : JV_CHUNK;
+    __syncthreads();
+    for (int x = tid; x < nr * npair; x += JV_THREADS) {
+      cs[x] = jb.rot[(size_t)r0 * npair + x];
+      pqs[x] = jb.pq[(size_t)r0 * npair + x];
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      for (int u = tid; u < rows * npair; u += JV_THREADS) {
+        const int i = u / npair, k = u - i * npair;
+        const double2 v = cs[rr * npair + k];
+        if (v.y == 0.0) continue;
+        const int pq = pqs[rr * npair + k];
+        const int p = pq & 0xFFFF, q = pq >> 16;
+        const double x0 = e[i][p], x1 = e[i][q];
+        e[i][p] = v.x * x0 - v.y * x1;
+        e[i][q] = v.y * x0 + v.x * x1;
+      }
+      __syncthreads();
+    }
+  }
+  for (int x = tid; x < rows * N; x += JV_THREADS) {
+    const int i = x / N, j = x % N;
+    jb.E[(size_t)(row0 + i) * N + j] = e[i][j];
+  }
 }
-constexpr size_t LDS_LIMIT = 160 * 1024 - 2048;  // leave room for the static arrays
+
+static size_t jacobi_lds_bytes(int N) { return (size_t)N * (N + 1) * sizeof(double); }
+
+hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
+                         int n_max) {
+  const size_t lds = jacobi_lds_bytes(n_max);
+  // raise the dynamic-LDS cap where the runtime asks for it; a refusal
+  // surfaces as a launch error below
+  (void)hipFuncSetAttribute((const void *)k_jacobi_values,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_jacobi_values, dim3(D), dim3(JAC_THREADS), lds, st, jobs_dev, one);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3(D, (n_max + JV_ROWS - 1) / JV_ROWS), dim3(JV_THREADS),
+                     0, st, jobs_dev, one);
+  return hipGetLastError();
+}
 
 // Sort descending (rank by count, ties by index), sign rule, rank check,
 // whitening matrix Wh = D^(-1/2) E^T.
@@ -400,71 +490,91 @@ __global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N,
   }
 }
 
-size_t whiten_workspace_bytes(int N, int64_t T) {
-  const int ch = n_chunks(T);
-  const int cch = n_cov_chunks(N, T);
-  size_t b = 0;
-  b += (size_t)ch * N * sizeof(double);          // mean partials
-  b += (size_t)cch * N * N * sizeof(double);     // covariance partials
-  b += (size_t)N * N * sizeof(double);           // C
-  b += (size_t)(N * N + N) * sizeof(double);     // E + eigenvalues
-  b += (size_t)N * N * sizeof(double);           // Wh
-  b += (size_t)N * sizeof(double) * 2;           // mean, eig
-  b += 64;                                       // sweeps
-  return b + 1024;
+// Per-problem buffers that live from the statistics to the apply phase.
+struct WhitenBufs {
+  double *C, *E, *Wh, *mean, *eig;
+  int *sweeps;
+  double2 *rot;
+  int *pq;
+};
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// partial sums of the statistics phase (reused problem after problem)
+static size_t stats_scratch_bytes(int N, int64_t T) {
+  return al256((size_t)n_chunks(T) * N * sizeof(double)) +
+         al256((size_t)n_cov_chunks(N, T) * N * N * sizeof(double));
 }
 
-template <typename TIN>
-static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, void *Xw,
-                              oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
-                              double *eig_out, char *ws, int *flags_dev) {
-  const int ch = n_chunks(T);
-  const int cch = n_cov_chunks(N, T);
-  char *p = ws;
+static size_t bufs_bytes(int N) {
+  return al256((size_t)N * N * sizeof(double)) +            // C
+         al256((size_t)(N * N + N) * sizeof(double)) +      // E + eigenvalues
+         3 * al256((size_t)N * N * sizeof(double)) +        // Wh (+ slack for mean, eig)
+         al256(64) +                                        // sweeps
+         al256(jacobi_log_entries(N) * sizeof(double2)) + al256(jacobi_log_entries(N) * sizeof(int));
+}
+
+static WhitenBufs carve_bufs(char *&p, int N, double *V_out, double *mean_out, double *eig_out) {
   auto take = [&](size_t bytes) {
     char *r = p;
-    p += (bytes + 255) & ~(size_t)255;
+    p += al256(bytes);
     return r;
   };
-  double *mpart = (double *)take((size_t)ch * N * sizeof(double));
-  double *cpart = (double *)take((size_t)cch * N * N * sizeof(double));
-  double *C = (double *)take((size_t)N * N * sizeof(double));
-  double *E = (double *)take((size_t)(N * N + N) * sizeof(double));
-  double *Wh = V_out ? V_out : (double *)take((size_t)N * N * sizeof(double));
-  double *mean = mean_out ? mean_out : (double *)take((size_t)N * sizeof(double));
-  double *eig = eig_out ? eig_out : (double *)take((size_t)N * sizeof(double));
-  int *sweeps = (int *)take(64);
+  WhitenBufs b;
+  b.C = (double *)take((size_t)N * N * sizeof(double));
+  b.E = (double *)take((size_t)(N * N + N) * sizeof(double));
+  b.Wh = (double *)take((size_t)N * N * sizeof(double));
+  b.mean = (double *)take((size_t)N * sizeof(double));
+  b.eig = (double *)take((size_t)N * sizeof(double));
+  if (V_out) b.Wh = V_out;
+  if (mean_out) b.mean = mean_out;
+  if (eig_out) b.eig = eig_out;
+  b.sweeps = (int *)take(64);
+  b.rot = (double2 *)take(jacobi_log_entries(N) * sizeof(double2));
+  b.pq = (int *)take(jacobi_log_entries(N) * sizeof(int));
+  return b;
+}
 
+size_t whiten_workspace_bytes(int N, int64_t T) {
+  return stats_scratch_bytes(N, T) + bufs_bytes(N) + 1024;
+}
+
+size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
+  size_t scratch = 0, b = 0;
+  for (int d = 0; d < D; ++d) {
+    scratch = std::max(scratch, stats_scratch_bytes(jobs[d].N, jobs[d].T));
+    b += bufs_bytes(jobs[d].N);
+  }
+  return scratch + b + al256((size_t)D * sizeof(JacJob)) + 1024;
+}
+
+// mean and covariance of one problem into bufs.C / bufs.mean
+template <typename TIN>
+static void stats_phase(hipStream_t st, int N, int64_t T, const TIN *X, char *scratch,
+                        const WhitenBufs &b, int *flags) {
+  const int ch = n_chunks(T);
+  const int cch = n_cov_chunks(N, T);
+  double *mpart = (double *)scratch;
+  double *cpart = (double *)(scratch + al256((size_t)ch * N * sizeof(double)));
   hipLaunchKernelGGL((k_mean_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mpart,
-                     flags_dev);
+                     flags);
   hipLaunchKernelGGL(k_mean_final, dim3((N + 3) / 4), dim3(256), 0, st, N, (long long)T, ch,
-                     mpart, mean);
+                     mpart, b.mean);
   if (N <= 64)
     hipLaunchKernelGGL((k_cov_part<TIN, 4>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
-                       mean, cpart);
+                       b.mean, cpart);
   else
     hipLaunchKernelGGL((k_cov_part<TIN, 8>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
-                       mean, cpart);
+                       b.mean, cpart);
   hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, N, (long long)T, cch,
-                     cpart, C);
-  const bool e_lds = jacobi_lds_bytes(N, true) <= LDS_LIMIT;
-  const size_t lds = jacobi_lds_bytes(N, e_lds);
-  if (e_lds) {
-    // raise the dynamic-LDS cap where the runtime asks for it; a refusal
-    // surfaces as a launch error below
-    (void)hipFuncSetAttribute((const void *)k_jacobi<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(JAC_THREADS), lds, st, N, C, E, sweeps);
-  } else {
-    // raise the dynamic-LDS cap where the runtime asks for it; a refusal
-    // surfaces as a launch error below
-    (void)hipFuncSetAttribute((const void *)k_jacobi<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(JAC_THREADS), lds, st, N, C, E, sweeps);
-  }
-  hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, N, E, Wh, eig, flags_dev);
+                     cpart, b.C);
+}
+
+// canonical order / sign, rank check, Xw = Wh (X - mean)
+template <typename TIN>
+static void apply_phase(hipStream_t st, int N, int64_t T, const TIN *X, void *Xw, oica_dtype out_t,
+                        float *Xw_f32, const WhitenBufs &b, int *flags) {
+  hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, N, b.E, b.Wh, b.eig, flags);
   float *o32 = nullptr, *o32b = nullptr;
   uint16_t *obf = nullptr;
   if (out_t == OICA_F32) {
@@ -474,20 +584,74 @@ static hipError_t whiten_impl(hipStream_t st, int N, int64_t T, const TIN *X, vo
     o32b = Xw_f32;
   }
   dim3 g((unsigned)((T + AP_T - 1) / AP_T), (unsigned)((N + AP_T - 1) / AP_T));
-  hipLaunchKernelGGL((k_apply<TIN>), g, dim3(256), 0, st, X, N, (long long)T, Wh, mean, o32, obf,
-                     o32b);
-  return hipGetLastError();
+  hipLaunchKernelGGL((k_apply<TIN>), g, dim3(256), 0, st, X, N, (long long)T, b.Wh, b.mean, o32,
+                     obf, o32b);
+}
+
+static void stats_any(hipStream_t st, const WhitenJob &j, char *scratch, const WhitenBufs &b,
+                      int *flags) {
+  if (j.raw_t == OICA_F64)
+    stats_phase<double>(st, j.N, j.T, (const double *)j.X, scratch, b, flags);
+  else
+    stats_phase<float>(st, j.N, j.T, (const float *)j.X, scratch, b, flags);
+}
+
+static void apply_any(hipStream_t st, const WhitenJob &j, const WhitenBufs &b, int *flags) {
+  if (j.raw_t == OICA_F64)
+    apply_phase<double>(st, j.N, j.T, (const double *)j.X, j.Xw, j.out_t, j.Xw_f32, b, flags);
+  else
+    apply_phase<float>(st, j.N, j.T, (const float *)j.X, j.Xw, j.out_t, j.Xw_f32, b, flags);
 }
 
 hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, void *Xw,
                          oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
                          double *eig_out, void *ws, size_t ws_bytes, int *flags_dev) {
   (void)ws_bytes;
-  if (raw_t == OICA_F64)
-    return whiten_impl<double>(st, N, T, (const double *)X, Xw, out_t, Xw_f32, V_out, mean_out,
-                               eig_out, (char *)ws, flags_dev);
-  return whiten_impl<float>(st, N, T, (const float *)X, Xw, out_t, Xw_f32, V_out, mean_out, eig_out,
-                            (char *)ws, flags_dev);
+  const WhitenJob j{N, T, X, raw_t, Xw, out_t, Xw_f32, V_out, mean_out, eig_out};
+  char *scratch = (char *)ws;
+  char *p = scratch + stats_scratch_bytes(N, T);
+  const WhitenBufs b = carve_bufs(p, N, V_out, mean_out, eig_out);
+  stats_any(st, j, scratch, b, flags_dev);
+  const JacJob job{N, b.C, b.E, b.rot, b.pq, b.sweeps};
+  hipError_t e = launch_jacobi(st, 1, nullptr, job, N);
+  if (e != hipSuccess) return e;
+  apply_any(st, j, b, flags_dev);
+  return hipGetLastError();
+}
+
+// Many problems: statistics problem after problem (HBM-bound, one reused set
+// of partial buffers), every eigenproblem in one launch of the Jacobi kernels
+// (one work-group each), then the apply phase problem after problem.
+// flags_dev: D ints, zero on entry; the job table is copied to the device
+// first and the stream synchronised, so `jobs` may be freed on return.
+hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, void *ws,
+                                 int *flags_dev) {
+  size_t scratch_bytes = 0;
+  int n_max = 1;
+  for (int d = 0; d < D; ++d) {
+    scratch_bytes = std::max(scratch_bytes, stats_scratch_bytes(jobs[d].N, jobs[d].T));
+    n_max = std::max(n_max, jobs[d].N);
+  }
+  char *scratch = (char *)ws;
+  char *p = scratch + scratch_bytes;
+  JacJob *jobs_dev = (JacJob *)p;
+  p += al256((size_t)D * sizeof(JacJob));
+  std::vector<WhitenBufs> bufs(D);
+  std::vector<JacJob> jj(D);
+  for (int d = 0; d < D; ++d) {
+    bufs[d] = carve_bufs(p, jobs[d].N, jobs[d].V, jobs[d].mean, jobs[d].eig);
+    jj[d] = JacJob{jobs[d].N, bufs[d].C, bufs[d].E, bufs[d].rot, bufs[d].pq, bufs[d].sweeps};
+  }
+  hipError_t e = hipMemcpyAsync(jobs_dev, jj.data(), (size_t)D * sizeof(JacJob),
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (int d = 0; d < D; ++d) stats_any(st, jobs[d], scratch, bufs[d], flags_dev + d);
+  e = launch_jacobi(st, D, jobs_dev, jj[0], n_max);
+  if (e != hipSuccess) return e;
+  for (int d = 0; d < D; ++d) apply_any(st, jobs[d], bufs[d], flags_dev + d);
+  return hipGetLastError();
 }
 
 }  // namespace oica

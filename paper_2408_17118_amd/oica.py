@@ -47,6 +47,12 @@ class FpStats(C.Structure):
                 ("pruned", C.c_int), ("guard_tripped", C.c_int)]
 
 
+class WhitenProblem(C.Structure):
+    _fields_ = [("N", C.c_int), ("T", C.c_int64), ("X_raw", C.c_void_p), ("raw_t", C.c_int),
+                ("Xw", C.c_void_p), ("Xw_f32", C.c_void_p), ("V", C.c_void_p),
+                ("mean", C.c_void_p), ("eigval", C.c_void_p), ("status", C.c_int)]
+
+
 class Problem(C.Structure):
     _fields_ = [("N", C.c_int), ("T", C.c_int64), ("K", C.c_int), ("Xw", C.c_void_p),
                 ("Xw_f32", C.c_void_p), ("W0", C.c_void_p), ("W_out", C.c_void_p),
@@ -62,7 +68,7 @@ class BatchStats(C.Structure):
     _fields_ = [("thread_iters", C.c_int64), ("refine_thread_iters", C.c_int64),
                 ("passes", C.c_int), ("ms", C.c_double), ("update_ms", C.c_double),
                 ("update_launches", C.c_int), ("grid", C.c_int), ("wk32", C.c_int),
-                ("wk64", C.c_int), ("tuned", C.c_int)]
+                ("wk64", C.c_int), ("tuned", C.c_int), ("update_flops", C.c_double)]
 
 
 class UniqueParams(C.Structure):
@@ -78,6 +84,7 @@ _SIGS = {
     "oica_last_error": (C.c_char_p, [_P]),
     "oica_set_stream": (C.c_int, [_P, _P]),
     "oica_whiten": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P, _P, _P, _P]),
+    "oica_whiten_batched": (C.c_int, [_P, C.c_int, C.POINTER(WhitenProblem), C.c_int]),
     "oica_fixed_point": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P,
                                    C.POINTER(FpParams), _P, _P, _P, _P, _P, C.POINTER(FpStats)]),
     "oica_update": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, C.c_int, _P, _P, _P]),
@@ -191,6 +198,34 @@ class Context:
                                   _ptr(Xw32), _ptr(V), _ptr(mean), _ptr(eig))
         self._check(rc)
         return Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig
+
+    def whiten_batched(self, Xs, out_dtype=torch.float32, want_f32=True, return_status=False):
+        """Xs: list of N_d x T_d raw device tensors.  Returns a list of
+        (Xw, Xw_f32, V, mean, eigval) per dataset, as whiten() does; with
+        return_status, also the per-dataset codes, and data errors (rank,
+        non-finite) do not raise."""
+        D = len(Xs)
+        arr = (WhitenProblem * D)()
+        dev = self._tdev()
+        outs = []
+        for d, X in enumerate(Xs):
+            _dev(X, "X")
+            N, T = X.shape
+            Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
+            Xw32 = None
+            if out_dtype == torch.bfloat16 and want_f32:
+                Xw32 = torch.empty((N, T), dtype=torch.float32, device=dev)
+            V = torch.empty((N, N), dtype=torch.float64, device=dev)
+            mean = torch.empty(N, dtype=torch.float64, device=dev)
+            eig = torch.empty(N, dtype=torch.float64, device=dev)
+            arr[d] = WhitenProblem(N, T, _ptr(X), _DT[X.dtype], _ptr(Xw), _ptr(Xw32), _ptr(V),
+                                   _ptr(mean), _ptr(eig), 0)
+            outs.append((Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig))
+        rc = self.lib.oica_whiten_batched(self.h, D, arr, _DT[out_dtype])
+        if return_status and rc in (-3, -4):
+            return outs, [arr[d].status for d in range(D)]
+        self._check(rc)
+        return (outs, [arr[d].status for d in range(D)]) if return_status else outs
 
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
@@ -391,3 +426,26 @@ def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_
                      gaussianity_test=gaussianity_test)
     res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)
     return res
+
+
+def ordering_ica_batched(ctx: Context, Xs, W0s, tol=1e-6, max_iter=1000, tau=1e-3,
+                         gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
+                         profile=False, autotune=True, cache_path=None):
+    """Whole hot path for many device-resident raw datasets: whiten each, one
+    batched fixed point over all of them, unique set of each.  Returns (list of
+    per-dataset results as from ordering_ica, batched stats)."""
+    xw_dtype = torch.bfloat16 if precision == "bf16" else torch.float32
+    probs, wh = [], []
+    for (Xw, Xw32, V, mean, eig), W0 in zip(ctx.whiten_batched(Xs, out_dtype=xw_dtype), W0s):
+        probs.append({"Xw": Xw, "Xw_f32": Xw32, "W0": W0})
+        wh.append((V, mean, eig))
+    outs, st = ctx.fixed_point_batched(probs, max_iter=max_iter, tol=tol, precision=precision,
+                                       tol_bf16=tol_bf16, refine_iters=refine_iters,
+                                       profile=profile, autotune=autotune, cache_path=cache_path)
+    res = []
+    for X, o, (V, mean, eig) in zip(Xs, outs, wh):
+        r = ctx.unique(o["W"], o["kurt"], o["status"], X.shape[1], tau=tau,
+                       gaussianity_test=gaussianity_test)
+        r.update(fp=o, V=V, mean=mean, eig=eig)
+        res.append(r)
+    return res, st

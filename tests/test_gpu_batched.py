@@ -167,3 +167,30 @@ def test_full_size_many_datasets(ctx):
         assert np.all(cos.max(axis=1) >= 1 - 1e-6), d
         j = cos.argmax(axis=1)
         assert np.all(np.abs(aa - ref["alpha"][j]) <= 1e-5 * np.maximum(np.abs(ref["alpha"][j]), 0.1))
+
+
+def test_ordering_ica_batched_end_to_end(ctx):
+    """Raw data in, unique sets out, for three datasets in one batched call: each
+    side whitens its own copy, sets are compared in raw space against the
+    oracle's run of each dataset (same count, |cos| >= 1 - 1e-6, kurtosis within
+    1e-5 max(|alpha|, 0.1))."""
+    from paper_2408_17118_amd import oica
+    shapes = [(8, 10_000, 256), (12, 15_000, 1024), (16, 8_000, 2048)]   # every basin >= 6 starts
+    Xs, W0s, refs = [], [], []
+    for i, (N, T, K) in enumerate(shapes):
+        p = synth.make_problem(synth.eeg_kinds(N), T=T, K=K, seed=200 + i)
+        Xs.append(torch.from_numpy(p.X).cuda())
+        W0s.append(torch.from_numpy(p.W0.astype(np.float32)).cuda())
+        refs.append(ica.ordering_ica(p.X, p.W0, tol=1e-10, max_iter=1000))
+    res, st = oica.ordering_ica_batched(ctx, Xs, W0s, tol=1e-6, autotune=False)
+    assert st["thread_iters"] > 0
+    for d, (r, ref) in enumerate(zip(res, refs)):
+        n = r["n_accepted"]
+        assert n == ref["n_accepted"], (d, n, ref["n_accepted"])
+        U = r["U"].cpu().numpy()[:n] @ r["V"].cpu().numpy()
+        U /= np.linalg.norm(U, axis=1, keepdims=True)
+        cos = np.abs(U @ np.asarray(ref["U_raw"])[:n].T)
+        assert np.all(cos.max(axis=1) >= 1 - 1e-6), (d, np.sort(cos.max(axis=1))[:3])
+        j = cos.argmax(axis=1)
+        ar = np.asarray(ref["alpha"])[j]
+        assert np.all(np.abs(r["alpha"].cpu().numpy()[:n] - ar) <= 1e-5 * np.maximum(np.abs(ar), 0.1))

@@ -135,6 +135,44 @@ def test_whiten_errors(ctx):
     assert e.value.code == -7
 
 
+def test_whiten_batched_equals_single(ctx):
+    """One batched call gives every dataset exactly the single call's outputs
+    (same kernels, one Jacobi launch for all eigenproblems)."""
+    shapes = [(1, 1000), (2, 3000), (7, 5001), (33, 4000), (64, 20_000), (100, 9000), (128, 12_000)]
+    Xs = []
+    for i, (N, T) in enumerate(shapes):
+        X = _mixture(N, T, 1, seed=300 + i).X + 0.25
+        Xs.append(dev(X) if i % 3 else dev(X.astype(np.float32)))
+    for out_dtype in (torch.float32, torch.bfloat16):
+        outs = ctx.whiten_batched(Xs, out_dtype=out_dtype)
+        for X, o in zip(Xs, outs):
+            ref = ctx.whiten(X, out_dtype=out_dtype)
+            for a, b in zip(o, ref):
+                assert torch.equal(a, b)
+    # and against the oracle for the largest
+    Vr = ica.whiten(host(Xs[-1]).astype(np.float64))[1]
+    V = host(outs[-1][2])
+    assert np.allclose(V, Vr, rtol=1e-8, atol=1e-8 * np.abs(Vr).max())
+
+
+def test_whiten_batched_status(ctx):
+    rng = np.random.default_rng(1)
+    S = rng.standard_normal((3, 500))
+    bad = rng.standard_normal((4, 500))
+    bad[1, 10] = np.inf
+    Xs = [dev(rng.standard_normal((5, 600))), dev(np.vstack([S, S[:1]])), dev(bad),
+          dev(rng.standard_normal((6, 700)))]
+    outs, st = ctx.whiten_batched(Xs, return_status=True)
+    assert st == [0, -3, -4, 0]
+    for i in (0, 3):
+        ref = ctx.whiten(Xs[i])
+        assert torch.equal(outs[i][0], ref[0])
+    from paper_2408_17118_amd import oica
+    with pytest.raises(oica.OicaError) as e:
+        ctx.whiten_batched(Xs)
+    assert e.value.code == -3
+
+
 # ---- the fixed point --------------------------------------------------------------
 
 def _rowwise_abs_cos(A, B):
