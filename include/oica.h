@@ -307,9 +307,12 @@ typedef struct {          /* host */
                              sum over problems of 4 N T thread_iters        */
 } oica_batch_stats;
 
-/* D in [1, 1024].  params as for oica_fixed_point (traj_iters must be 0;
- * refine_groups is ignored: in BF16 mode every row that converged on BF16 data
- * or is still moving takes the FP32 passes).  bparams and stats may be NULL.
+/* D in [1, 1024].  params as for oica_fixed_point (traj_iters must be 0; the
+ * pruner is not used).  BF16 mode with refine_groups = 1: per problem, the rows
+ * that converged on BF16 data are grouped as in oica_fixed_point and one row
+ * per group takes the FP32 passes with the rows still moving (one batched
+ * launch per pass for all problems); with refine_groups = 0 every such row
+ * does.  bparams and stats may be NULL.
  * Synchronises.  Errors: OICA_E_ARG (naming the problem index),
  * OICA_E_UNSUPPORTED, OICA_E_NOMEM, OICA_E_DEVICE. */
 int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *problems, oica_dtype xw_t,
@@ -346,6 +349,32 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
                 const uint8_t *status, const oica_unique_params *params, int cap,
                 double *U, double *kurt_u, double *ups_u, int32_t *rep_thread,
                 int32_t *cluster_size, int32_t *row_cluster, int *n_unique, int *n_accepted);
+
+/* Many problems in one call, each exactly as in oica_unique (the same
+ * partition, order, outputs and counts): the per-row passes cover every
+ * problem in one launch, and the clustering rounds of all problems with
+ * K <= 16384 and K N <= 2^19 run in one launch (one work-group per problem).
+ * problems: host array of D (1..1024) descriptors whose pointers are device
+ * pointers as in oica_unique; n_unique and n_accepted are written back.
+ * Synchronises.  Errors: OICA_E_ARG (argument errors before any device work,
+ * naming the problem); OICA_E_SHAPE for the first problem with cap < n_unique
+ * (every problem's counts and first cap clusters are still written). */
+typedef struct {
+  int N;
+  int64_t T;
+  int K;
+  const float *W;
+  const double *kurt;
+  const uint8_t *status;
+  int cap;
+  double *U, *kurt_u, *ups_u;
+  int32_t *rep_thread, *cluster_size;
+  int32_t *row_cluster;   /* nullable */
+  int n_unique, n_accepted;  /* out */
+} oica_unique_problem;
+
+int oica_unique_batched(oica_ctx *ctx, int D, oica_unique_problem *problems,
+                        const oica_unique_params *params);
 
 #ifdef __cplusplus
 }

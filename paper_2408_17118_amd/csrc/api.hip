@@ -357,7 +357,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   need += red_n * sizeof(double) + 256;         // split-group sums
   need += 5 * ((size_t)K * sizeof(int) + 256);  // act lists, kurtosis list, prune survivors
   need += 4 * (sizeof(FpControl) + 256);
-  need += unique_workspace_bytes(K) + 256;      // grouping of BF16 fixed points / guard
+  need += unique_workspace_bytes(K, N) + 256;   // grouping of BF16 fixed points / guard
   if (pruner && !traj) need += (size_t)K * traj_n * 2 * sizeof(float) + 256;
   if (pruner) need += (size_t)gcap * (N * 8 + 8 + 8 + 4 + 4) + 5 * 256;
   rc = ensure_ws(ctx, need);
@@ -376,7 +376,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   FpControl *ctl2 = cv.take<FpControl>(1);
   (void)cv.take<FpControl>(1);  // third control block (kurtosis list), ctl2 + 256 bytes
   int *prune_counts = (int *)cv.take<FpControl>(1);  // [0] survivors, [1] pruned
-  void *gwork = cv.take<char>(unique_workspace_bytes(K));
+  void *gwork = cv.take<char>(unique_workspace_bytes(K, N));
   float *traj_buf = traj;
   if (pruner && !traj) traj_buf = cv.take<float>((size_t)K * traj_n * 2);
   double *gU = nullptr, *gk = nullptr, *gu = nullptr;
@@ -445,10 +445,9 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 4 * sizeof(int), ctx->stream));
         HIP_TRY(ctx, launch_groups(ctx->stream, N, K, W_out, status, 1e-6, gwork, ctx->small_dev,
                                    ctx->small_host, &cluster, &reps));
-        const int n_groups = ctx->small_host[1];
         FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
-        HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, n_groups, status, act2, ctl2,
-                                        left_list, left_rows, kurt_list, ctl3));
+        HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, ctx->small_dev + 1, status,
+                                        act2, ctl2, left_list, left_rows, kurt_list, ctl3));
         if (fp32_passes > 0) {
           rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
                           ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
@@ -769,6 +768,15 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   add((size_t)(D + 1) * 4 * 2 + (size_t)(D + 1) * 8);
   add((size_t)D * 256 * 2);  // two control blocks per problem
   add(kurt_rows * 8);
+  const bool grouped = bf16 && params->refine_groups;
+  if (grouped) {
+    add((size_t)D * 256);                 // clustering control, 4 ints per problem
+    add((size_t)D * sizeof(ClusterJob));
+    for (int d = 0; d < D; ++d) {
+      add(unique_workspace_bytes(pr[d].K, pr[d].N));  // grouping of the BF16 fixed points
+      add((size_t)pr[d].K * 4);              // kurtosis list
+    }
+  }
   rc = ensure_ws(ctx, need + 4096);
   if (rc) return rc;
   Carve cv{(char *)ctx->ws};
@@ -779,6 +787,24 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   long long *red_start = cv.take<long long>(D + 1);
   char *ctl_base = cv.take<char>((size_t)D * 256 * 2);
   double *s4part64 = cv.take<double>(kurt_rows);
+  int *gctl = nullptr;
+  ClusterJob *gjobs_dev = nullptr;
+  std::vector<ClusterJob> gjobs;
+  std::vector<ClusterWs> gws;
+  std::vector<int *> kurt_list(D, nullptr);
+  if (grouped) {
+    gctl = cv.take<int>((size_t)D * 64);
+    gjobs_dev = cv.take<ClusterJob>(D);
+    gjobs.resize(D);
+    gws.resize(D);
+    for (int d = 0; d < D; ++d) {
+      const int K = pr[d].K;
+      gws[d] = carve_cluster_ws(cv.take<char>(unique_workspace_bytes(K, pr[d].N)), K, pr[d].N);
+      gjobs[d] = ClusterJob{K, pr[d].N, pr[d].W_out, gws[d].Wt, gws[d].key, gws[d].cluster,
+                            gws[d].reps, gctl + 64 * d};
+      kurt_list[d] = cv.take<int>((size_t)K);
+    }
+  }
   std::vector<int *> act2(D);
   for (int d = 0; d < D; ++d) {
     const oica_problem &q = pr[d];
@@ -878,10 +904,17 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
 
   // ---- passes -----------------------------------------------------------------
   std::vector<char> ctl_host((size_t)D * 256 * 2);
-  auto run = [&](int max_passes, double tol, int exit_below, int stall_polls, bool data_bf16,
-                 int *launched, double *kernel_ms) -> int {
+  // Early exit of the BF16 loop, per problem: a problem whose active count is
+  // at most K/64, or has not shrunk over two polls, is parked (its count is set
+  // to zero, its active list is left as it is) and its rows go on to the FP32
+  // passes.  The decisions use the problem's own counts at the common poll
+  // passes, so they do not depend on the other problems of the batch.
+  std::vector<int> park_count(D, -1), park_parity(D, 0);
+  auto run = [&](int max_passes, double tol, bool park, bool data_bf16, int *launched,
+                 double *kernel_ms) -> int {
     long long kmax = ktot;
-    int stalled = 0;
+    std::vector<int> kprev(D), stalled(D, 0);
+    for (int d = 0; d < D; ++d) kprev[d] = pr[d].K;
     *launched = 0;
     *kernel_ms = 0.0;
     for (int pass = 0; pass < max_passes; ++pass) {
@@ -905,14 +938,27 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
         HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data(), hd[0].ctl, (size_t)D * 256, hipMemcpyDeviceToHost,
                                     ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        const int par = (pass + 1) & 1;
         long long left = 0;
-        for (int d = 0; d < D; ++d)
-          left += ((const FpControl *)(ctl_host.data() + (size_t)d * 256))->kact[(pass + 1) & 1];
+        bool parked_now = false;
+        for (int d = 0; d < D; ++d) {
+          int kd = ((const FpControl *)(ctl_host.data() + (size_t)d * 256))->kact[par];
+          if (park && park_count[d] < 0 && kd > 0) {
+            stalled[d] = kd >= kprev[d] ? stalled[d] + 1 : 0;
+            kprev[d] = kd;
+            if (kd <= std::max(pr[d].K / 64, 1) || stalled[d] >= 2) {
+              park_count[d] = kd;
+              park_parity[d] = par;
+              HIP_TRY(ctx, hipMemsetAsync(&hd[d].ctl->kact[par], 0, sizeof(int), ctx->stream));
+              parked_now = true;
+              kd = 0;
+            }
+          }
+          left += kd;
+        }
+        if (parked_now) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         if (left == 0) break;
-        stalled = (left >= kmax) ? stalled + 1 : 0;
         kmax = left;
-        if (exit_below > 0 && left <= exit_below) break;
-        if (stall_polls > 0 && stalled >= stall_polls) break;
       }
     }
     if (profile)
@@ -925,8 +971,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   };
   int launched = 0;
   double kernel_ms = 0.0;
-  rc = run(params->max_iter, bf16 ? params->tol_bf16 : params->tol,
-           bf16 ? (int)std::max<long long>(ktot / 64, 1) : 0, bf16 ? 2 : 0, bf16, &launched,
+  rc = run(params->max_iter, bf16 ? params->tol_bf16 : params->tol, bf16, bf16, &launched,
            &kernel_ms);
   if (rc) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data(), hd[0].ctl, (size_t)D * 256, hipMemcpyDeviceToHost,
@@ -942,13 +987,44 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     main_passes = std::max(main_passes, c->passes);
   }
   if (bf16) {
-    // FP32 passes for every row that converged on BF16 data or is still moving
+    // FP32 passes: grouped, for one row per group of rows at numerically the
+    // same BF16 fixed point (1 - |cos| <= 1e-6) plus the rows still moving;
+    // otherwise for every row that converged on BF16 data or is still moving
+    if (grouped) {
+      HIP_TRY(ctx, hipMemsetAsync(gctl, 0, (size_t)D * 64 * sizeof(int), ctx->stream));
+      for (int d = 0; d < D; ++d)
+        HIP_TRY(ctx, launch_prep_groups(ctx->stream, pr[d].K, pr[d].N, pr[d].status, pr[d].W_out,
+                                        gws[d]));
+      std::vector<ClusterJob> small;
+      for (int d = 0; d < D; ++d)
+        if (cluster_in_one_wg(pr[d].K, true)) small.push_back(gjobs[d]);
+      if (!small.empty()) {
+        HIP_TRY(ctx, hipMemcpyAsync(gjobs_dev, small.data(), small.size() * sizeof(ClusterJob),
+                                    hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // `small` is a local table
+        HIP_TRY(ctx, launch_cluster_wg(ctx->stream, (int)small.size(), gjobs_dev, small[0], 1e-6));
+      }
+      for (int d = 0; d < D; ++d)
+        if (!cluster_in_one_wg(pr[d].K, true)) {
+          int *reps = nullptr, *cl = nullptr;
+          HIP_TRY(ctx, launch_groups(ctx->stream, pr[d].N, pr[d].K, pr[d].W_out, pr[d].status, 1e-6,
+                                     (void *)gws[d].key, gjobs[d].ctl, ctx->small_host, &cl, &reps));
+        }
+    }
     for (int d = 0; d < D; ++d) {
       const FpControl *c = (const FpControl *)(ctl_host.data() + (size_t)d * 256);
       BatchDesc &b = hd[d];
       FpControl *c2 = (FpControl *)(ctl_base + (size_t)(D + d) * 256);
-      HIP_TRY(ctx, launch_refine_select(ctx->stream, b.K, b.status, act2[d], c2,
-                                        (launched & 1) ? b.act1 : b.act0, c->kact[launched & 1]));
+      const bool parked = park_count[d] >= 0;
+      const int par = parked ? park_parity[d] : (launched & 1);
+      const int *left_list = par ? b.act1 : b.act0;
+      const int left = parked ? park_count[d] : c->kact[launched & 1];
+      if (grouped)
+        HIP_TRY(ctx, launch_group_lists(ctx->stream, b.K, gjobs[d].cluster, gjobs[d].reps,
+                                        gjobs[d].ctl + 1, b.status, act2[d], c2, left_list, left,
+                                        kurt_list[d], (FpControl *)((char *)c2 + 128)));
+      else
+        HIP_TRY(ctx, launch_refine_select(ctx->stream, b.K, b.status, act2[d], c2, left_list, left));
       int *old0 = b.act0;
       b.act0 = act2[d];
       b.act1 = old0;
@@ -964,7 +1040,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     int l2 = 0;
     double ms2 = 0.0;
     if (passes32 > 0) {
-      rc = run(passes32, params->tol, 0, 0, false, &l2, &ms2);
+      rc = run(passes32, params->tol, false, false, &l2, &ms2);
       if (rc) return rc;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data() + (size_t)D * 256, ctl_base + (size_t)D * 256,
@@ -973,11 +1049,25 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     for (int d = 0; d < D; ++d)
       refine_ti += ((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->thread_iters;
   }
-  // final kurtosis of every row, FP32 data, FP64 sums
-  for (int d = 0; d < D; ++d) {
-    const oica_problem &q = pr[d];
-    HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T, q.Xw_f32,
-                                 q.K, q.W_out, s4part64, q.kurt));
+  if (grouped) {
+    // kurtosis of the group representatives and of the ungrouped rows, then
+    // every group member takes its representative's row, status and kurtosis
+    for (int d = 0; d < D; ++d) {
+      const oica_problem &q = pr[d];
+      FpControl *c3 = (FpControl *)(ctl_base + (size_t)(D + d) * 256 + 128);
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T, q.Xw_f32,
+                                   q.K, q.W_out, s4part64, q.kurt, kurt_list[d], &c3->kact[0]));
+      HIP_TRY(ctx, launch_propagate(ctx->stream, q.K, q.N, gjobs[d].cluster, gjobs[d].reps, q.W_out,
+                                    q.status, q.kurt));
+    }
+  } else
+  {
+    // final kurtosis of every row, FP32 data, FP64 sums
+    for (int d = 0; d < D; ++d) {
+      const oica_problem &q = pr[d];
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T,
+                                   q.Xw_f32, q.K, q.W_out, s4part64, q.kurt));
+    }
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
@@ -1014,7 +1104,7 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
     return fail(ctx, OICA_E_ARG, "W, kurt, status, n_unique and n_accepted must be non-null");
   if (cap > 0 && (!U || !kurt_u || !ups_u || !rep_thread || !cluster_size))
     return fail(ctx, OICA_E_ARG, "output arrays must be non-null when cap > 0");
-  rc = ensure_ws(ctx, unique_workspace_bytes(K));
+  rc = ensure_ws(ctx, unique_workspace_bytes(K, N));
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
@@ -1027,6 +1117,65 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
   if (cap < *n_unique)
     return fail(ctx, OICA_E_SHAPE, "cap=%d is smaller than the %d clusters found", cap, *n_unique);
   return OICA_OK;
+}
+
+int oica_unique_batched(oica_ctx *ctx, int D, oica_unique_problem *problems,
+                        const oica_unique_params *params) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  if (D < 1 || D > 1024) return fail(ctx, OICA_E_ARG, "D must be in [1, 1024]");
+  if (!problems) return fail(ctx, OICA_E_ARG, "problems must be non-null");
+  if (!params) return fail(ctx, OICA_E_ARG, "params must be non-null");
+  if (!(params->tau > 0.0 && params->tau < 1.0)) return fail(ctx, OICA_E_ARG, "tau must be in (0, 1)");
+  if (params->n_top < 0) return fail(ctx, OICA_E_ARG, "n_top must be >= 0");
+  std::vector<oica::UJob> jobs(D);
+  for (int d = 0; d < D; ++d) {
+    oica_unique_problem &q = problems[d];
+    q.n_unique = q.n_accepted = 0;
+    int rc = check_dims(ctx, q.N, q.T);
+    if (rc) {
+      const std::string why = ctx->err;
+      return fail(ctx, rc, "problem %d: %s", d, why.c_str());
+    }
+    if (q.K < 1) return fail(ctx, OICA_E_ARG, "problem %d: K must be >= 1", d);
+    if (q.cap < 0) return fail(ctx, OICA_E_ARG, "problem %d: cap must be >= 0", d);
+    if (!q.W || !q.kurt || !q.status)
+      return fail(ctx, OICA_E_ARG, "problem %d: W, kurt and status must be non-null", d);
+    if (q.cap > 0 && (!q.U || !q.kurt_u || !q.ups_u || !q.rep_thread || !q.cluster_size))
+      return fail(ctx, OICA_E_ARG, "problem %d: output arrays must be non-null when cap > 0", d);
+    oica::UJob &j = jobs[d];
+    j = oica::UJob{};
+    j.K = q.K;
+    j.N = q.N;
+    j.T = q.T;
+    j.W = q.W;
+    j.kurt = q.kurt;
+    j.status = q.status;
+    j.tau = params->tau;
+    j.gtest = params->gaussianity_test;
+    j.n_top = params->n_top;
+    j.cap = q.cap;
+    j.U = q.U;
+    j.kurt_u = q.kurt_u;
+    j.ups_u = q.ups_u;
+    j.rep_thread = q.rep_thread;
+    j.csize = q.cluster_size;
+    j.row_cluster = q.row_cluster;
+  }
+  int rc = ensure_ws(ctx, unique_batched_workspace_bytes(D, jobs.data()));
+  if (rc) return rc;
+  std::vector<int> counts((size_t)D * 4);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_unique_batched(ctx->stream, D, jobs.data(), ctx->ws, counts.data()));
+  int first = OICA_OK;
+  for (int d = 0; d < D; ++d) {
+    problems[d].n_unique = counts[4 * d + 1];
+    problems[d].n_accepted = counts[4 * d + 3];
+    if (problems[d].cap < problems[d].n_unique && first == OICA_OK)
+      first = fail(ctx, OICA_E_SHAPE, "problem %d: cap=%d is smaller than the %d clusters found", d,
+                   problems[d].cap, problems[d].n_unique);
+  }
+  return first;
 }
 
 }  // extern "C"

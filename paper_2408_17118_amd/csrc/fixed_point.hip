@@ -452,12 +452,12 @@ hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
 // active after the BF16 loop go to refine_list; every row that is not a
 // non-representative group member goes to kurt_list.
 __global__ void k_group_lists(int K, const int *__restrict__ cluster, const int *__restrict__ reps,
-                              int n_groups, uint8_t *__restrict__ status,
+                              const int *__restrict__ n_groups_dev, uint8_t *__restrict__ status,
                               int *__restrict__ refine_list, FpControl *ctl_refine,
                               const int *__restrict__ left_list, int left,
                               int *__restrict__ kurt_list, FpControl *ctl_kurt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_groups) {
+  if (i < *n_groups_dev) {
     const int r = reps[i];
     status[r] = OICA_ROW_NOTCONV;
     refine_list[atomicAdd(&ctl_refine->kact[0], 1)] = r;
@@ -495,10 +495,12 @@ __global__ void k_propagate(int K, int N, const int *__restrict__ cluster,
 }
 
 hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
-                              int n_groups, uint8_t *status, int *refine_list, FpControl *ctl_refine,
-                              const int *left_list, int left, int *kurt_list, FpControl *ctl_kurt) {
+                              const int *n_groups_dev, uint8_t *status, int *refine_list,
+                              FpControl *ctl_refine, const int *left_list, int left, int *kurt_list,
+                              FpControl *ctl_kurt) {
   hipLaunchKernelGGL(k_group_lists, dim3((K + 255) / 256), dim3(256), 0, st, K, cluster, reps,
-                     n_groups, status, refine_list, ctl_refine, left_list, left, kurt_list, ctl_kurt);
+                     n_groups_dev, status, refine_list, ctl_refine, left_list, left, kurt_list,
+                     ctl_kurt);
   return hipGetLastError();
 }
 

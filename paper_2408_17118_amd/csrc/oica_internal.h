@@ -82,6 +82,24 @@ struct BatchCtl {
 
 // ---- launchers (defined next to their kernels) ----------------------------
 
+// unique.hip: greedy leader clustering of one problem in one work-group
+struct ClusterJob {
+  int K, N;
+  const float *W;      // K x N rows
+  const float *Wt;     // N x K: the same rows transposed
+  const double *key;   // K: rank key (descending, then row index)
+  int *cluster;        // K: -2 not a candidate, -1 candidate; out: cluster id
+  int *reps;           // out: representative row of each cluster
+  int *ctl;            // out: ctl[1] = number of clusters, ctl[2] = 1
+};
+constexpr int CW_MAX_K = 4096;
+// One problem alone: the one-work-group form only while its rounds are short
+// (its row loads are latency-bound); many problems: whenever K fits, since
+// the problems then run side by side.
+inline bool cluster_in_one_wg(int K, bool many) { return K <= (many ? CW_MAX_K : 1024); }
+hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
+                             const ClusterJob &one, double tau);
+
 // whiten.hip
 struct JacJob {        // one symmetric eigenproblem of the Jacobi solver
   int N;
@@ -137,8 +155,9 @@ hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            const float *X, int K, const float *W, double *s4part64,
                            double *kurt, const int *act = nullptr, const int *kact_dev = nullptr);
 hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
-                              int n_groups, uint8_t *status, int *refine_list, FpControl *ctl_refine,
-                              const int *left_list, int left, int *kurt_list, FpControl *ctl_kurt);
+                              const int *n_groups_dev, uint8_t *status, int *refine_list,
+                              FpControl *ctl_refine, const int *left_list, int left, int *kurt_list,
+                              FpControl *ctl_kurt);
 hipError_t launch_propagate(hipStream_t st, int K, int N, const int *cluster, const int *reps,
                             float *W, uint8_t *status, double *kurt);
 hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,
@@ -172,7 +191,34 @@ hipError_t launch_prune(hipStream_t st, const PrunerState *p, const float *traj,
 hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpControl *ctl);
 
 // unique.hip
-size_t unique_workspace_bytes(int K);
+struct UJob {          // one unique-components problem
+  int K, N;
+  long long T;
+  const float *W;
+  const double *kurt;
+  const uint8_t *status;
+  double tau;
+  int gtest, n_top, cap;
+  double *U, *kurt_u, *ups_u;
+  int32_t *rep_thread, *csize, *row_cluster;
+  // workspace (carved by the launcher)
+  double *key;
+  int *cluster, *part_idx, *reps, *sizes, *ctl;
+  float *Wt;
+};
+struct ClusterWs {     // workspace of one clustering problem
+  double *key;
+  int *cluster, *reps, *sizes, *part_idx;
+  float *Wt;           // N x K transposed rows
+};
+size_t cluster_ws_bytes(int K, int N);
+ClusterWs carve_cluster_ws(void *ws, int K, int N);
+size_t unique_workspace_bytes(int K, int N);
+// grouping candidates: CONV rows, equal keys (cluster -1), others -2; writes cw.Wt
+hipError_t launch_prep_groups(hipStream_t st, int K, int N, const uint8_t *status, const float *W,
+                              const ClusterWs &cw);
+size_t unique_batched_workspace_bytes(int D, const UJob *jobs);
+hipError_t launch_unique_batched(hipStream_t st, int D, UJob *jobs, void *ws, int *counts_host);
 hipError_t launch_groups(hipStream_t st, int N, int K, const float *W, const uint8_t *status,
                          double tau, void *ws, int *ctl_dev, int *ctl_host, int **cluster_out,
                          int **reps_out);

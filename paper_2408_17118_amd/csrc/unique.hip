@@ -13,6 +13,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 namespace oica {
@@ -31,44 +32,72 @@ __device__ inline bool ranks_above(double ka, int ia, double kb, int ib) {
   return (ka > kb) || (ka == kb && ia < ib);
 }
 
-struct UniqueWs {
-  double *key;      // K: criterion of each candidate
-  int *cluster;     // K: -2 not a candidate, -1 unassigned, >= 0 cluster id
-  int *part_idx;    // blocks: best unassigned index per block
-  int *reps;        // K + 1: representative of each round
-  int *ctl;         // [0] any CONV, [1] number of clusters, [2] done, [3] accepted
-  int *sizes;       // K
-};
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t unique_workspace_bytes(int K) {
+size_t cluster_ws_bytes(int K, int N) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
-  return (size_t)K * 8 + (size_t)K * 4 + (size_t)nb * 4 + (size_t)(K + 1) * 4 + 64 +
-         (size_t)K * 4 + 6 * 256;
+  return al256((size_t)K * 8) + 3 * al256((size_t)(K + 1) * 4) + al256((size_t)nb * 4) +
+         al256((size_t)K * N * 4);
 }
 
-__global__ void k_any_conv(int K, const uint8_t *__restrict__ status, int *ctl) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < K && status[l] == OICA_ROW_CONV) ctl[0] = 1;
+ClusterWs carve_cluster_ws(void *ws, int K, int N) {
+  const int nb = (K + U_BLOCK - 1) / U_BLOCK;
+  char *p = (char *)ws;
+  auto take = [&](size_t bytes) {
+    char *r = p;
+    p += al256(bytes);
+    return r;
+  };
+  ClusterWs w;
+  w.key = (double *)take((size_t)K * 8);
+  w.cluster = (int *)take((size_t)(K + 1) * 4);
+  w.reps = (int *)take((size_t)(K + 1) * 4);
+  w.sizes = (int *)take((size_t)(K + 1) * 4);
+  w.part_idx = (int *)take((size_t)nb * 4);
+  w.Wt = (float *)take((size_t)K * N * 4);
+  return w;
 }
 
-__global__ void k_prep(int K, const double *__restrict__ kurt, const uint8_t *__restrict__ status,
-                       const int *__restrict__ ctl, double *__restrict__ key,
-                       int *__restrict__ cluster, int *__restrict__ sizes) {
+size_t unique_workspace_bytes(int K, int N) { return cluster_ws_bytes(K, N); }
+
+// Wt[n][l] = W[l][n]: the clustering reads candidate rows column by column, so
+// the lanes of a wave (consecutive rows) read consecutive addresses.
+__device__ inline void transpose_row(const float *__restrict__ W, float *__restrict__ Wt, int K,
+                                     int N, int l) {
+  for (int n = 0; n < N; ++n) Wt[(size_t)n * K + l] = W[(size_t)l * N + n];
+}
+
+__device__ inline const UJob &ujob(const UJob *jobs, const UJob &one) {
+  return jobs ? jobs[blockIdx.y] : one;
+}
+
+__global__ void k_any_conv(const UJob *__restrict__ jobs, UJob one) {
+  const UJob &j = ujob(jobs, one);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= K) return;
-  const bool any_conv = ctl[0] != 0;
-  const uint8_t s = status[l];
+  if (l < j.K && j.status[l] == OICA_ROW_CONV) j.ctl[0] = 1;
+}
+
+__global__ void k_prep(const UJob *__restrict__ jobs, UJob one) {
+  const UJob &j = ujob(jobs, one);
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= j.K) return;
+  const bool any_conv = j.ctl[0] != 0;
+  const uint8_t s = j.status[l];
   bool cand = any_conv ? (s == OICA_ROW_CONV) : (s != OICA_ROW_DEGENERATE);
-  const double a = kurt[l];
+  const double a = j.kurt[l];
   cand = cand && isfinite(a);
-  key[l] = cand ? upsilon_dev(a) : -INFINITY;
-  cluster[l] = cand ? -1 : -2;
-  sizes[l] = 0;
+  j.key[l] = cand ? upsilon_dev(a) : -INFINITY;
+  j.cluster[l] = cand ? -1 : -2;
+  j.sizes[l] = 0;
+  transpose_row(j.W, j.Wt, j.K, j.N, l);
 }
+
+constexpr int DOT_CHUNK = 8;  // samples of a candidate row loaded before its FMAs
 
 // One round: assign unassigned candidates within tau of representative
 // reps[r] (skipped for r < 0), then per-block arg-max of the still unassigned.
 __global__ __launch_bounds__(U_BLOCK) void k_assign(int K, int N, const float *__restrict__ W,
+                                                    const float *__restrict__ Wt,
                                                     const double *__restrict__ key,
                                                     int *__restrict__ cluster,
                                                     const int *__restrict__ reps, int r,
@@ -84,10 +113,17 @@ __global__ __launch_bounds__(U_BLOCK) void k_assign(int K, int N, const float *_
   if (l < K && cluster[l] == -1) {
     bool joined = false;
     if (rep >= 0) {
-      const float *a = W + (size_t)l * N;
       const float *b = W + (size_t)rep * N;
       double dot = 0.0;
-      for (int n = 0; n < N; ++n) dot = fma((double)a[n], (double)b[n], dot);
+      for (int n0 = 0; n0 < N; n0 += DOT_CHUNK) {
+        float v[DOT_CHUNK];  // loads of a chunk first, then the FMAs in order
+#pragma unroll
+        for (int j = 0; j < DOT_CHUNK; ++j)
+          v[j] = n0 + j < N ? Wt[(size_t)(n0 + j) * K + l] : 0.f;
+#pragma unroll
+        for (int j = 0; j < DOT_CHUNK; ++j)
+          if (n0 + j < N) dot = fma((double)v[j], (double)b[n0 + j], dot);
+      }
       if (1.0 - fabs(dot) <= tau || l == rep) {
         cluster[l] = r;
         joined = true;
@@ -152,28 +188,25 @@ __global__ __launch_bounds__(U_BLOCK) void k_pick(int nblocks, const double *__r
   }
 }
 
-__global__ void k_sizes(int K, const int *__restrict__ cluster, int *__restrict__ sizes,
-                        int32_t *__restrict__ row_cluster) {
+__global__ void k_sizes(const UJob *__restrict__ jobs, UJob one) {
+  const UJob &j = ujob(jobs, one);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= K) return;
-  const int c = cluster[l];
-  if (c >= 0) atomicAdd(&sizes[c], 1);
-  if (row_cluster) row_cluster[l] = c >= 0 ? c : -1;
+  if (l >= j.K) return;
+  const int c = j.cluster[l];
+  if (c >= 0) atomicAdd(&j.sizes[c], 1);
+  if (j.row_cluster) j.row_cluster[l] = c >= 0 ? c : -1;
 }
 
 // Output of the first min(U, cap) clusters, and the Gaussianity walk.
-__global__ void k_finalize(int N, long long T, const float *__restrict__ W,
-                           const double *__restrict__ kurt, const double *__restrict__ key,
-                           const int *__restrict__ reps, const int *__restrict__ sizes, int gtest,
-                           int n_top, int cap, double *__restrict__ U, double *__restrict__ kurt_u,
-                           double *__restrict__ ups_u, int32_t *__restrict__ rep_thread,
-                           int32_t *__restrict__ csize, int *__restrict__ ctl) {
-  const int nu = ctl[1];
-  const int lim = nu < cap ? nu : cap;
+__global__ void k_finalize(const UJob *__restrict__ jobs, UJob one) {
+  const UJob &j = ujob(jobs, one);
+  const int N = j.N;
+  const int nu = j.ctl[1];
+  const int lim = nu < j.cap ? nu : j.cap;
   __shared__ int pm;
   for (int r = blockIdx.x; r < lim; r += gridDim.x) {
-    const int rep = reps[r];
-    const float *w = W + (size_t)rep * N;
+    const int rep = j.reps[r];
+    const float *w = j.W + (size_t)rep * N;
     // sign rule: largest-magnitude entry positive, lowest index on ties
     if (threadIdx.x == 0) {
       int best = 0;
@@ -189,48 +222,168 @@ __global__ void k_finalize(int N, long long T, const float *__restrict__ W,
     }
     __syncthreads();
     const double sg = w[pm] < 0.f ? -1.0 : 1.0;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) U[(size_t)r * N + n] = sg * (double)w[n];
+    for (int n = threadIdx.x; n < N; n += blockDim.x) j.U[(size_t)r * N + n] = sg * (double)w[n];
     if (threadIdx.x == 0) {
-      kurt_u[r] = kurt[rep];
-      ups_u[r] = key[rep];
-      rep_thread[r] = rep;
-      csize[r] = sizes[r];
+      j.kurt_u[r] = j.kurt[rep];
+      j.ups_u[r] = j.key[rep];
+      j.rep_thread[r] = rep;
+      j.csize[r] = j.sizes[r];
     }
     __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     int acc = nu;
-    if (gtest) {
+    if (j.gtest) {
       acc = 0;
       for (int r = 1; r <= nu; ++r) {
-        const double thr = 2.0 * (double)(N - r + 2) * (double)(N - r + 1) / (double)T;
-        if (key[reps[r - 1]] < thr) break;
+        const double thr = 2.0 * (double)(N - r + 2) * (double)(N - r + 1) / (double)j.T;
+        if (j.key[j.reps[r - 1]] < thr) break;
         acc = r;
       }
     }
-    if (n_top > 0 && acc > n_top) acc = n_top;
-    ctl[3] = acc;
+    if (j.n_top > 0 && acc > j.n_top) acc = j.n_top;
+    j.ctl[3] = acc;
   }
+}
+
+// All rounds in one work-group (problems with K <= CW_MAX_K; several problems
+// in one launch, one work-group each).  Each thread keeps the cluster state
+// and key of its rows in registers; a round is one pass (assign to the current
+// representative, arg-max of the rest) and a block arg-max: three barriers per
+// round instead of two kernel launches.  The dot products are the ones k_assign
+// computes, in the same order, so the partition is identical.
+constexpr int CW_THREADS = 1024;
+
+__device__ inline void cw_better(double &bk, int &bi, double k2, int i2) {
+  if (ranks_above(k2, i2, bk, bi)) {
+    bk = k2;
+    bi = i2;
+  }
+}
+
+__global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__restrict__ jobs,
+                                                           ClusterJob one, double tau) {
+  constexpr int R = CW_MAX_K / CW_THREADS;  // rows per thread
+  __shared__ double lw[OICA_MAX_N];
+  __shared__ double wk[CW_THREADS / 64];
+  __shared__ int wi[CW_THREADS / 64];
+  __shared__ int s_leader;
+  const ClusterJob jb = jobs ? jobs[blockIdx.x] : one;
+  const int K = jb.K, N = jb.N;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const float *__restrict__ Wt = jb.Wt;
+  // this thread's rows l = tid + i * CW_THREADS: cluster state and key
+  int cl[R];
+  double key[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int l = tid + i * CW_THREADS;
+    cl[i] = l < K ? jb.cluster[l] : -2;
+    key[i] = cl[i] == -1 ? jb.key[l] : -INFINITY;
+  }
+  int leader = -1;
+  int r = -1;
+  for (;;) {
+    // assign to the current leader (round r), arg-max of the unassigned rest
+    if (leader >= 0) {
+      double dot[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) dot[i] = 0.0;
+      constexpr int C = DOT_CHUNK / 2;
+      for (int n0 = 0; n0 < N; n0 += C) {
+        float v[R][C];  // every load of the chunk first, then the FMAs in order
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int j = 0; j < C; ++j)
+            v[i][j] = (cl[i] == -1 && n0 + j < N) ? Wt[(size_t)(n0 + j) * K + tid + i * CW_THREADS]
+                                                  : 0.f;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int j = 0; j < C; ++j)
+            if (n0 + j < N) dot[i] = fma((double)v[i][j], lw[n0 + j], dot[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (cl[i] == -1 && (1.0 - fabs(dot[i]) <= tau || tid + i * CW_THREADS == leader)) cl[i] = r;
+    }
+    double bk = -INFINITY;
+    int bi = -1;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (cl[i] == -1) cw_better(bk, bi, key[i], tid + i * CW_THREADS);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double k2 = __shfl_xor(bk, o);
+      const int i2 = __shfl_xor(bi, o);
+      cw_better(bk, bi, k2, i2);
+    }
+    if (lane == 0) {
+      wk[wave] = bk;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double k0 = wk[0];
+      int i0 = wi[0];
+      for (int w = 1; w < CW_THREADS / 64; ++w) cw_better(k0, i0, wk[w], wi[w]);
+      s_leader = i0;
+      jb.reps[r + 1] = i0;  // -1 after the last cluster
+    }
+    __syncthreads();
+    leader = s_leader;
+    if (leader < 0) break;
+    ++r;
+    for (int n = tid; n < N; n += CW_THREADS) lw[n] = (double)jb.W[(size_t)leader * N + n];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int l = tid + i * CW_THREADS;
+    if (l < K) jb.cluster[l] = cl[i];
+  }
+  if (tid == 0) {
+    jb.ctl[1] = r + 1;
+    jb.ctl[2] = 1;
+  }
+}
+
+hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
+                             const ClusterJob &one, double tau) {
+  hipLaunchKernelGGL(k_cluster_wg, dim3(D), dim3(CW_THREADS), 0, st, jobs_dev, one, tau);
+  return hipGetLastError();
 }
 
 // Greedy leader clustering of the candidates (cluster[l] == -1 on entry) in
 // (key descending, row index) order; writes cluster ids, the representative of
 // every cluster (reps[0..n)), and n into ctl_dev[1] / ctl_host[1].
 // ctl_dev (4 ints) must be zero on entry except ctl_dev[0].  Synchronises.
-hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const double *key,
-                          int *cluster, int *reps, int *part_idx, double tau, int *ctl_dev,
-                          int *ctl_host) {
+// W is read through its transposed copy in cw.Wt (written by the prep kernel).
+hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const ClusterWs &cw,
+                          double tau, int *ctl_dev, int *ctl_host) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
+  const double *key = cw.key;
+  int *cluster = cw.cluster, *reps = cw.reps, *part_idx = cw.part_idx;
+  const float *Wt = cw.Wt;
+  if (cluster_in_one_wg(K, false)) {
+    const ClusterJob job{K, N, W, Wt, key, cluster, reps, ctl_dev};
+    hipError_t e = launch_cluster_wg(st, 1, nullptr, job, tau);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  }
   // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left
-  hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, key, cluster, reps, -1,
-                     tau, part_idx, ctl_dev);
+  hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, Wt, key, cluster, reps,
+                     -1, tau, part_idx, ctl_dev);
   hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, -1,
                      ctl_dev);  // writes reps[0]
   const int BATCH = 16;
   for (int r0 = 0; r0 <= K; r0 += BATCH) {
     for (int r = r0; r < r0 + BATCH && r <= K; ++r) {
-      hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, key, cluster, reps, r,
-                         tau, part_idx, ctl_dev);
+      hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, Wt, key, cluster,
+                         reps, r, tau, part_idx, ctl_dev);
       hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, r,
                          ctl_dev);
     }
@@ -243,38 +396,47 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const do
   return hipGetLastError();
 }
 
-size_t cluster_workspace_bytes(int K) { return unique_workspace_bytes(K); }
-
 // Candidates for grouping the rows that converged on BF16 data: every CONV row,
 // all with the same key, so the lowest row index of a group represents it.
-__global__ void k_prep_groups(int K, const uint8_t *__restrict__ status, double *__restrict__ key,
-                              int *__restrict__ cluster) {
+__global__ void k_prep_groups(int K, int N, const uint8_t *__restrict__ status,
+                              const float *__restrict__ W, ClusterWs cw) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= K) return;
   const bool cand = status[l] == OICA_ROW_CONV;
-  key[l] = cand ? 0.0 : -INFINITY;
-  cluster[l] = cand ? -1 : -2;
+  cw.key[l] = cand ? 0.0 : -INFINITY;
+  cw.cluster[l] = cand ? -1 : -2;
+  transpose_row(W, cw.Wt, K, N, l);
+}
+
+hipError_t launch_prep_groups(hipStream_t st, int K, int N, const uint8_t *status, const float *W,
+                              const ClusterWs &cw) {
+  hipLaunchKernelGGL(k_prep_groups, dim3((K + U_BLOCK - 1) / U_BLOCK), dim3(U_BLOCK), 0, st, K, N,
+                     status, W, cw);
+  return hipGetLastError();
 }
 
 hipError_t launch_groups(hipStream_t st, int N, int K, const float *W, const uint8_t *status,
                          double tau, void *ws, int *ctl_dev, int *ctl_host, int **cluster_out,
                          int **reps_out) {
-  const int nb = (K + U_BLOCK - 1) / U_BLOCK;
-  char *p = (char *)ws;
-  auto take = [&](size_t bytes) {
-    char *r = p;
-    p += (bytes + 255) & ~(size_t)255;
-    return r;
-  };
-  double *key = (double *)take((size_t)K * 8);
-  int *cluster = (int *)take((size_t)K * 4);
-  int *part_idx = (int *)take((size_t)nb * 4);
-  int *reps = (int *)take((size_t)(K + 1) * 4);
-  hipLaunchKernelGGL(k_prep_groups, dim3(nb), dim3(U_BLOCK), 0, st, K, status, key, cluster);
-  hipError_t e = launch_cluster(st, N, K, W, key, cluster, reps, part_idx, tau, ctl_dev, ctl_host);
-  *cluster_out = cluster;
-  *reps_out = reps;
+  const ClusterWs cw = carve_cluster_ws(ws, K, N);
+  hipError_t e = launch_prep_groups(st, K, N, status, W, cw);
+  if (e != hipSuccess) return e;
+  e = launch_cluster(st, N, K, W, cw, tau, ctl_dev, ctl_host);
+  *cluster_out = cw.cluster;
+  *reps_out = cw.reps;
   return e;
+}
+
+// Carve one problem's workspace (unique_workspace_bytes(K, N) bytes at ws).
+static ClusterWs carve_ujob(UJob &j, void *ws) {
+  const ClusterWs cw = carve_cluster_ws(ws, j.K, j.N);
+  j.key = cw.key;
+  j.cluster = cw.cluster;
+  j.part_idx = cw.part_idx;
+  j.reps = cw.reps;
+  j.sizes = cw.sizes;
+  j.Wt = cw.Wt;
+  return cw;
 }
 
 hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W,
@@ -283,31 +445,83 @@ hipError_t launch_unique(hipStream_t st, int N, int64_t T, int K, const float *W
                          int32_t *rep_thread, int32_t *cluster_size, void *ws, int *counts_host,
                          int *counts_dev, int32_t *row_cluster) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
+  UJob j{K, N, (long long)T, W, kurt, status, tau, gtest, n_top, cap, U, kurt_u, ups_u,
+         rep_thread, cluster_size, row_cluster};
+  const ClusterWs cw = carve_ujob(j, ws);
+  j.ctl = counts_dev;  // 4 ints, zeroed by the caller
+  hipLaunchKernelGGL(k_any_conv, dim3(nb), dim3(U_BLOCK), 0, st, nullptr, j);
+  hipLaunchKernelGGL(k_prep, dim3(nb), dim3(U_BLOCK), 0, st, nullptr, j);
+  hipError_t e = launch_cluster(st, N, K, W, cw, tau, j.ctl, counts_host);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sizes, dim3(nb), dim3(U_BLOCK), 0, st, nullptr, j);
+  hipLaunchKernelGGL(k_finalize, dim3(64), dim3(128), 0, st, nullptr, j);
+  e = hipMemcpyAsync(counts_host, j.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+size_t unique_batched_workspace_bytes(int D, const UJob *jobs) {
+  size_t b = 2 * (((size_t)D * sizeof(UJob) + 255) & ~(size_t)255) + (size_t)D * 4 * sizeof(int) + 512;
+  for (int d = 0; d < D; ++d) b += unique_workspace_bytes(jobs[d].K, jobs[d].N) + 256;
+  return b;
+}
+
+// Many problems: the per-row kernels cover every problem in one launch
+// (blockIdx.y = problem), the problems small enough for one work-group are
+// clustered in one launch, the others round by round one after another.
+// jobs: host table with the problem fields set; counts_host: D x 4 ints
+// ([1] clusters, [3] accepted per problem).  Synchronises.
+hipError_t launch_unique_batched(hipStream_t st, int D, UJob *jobs, void *ws, int *counts_host) {
   char *p = (char *)ws;
   auto take = [&](size_t bytes) {
     char *r = p;
     p += (bytes + 255) & ~(size_t)255;
     return r;
   };
-  UniqueWs w;
-  w.key = (double *)take((size_t)K * 8);
-  w.cluster = (int *)take((size_t)K * 4);
-  w.part_idx = (int *)take((size_t)nb * 4);
-  w.reps = (int *)take((size_t)(K + 1) * 4);
-  w.sizes = (int *)take((size_t)K * 4);
-  w.ctl = counts_dev;  // 4 ints, zeroed by the caller
-
-  hipLaunchKernelGGL(k_any_conv, dim3(nb), dim3(U_BLOCK), 0, st, K, status, w.ctl);
-  hipLaunchKernelGGL(k_prep, dim3(nb), dim3(U_BLOCK), 0, st, K, kurt, status, w.ctl, w.key,
-                     w.cluster, w.sizes);
-  hipError_t e = launch_cluster(st, N, K, W, w.key, w.cluster, w.reps, w.part_idx, tau, w.ctl,
-                                counts_host);
+  UJob *jobs_dev = (UJob *)take((size_t)D * sizeof(UJob));
+  ClusterJob *cjobs_dev = (ClusterJob *)take((size_t)D * sizeof(UJob));
+  int *ctl = (int *)take((size_t)D * 4 * sizeof(int));
+  int k_max = 1;
+  std::vector<ClusterJob> small;
+  std::vector<ClusterWs> cws(D);
+  for (int d = 0; d < D; ++d) {
+    cws[d] = carve_ujob(jobs[d], take(unique_workspace_bytes(jobs[d].K, jobs[d].N)));
+    jobs[d].ctl = ctl + 4 * d;
+    k_max = std::max(k_max, jobs[d].K);
+    if (cluster_in_one_wg(jobs[d].K, true))
+      small.push_back(ClusterJob{jobs[d].K, jobs[d].N, jobs[d].W, jobs[d].Wt, jobs[d].key,
+                                 jobs[d].cluster, jobs[d].reps, jobs[d].ctl});
+  }
+  hipError_t e = hipMemsetAsync(ctl, 0, (size_t)D * 4 * sizeof(int), st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sizes, dim3(nb), dim3(U_BLOCK), 0, st, K, w.cluster, w.sizes, row_cluster);
-  hipLaunchKernelGGL(k_finalize, dim3(64), dim3(128), 0, st, N, (long long)T, W, kurt, w.key,
-                     w.reps, w.sizes, gtest, n_top, cap, U, kurt_u, ups_u, rep_thread,
-                     cluster_size, w.ctl);
-  e = hipMemcpyAsync(counts_host, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+  e = hipMemcpyAsync(jobs_dev, jobs, (size_t)D * sizeof(UJob), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if (!small.empty()) {
+    e = hipMemcpyAsync(cjobs_dev, small.data(), small.size() * sizeof(ClusterJob),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamSynchronize(st);  // the host tables may go out of scope
+  if (e != hipSuccess) return e;
+  const int nb = (k_max + U_BLOCK - 1) / U_BLOCK;
+  const UJob none{};
+  hipLaunchKernelGGL(k_any_conv, dim3(nb, D), dim3(U_BLOCK), 0, st, jobs_dev, none);
+  hipLaunchKernelGGL(k_prep, dim3(nb, D), dim3(U_BLOCK), 0, st, jobs_dev, none);
+  if (!small.empty()) {
+    e = launch_cluster_wg(st, (int)small.size(), cjobs_dev, small[0], jobs[0].tau);
+    if (e != hipSuccess) return e;
+  }
+  for (int d = 0; d < D; ++d)
+    if (!cluster_in_one_wg(jobs[d].K, true)) {
+      e = launch_cluster(st, jobs[d].N, jobs[d].K, jobs[d].W, cws[d], jobs[d].tau, jobs[d].ctl,
+                         counts_host);
+      if (e != hipSuccess) return e;
+    }
+  hipLaunchKernelGGL(k_sizes, dim3(nb, D), dim3(U_BLOCK), 0, st, jobs_dev, none);
+  hipLaunchKernelGGL(k_finalize, dim3(64, D), dim3(128), 0, st, jobs_dev, none);
+  e = hipMemcpyAsync(counts_host, ctl, (size_t)D * 4 * sizeof(int), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;

@@ -71,6 +71,14 @@ class BatchStats(C.Structure):
                 ("wk64", C.c_int), ("tuned", C.c_int), ("update_flops", C.c_double)]
 
 
+class UniqueProblem(C.Structure):
+    _fields_ = [("N", C.c_int), ("T", C.c_int64), ("K", C.c_int), ("W", C.c_void_p),
+                ("kurt", C.c_void_p), ("status", C.c_void_p), ("cap", C.c_int),
+                ("U", C.c_void_p), ("kurt_u", C.c_void_p), ("ups_u", C.c_void_p),
+                ("rep_thread", C.c_void_p), ("cluster_size", C.c_void_p),
+                ("row_cluster", C.c_void_p), ("n_unique", C.c_int), ("n_accepted", C.c_int)]
+
+
 class UniqueParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("gaussianity_test", C.c_int), ("n_top", C.c_int)]
 
@@ -104,6 +112,8 @@ _SIGS = {
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
                               C.c_int, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int),
                               C.POINTER(C.c_int)]),
+    "oica_unique_batched": (C.c_int, [_P, C.c_int, C.POINTER(UniqueProblem),
+                                      C.POINTER(UniqueParams)]),
 }
 
 
@@ -263,7 +273,8 @@ class Context:
 
     def fixed_point_batched(self, problems, max_iter=1000, tol=1e-6, precision="f32",
                             tol_bf16=1e-5, refine_iters=5, check_every=4, profile=False,
-                            autotune=True, cache_path=None, force_wk=0, force_grid=0):
+                            autotune=True, cache_path=None, force_wk=0, force_grid=0,
+                            refine_groups=True):
         """problems: list of dicts with device tensors Xw (N x T), W0 (K x N float32) and,
         for BF16 data, Xw_f32.  Returns (list of per-problem outputs, stats dict)."""
         D = len(problems)
@@ -287,7 +298,7 @@ class Context:
             outs.append(o)
         xw_t = OICA_BF16 if precision == "bf16" else OICA_F32
         p = FpParams(max_iter, tol, xw_t, tol_bf16, refine_iters, 0, check_every,
-                     1 if profile else 0, 0, None, 0, 0, 0)
+                     1 if profile else 0, 1 if refine_groups else 0, None, 0, 0, 0)
         bp = BatchParams(1 if autotune else 0, cache_path.encode() if cache_path else None,
                          force_wk, force_grid)
         st = BatchStats()
@@ -345,6 +356,37 @@ class Context:
         if row_cluster:
             out["row_cluster"] = rc_rows
         return out
+
+    def unique_batched(self, items, tau=1e-3, gaussianity_test=True, n_top=0, row_cluster=False):
+        """items: list of (W, kurt, status, T).  Returns a list of dicts as unique() does."""
+        D = len(items)
+        arr = (UniqueProblem * D)()
+        dev = self._tdev()
+        outs = []
+        for d, (W, kurt, status, T) in enumerate(items):
+            _dev(W, "W")
+            K, N = W.shape
+            o = {"U": torch.empty((K, N), dtype=torch.float64, device=dev),
+                 "alpha": torch.empty(K, dtype=torch.float64, device=dev),
+                 "upsilon": torch.empty(K, dtype=torch.float64, device=dev),
+                 "rep": torch.empty(K, dtype=torch.int32, device=dev),
+                 "size": torch.empty(K, dtype=torch.int32, device=dev)}
+            if row_cluster:
+                o["row_cluster"] = torch.empty(K, dtype=torch.int32, device=dev)
+            arr[d] = UniqueProblem(N, T, K, _ptr(W), _ptr(kurt), _ptr(status), K, _ptr(o["U"]),
+                                   _ptr(o["alpha"]), _ptr(o["upsilon"]), _ptr(o["rep"]),
+                                   _ptr(o["size"]), _ptr(o.get("row_cluster")), 0, 0)
+            outs.append(o)
+        p = UniqueParams(tau, 1 if gaussianity_test else 0, n_top)
+        rc = self.lib.oica_unique_batched(self.h, D, arr, C.byref(p))
+        self._check(rc)
+        for d, o in enumerate(outs):
+            n = arr[d].n_unique
+            for k in ("U", "alpha", "upsilon", "rep", "size"):
+                o[k] = o[k][:n]
+            o["n_unique"] = n
+            o["n_accepted"] = arr[d].n_accepted
+        return outs
 
 
 class Pruner:
@@ -430,7 +472,7 @@ def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_
 
 def ordering_ica_batched(ctx: Context, Xs, W0s, tol=1e-6, max_iter=1000, tau=1e-3,
                          gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
-                         profile=False, autotune=True, cache_path=None):
+                         profile=False, autotune=True, cache_path=None, refine_groups=True):
     """Whole hot path for many device-resident raw datasets: whiten each, one
     batched fixed point over all of them, unique set of each.  Returns (list of
     per-dataset results as from ordering_ica, batched stats)."""
@@ -441,11 +483,11 @@ def ordering_ica_batched(ctx: Context, Xs, W0s, tol=1e-6, max_iter=1000, tau=1e-
         wh.append((V, mean, eig))
     outs, st = ctx.fixed_point_batched(probs, max_iter=max_iter, tol=tol, precision=precision,
                                        tol_bf16=tol_bf16, refine_iters=refine_iters,
-                                       profile=profile, autotune=autotune, cache_path=cache_path)
-    res = []
-    for X, o, (V, mean, eig) in zip(Xs, outs, wh):
-        r = ctx.unique(o["W"], o["kurt"], o["status"], X.shape[1], tau=tau,
-                       gaussianity_test=gaussianity_test)
+                                       profile=profile, autotune=autotune, cache_path=cache_path,
+                                       refine_groups=refine_groups)
+    res = ctx.unique_batched([(o["W"], o["kurt"], o["status"], X.shape[1])
+                              for X, o in zip(Xs, outs)], tau=tau,
+                             gaussianity_test=gaussianity_test)
+    for r, o, (V, mean, eig) in zip(res, outs, wh):
         r.update(fp=o, V=V, mean=mean, eig=eig)
-        res.append(r)
     return res, st

@@ -79,6 +79,14 @@ def test_batched_equals_alone_and_shape_independent(ctx, small_batch):
         for k in ("W", "kurt", "iters", "status"):
             assert torch.equal(outs[d][k], alone[0][k]), (d, k)
             assert torch.equal(outs[d][k], outs1[d][k]), (d, k, "wk")
+    # BF16 with the grouped FP32 finish: also independent of the batch
+    dev16 = _dev16(probs, dev_in)
+    o16, _ = ctx.fixed_point_batched(dev16, tol=1e-6, precision="bf16", autotune=False, force_wk=2)
+    for d in (0, 3, 6):
+        alone, _ = ctx.fixed_point_batched([dev16[d]], tol=1e-6, precision="bf16", autotune=False,
+                                           force_wk=2)
+        for k in ("W", "kurt", "iters", "status"):
+            assert torch.equal(o16[d][k], alone[0][k]), (d, k, "bf16")
 
 
 def test_tuner_cache_round_trip(ctx, small_batch, tmp_path):
@@ -121,14 +129,18 @@ def _compare_stable(ctx, a, b, T, label):
     assert abs(na - nb) <= small, (label, na, nb, small)
 
 
-def test_bf16_batched_matches_f32_batched(ctx, small_batch):
+def _dev16(probs, dev_in):
+    return [{"Xw": q["Xw"].to(torch.bfloat16).contiguous(), "Xw_f32": q["Xw"], "W0": q["W0"]}
+            for (p, X32), q in zip(probs, dev_in)]
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+def test_bf16_batched_matches_f32_batched(ctx, small_batch, grouped):
     probs, dev_in = small_batch
-    dev16 = []
-    for (p, X32), q in zip(probs, dev_in):
-        dev16.append({"Xw": q["Xw"].to(torch.bfloat16).contiguous(), "Xw_f32": q["Xw"],
-                      "W0": q["W0"]})
+    dev16 = _dev16(probs, dev_in)
     o32, _ = ctx.fixed_point_batched(dev_in, tol=1e-6, autotune=False)
-    o16, s16 = ctx.fixed_point_batched(dev16, tol=1e-6, precision="bf16", autotune=False)
+    o16, s16 = ctx.fixed_point_batched(dev16, tol=1e-6, precision="bf16", autotune=False,
+                                       refine_groups=grouped)
     assert s16["refine_thread_iters"] > 0
     for (p, X32), a, b in zip(probs, o32, o16):
         _compare_stable(ctx, a, b, p.T, f"N={p.N} T={p.T}")

@@ -319,6 +319,48 @@ def test_unique_fallback_and_cap(ctx):
     assert res["n_accepted"] == 1
 
 
+def test_unique_round_by_round_path(ctx):
+    """K N above the one-work-group limit: the round-by-round kernels, against the oracle."""
+    B, labels = _planted(seed=7, N=32, n_clusters=20, per=1000)
+    K = len(labels)
+    rng = np.random.default_rng(4)
+    alpha = 6.0 - 0.25 * labels + 1e-6 * rng.standard_normal(K)
+    status = np.full(K, ica.CONV, np.uint8)
+    B32 = B.astype(np.float32)
+    ref = ica.unique(B32.astype(np.float64), alpha, status, 5000, tau=1e-3, gaussianity_test=True)
+    res = ctx.unique(dev(B32), dev(alpha), dev(status), 5000, tau=1e-3)
+    assert K * 32 > (1 << 19)
+    assert res["n_unique"] == len(ref["U"]) == 20
+    assert res["n_accepted"] == ref["n_accepted"]
+    assert np.array_equal(host(res["rep"]), ref["rep"])
+    assert np.array_equal(host(res["size"]), ref["size"])
+    assert np.array_equal(host(res["U"]), ref["U"])
+
+
+def test_unique_batched_equals_single(ctx):
+    """One batched call gives every problem exactly the single call's result
+    (small problems in the one-work-group kernel, the large one round by round)."""
+    items = []
+    for i, (N, nc, per) in enumerate([(12, 9, 40), (6, 3, 5), (32, 20, 1000), (64, 30, 30),
+                                      (128, 10, 100)]):
+        B, labels = _planted(seed=20 + i, N=N, n_clusters=nc, per=per)
+        K = len(labels)
+        rng = np.random.default_rng(i)
+        alpha = 5.0 - 0.1 * labels + 1e-6 * rng.standard_normal(K)
+        status = np.full(K, ica.CONV, np.uint8)
+        status[rng.choice(K, K // 10, replace=False)] = ica.NOTCONV
+        if i == 1:
+            status[:] = ica.NOTCONV   # nothing converged: every row is a candidate
+        items.append((dev(B.astype(np.float32)), dev(alpha), dev(status), 40 * N))
+    for gtest in (True, False):
+        outs = ctx.unique_batched(items, gaussianity_test=gtest, row_cluster=True)
+        for it, o in zip(items, outs):
+            ref = ctx.unique(*it, gaussianity_test=gtest, row_cluster=True)
+            assert o["n_unique"] == ref["n_unique"] and o["n_accepted"] == ref["n_accepted"]
+            for k in ("U", "alpha", "upsilon", "rep", "size", "row_cluster"):
+                assert torch.equal(o[k], ref[k]), k
+
+
 # ---- end to end on raw data ------------------------------------------------------------
 
 def _compare_unique(res, ref, V_gpu, tie_rel=1e-5):
