@@ -245,6 +245,7 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int BT = 64;          // samples per LDS tile
 constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
 template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
@@ -306,22 +307,34 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       for (int nb = 0; nb < NP / 32; ++nb) gacc[w][nb] = f32x16{0.f};
     }
 
-    // X tiles go through registers (8 consecutive samples of one feature row
-    // per load; one tile ahead with PF) and are staged into both LDS layouts.
-    constexpr int F8 = NP * BT / 8 / (WAVES * 64);
-    bf16x8 pre[F8];
+    // X tiles go through registers, one tile ahead with PF.  A staging unit is
+    // one feature pair (2p, 2p+1) over 8 consecutive samples (two 16-byte
+    // loads); pairs vary fastest across lanes, so both LDS layouts are written
+    // without bank conflicts: xs rows with 16-byte stores, xt with one 32-bit
+    // store per sample holding the pair.
+    constexpr int PAIRS = NP / 2;
+    constexpr int UNITS = PAIRS * (BT / 8);
+    constexpr int F8 = (UNITS + WAVES * 64 - 1) / (WAVES * 64);
+    bf16x8 pre0[F8], pre1[F8];
     auto fetch = [&](long long mt) {
 #pragma unroll
       for (int q = 0; q < F8; ++q) {
-        const int e = tid + q * WAVES * 64;
-        const int n = e / (BT / 8);
-        const long long gm = mt + (e % (BT / 8)) * 8;
-        const __bf16 *src = X + (size_t)n * (size_t)T + (size_t)gm;
-        if (n < N && vec_ok && gm + 8 <= t_end) {
-          pre[q] = *reinterpret_cast<const bf16x8 *>(src);
+        const int u = tid + q * WAVES * 64;
+        const int pp = u % PAIRS, c = u / PAIRS;
+        const long long gm = mt + c * 8;
+        const int n0 = 2 * pp;
+        const __bf16 *src0 = X + (size_t)n0 * (size_t)T + (size_t)gm;
+        const __bf16 *src1 = src0 + (size_t)T;
+        if (u < UNITS && n0 + 1 < N && vec_ok && gm + 8 <= t_end) {
+          pre0[q] = *reinterpret_cast<const bf16x8 *>(src0);
+          pre1[q] = *reinterpret_cast<const bf16x8 *>(src1);
         } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) pre[q][j] = (n < N && gm + j < t_end) ? src[j] : (__bf16)0.f;
+          for (int j = 0; j < 8; ++j) {
+            const bool in = u < UNITS && gm + j < t_end;
+            pre0[q][j] = (in && n0 < N) ? src0[j] : (__bf16)0.f;
+            pre1[q][j] = (in && n0 + 1 < N) ? src1[j] : (__bf16)0.f;
+          }
         }
       }
     };
@@ -331,12 +344,19 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       if constexpr (!PF) fetch(m_tile);
 #pragma unroll
       for (int q = 0; q < F8; ++q) {
-        const int e = tid + q * WAVES * 64;
-        const int n = e / (BT / 8);
-        const int mc = (e % (BT / 8)) * 8;
-        *reinterpret_cast<bf16x8 *>(&xs[n * BSX + mc]) = pre[q];
+        const int u = tid + q * WAVES * 64;
+        if (u < UNITS) {
+          const int pp = u % PAIRS, c = u / PAIRS;
+          *reinterpret_cast<bf16x8 *>(&xs[(2 * pp) * BSX + c * 8]) = pre0[q];
+          *reinterpret_cast<bf16x8 *>(&xs[(2 * pp + 1) * BSX + c * 8]) = pre1[q];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xt[(mc + j) * XTS + n] = pre[q][j];
+          for (int j = 0; j < 8; ++j) {
+            bf16x2 two;
+            two[0] = pre0[q][j];
+            two[1] = pre1[q][j];
+            *reinterpret_cast<bf16x2 *>(&xt[(c * 8 + j) * XTS + 2 * pp]) = two;
+          }
+        }
       }
       __syncthreads();
       if constexpr (PF)
