@@ -25,7 +25,8 @@ namespace oica {
 
 constexpr int BATCH_SPLIT = 4096;   // samples per split in the batched form
 constexpr int MAX_D = 1024;         // datasets per call
-constexpr int BUF_BYTES = 36 * 1024;
+constexpr int BUF_BYTES_F32 = 36 * 1024;
+constexpr int BUF_BYTES_BF16 = 2 * (128 * BSX + BT * (128 + 8)) * 2;  // two BF16 buffers at NP = 128
 
 int batch_splits(int64_t T) {
   int64_t s = (T + BATCH_SPLIT / 2) / BATCH_SPLIT;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
                                                                  int D, BatchCtl *bctl,
                                                                  const int *__restrict__ item_start,
                                                                  int pass) {
-  __shared__ __attribute__((aligned(16))) char buf[BUF_BYTES];
+  __shared__ __attribute__((aligned(16))) char buf[BF16 ? BUF_BYTES_BF16 : BUF_BYTES_F32];
   __shared__ int s_start[MAX_D + 1];
   __shared__ int s_item;
   for (int d = threadIdx.x; d <= D; d += blockDim.x) s_start[d] = item_start[d];
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
       }
     } else {
       __bf16 *xs16 = reinterpret_cast<__bf16 *>(buf);
-      __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 18432);
+      __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 2 * 128 * BSX * 2);
       switch (b.variant) {
         case 8: call_bf16<32, 1>(c, kb, sp, xs16, xt16); break;
         case 9: call_bf16<32, 2>(c, kb, sp, xs16, xt16); break;

@@ -97,8 +97,8 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
     float *__restrict__ gpart, float *__restrict__ s4part, FpControl *ctl, int pass) {
   constexpr int KWG = WAVES * WK * 32;
   constexpr int XTS = BfStride<NP>::v;
-  __shared__ __attribute__((aligned(16))) __bf16 xs[NP * BSX];
-  __shared__ __attribute__((aligned(16))) __bf16 xt[BT * XTS];
+  __shared__ __attribute__((aligned(16))) __bf16 xs[2 * BfTile<NP>::xs_elems];
+  __shared__ __attribute__((aligned(16))) __bf16 xt[2 * BfTile<NP>::xt_elems];
 
   const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
   if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {

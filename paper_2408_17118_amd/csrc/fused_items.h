@@ -249,10 +249,16 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int BT = 64;          // samples per LDS tile
 constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
 template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
+// one LDS buffer of the BF16 item: xs (NP x BSX) and xt (BT x (NP + 8)); the
+// item uses two of each
+template <int NP> struct BfTile {
+  static constexpr int xs_elems = NP * BSX;
+  static constexpr int xt_elems = BT * BfStride<NP>::v;
+};
 
-template <int NP, int WK, bool PF = true>
-__device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs,
-                                          __bf16 *xt) {
+template <int NP, int WK>
+__device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs_base,
+                                          __bf16 *xt_base) {
   constexpr int KWG = WAVES * WK * 32;
   constexpr int XTS = BfStride<NP>::v;
   const __bf16 *__restrict__ X = (const __bf16 *)c.X;
@@ -338,10 +344,9 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
         }
       }
     };
-    if constexpr (PF) fetch(t_begin);
-    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT) {
-      __syncthreads();
-      if constexpr (!PF) fetch(m_tile);
+    auto stage = [&](int b) {
+      __bf16 *xs = xs_base + b * BfTile<NP>::xs_elems;
+      __bf16 *xt = xt_base + b * BfTile<NP>::xt_elems;
 #pragma unroll
       for (int q = 0; q < F8; ++q) {
         const int u = tid + q * WAVES * 64;
@@ -358,9 +363,19 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
           }
         }
       }
-      __syncthreads();
-      if constexpr (PF)
-        if (m_tile + BT < t_end) fetch(m_tile + BT);
+    };
+    // Two LDS buffers: tile i is computed from buffer i % 2 while tile i + 1
+    // (already in registers) is written to the other; one barrier per tile.
+    // The caller's previous use of the buffers must be finished: barrier first.
+    __syncthreads();
+    fetch(t_begin);
+    stage(0);
+    __syncthreads();
+    if (t_begin + BT < t_end) fetch(t_begin + BT);
+    int cur = 0;
+    for (long long m_tile = t_begin; m_tile < t_end; m_tile += BT, cur ^= 1) {
+      const __bf16 *xs = xs_base + cur * BfTile<NP>::xs_elems;
+      const __bf16 *xt = xt_base + cur * BfTile<NP>::xt_elems;
 #pragma unroll
       for (int sub = 0; sub < BT / 32; ++sub) {
         if (m_tile + sub * 32 >= t_end) break;
@@ -404,6 +419,9 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
           }
         }
       }
+      if (m_tile + BT < t_end) stage(cur ^ 1);
+      __syncthreads();
+      if (m_tile + 2 * BT < t_end) fetch(m_tile + 2 * BT);
     }
 
 #pragma unroll
