@@ -247,7 +247,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int BT = 64;          // samples per LDS tile
-constexpr int BSX = BT + 8;     // xs row stride (bf16): 144 bytes, 16-byte aligned
+// xs row stride (bf16): 136 bytes = 34 banks, so the 8-byte GEMM2 operand
+// reads of 32 consecutive rows hit 32 distinct bank pairs; rows are written
+// with 8-byte stores (8-byte aligned)
+constexpr int BSX = BT + 4;
 template <int NP> struct BfStride { static constexpr int v = NP + 8; };  // xt row stride
 // one LDS buffer of the BF16 item: xs (NP x BSX) and xt (BT x (NP + 8)); the
 // item uses two of each
@@ -352,8 +355,12 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
         const int u = tid + q * WAVES * 64;
         if (u < UNITS) {
           const int pp = u % PAIRS, c = u / PAIRS;
-          *reinterpret_cast<bf16x8 *>(&xs[(2 * pp) * BSX + c * 8]) = pre0[q];
-          *reinterpret_cast<bf16x8 *>(&xs[(2 * pp + 1) * BSX + c * 8]) = pre1[q];
+          bf16x4 *r0 = reinterpret_cast<bf16x4 *>(&xs[(2 * pp) * BSX + c * 8]);
+          bf16x4 *r1 = reinterpret_cast<bf16x4 *>(&xs[(2 * pp + 1) * BSX + c * 8]);
+          r0[0] = pre0[q].lo;
+          r0[1] = pre0[q].hi;
+          r1[0] = pre1[q].lo;
+          r1[1] = pre1[q].hi;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             bf16x2 two;
