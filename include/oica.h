@@ -208,6 +208,8 @@ typedef struct {         /* host */
  * W0: K x N FP32 (rows need not be normalised; a zero row ends DEGENERATE).
  * Outputs, all K rows in the original row order: W_out K x N FP32 unit rows,
  * kurt K FP64, iters K int32 (updates applied to the row), status K uint8.
+ * In BF16 mode with refine_groups, rows left PRUNED take no kurtosis pass:
+ * their kurt is NaN (they are never candidates of oica_unique).
  * traj may be NULL when traj_iters == 0; stats (host) may be NULL.
  * Synchronises (the active count is polled on the host).
  * Errors: OICA_E_ARG, OICA_E_UNSUPPORTED, OICA_E_NOMEM, OICA_E_DEVICE. */

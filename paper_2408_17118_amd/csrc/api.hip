@@ -447,7 +447,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
                                    ctx->small_host, &cluster, &reps));
         FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
         HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, ctx->small_dev + 1, status,
-                                        act2, ctl2, left_list, left_rows, kurt_list, ctl3));
+                                        kurt, act2, ctl2, left_list, left_rows, kurt_list, ctl3));
         if (fp32_passes > 0) {
           rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
                           ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
@@ -1021,8 +1021,9 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       const int left = parked ? park_count[d] : c->kact[launched & 1];
       if (grouped)
         HIP_TRY(ctx, launch_group_lists(ctx->stream, b.K, gjobs[d].cluster, gjobs[d].reps,
-                                        gjobs[d].ctl + 1, b.status, act2[d], c2, left_list, left,
-                                        kurt_list[d], (FpControl *)((char *)c2 + 128)));
+                                        gjobs[d].ctl + 1, b.status, pr[d].kurt, act2[d], c2,
+                                        left_list, left, kurt_list[d],
+                                        (FpControl *)((char *)c2 + 128)));
       else
         HIP_TRY(ctx, launch_refine_select(ctx->stream, b.K, b.status, act2[d], c2, left_list, left));
       int *old0 = b.act0;

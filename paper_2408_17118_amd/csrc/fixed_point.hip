@@ -188,69 +188,75 @@ __global__ __launch_bounds__(256) void k_epilogue(
   constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
   const int lane = threadIdx.x % 64;
-  const int posn = blockIdx.x * 4 + threadIdx.x / 64;
-  if (posn >= kact) return;
+  // EPI_ROWS rows per wave, one after the other; the rows that stay active
+  // are appended with one atomic per wave
+  const int posn0 = (blockIdx.x * 4 + threadIdx.x / 64) * EPI_ROWS;
+  if (posn0 >= kact) return;  // uniform over the wave
   const int n_kb = (kact + plan.kwg - 1) / plan.kwg;
   const int n_sp = plan_splits(plan, n_kb);
   const int groups = (n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
-  const int row = act_cur[posn];
-
   const int n0 = lane, n1 = lane + 64;
-  double g0 = 0.0, g1 = 0.0, s4 = 0.0;
-  // second stage: group sums in group order, EPI_U loads in flight per lane
-  constexpr int EPI_U = 8;
-  for (int q0 = 0; q0 < groups; q0 += EPI_U) {
-    double v0[EPI_U], v1[EPI_U], v4[EPI_U];
-#pragma unroll
-    for (int u = 0; u < EPI_U; ++u) {
-      const int q = q0 + u;
-      const bool ok = q < groups;
-      const double *src = red + ((size_t)(ok ? q : 0) * kact + posn) * RS;
-      v0[u] = (ok && n0 < NP) ? src[n0] : 0.0;
-      v1[u] = (ok && n1 < NP) ? src[n1] : 0.0;
-      v4[u] = (ok && lane == 0) ? src[NP] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < EPI_U; ++u) {
-      g0 += v0[u];
-      g1 += v1[u];
-      s4 += v4[u];
-    }
-  }
-  float *brow = Bm + (size_t)row * N;
-  const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
-  const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
   const double invT = 1.0 / (double)T;
-  g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
-  g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
-  const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
-  s4 = __shfl(s4, 0);
-  const double alpha = s4 * invT - 3.0;
-  double d;
-  if (!(gn > 0.0) || !isfinite(gn)) {
-    d = NAN;
-    if (lane == 0) status[row] = OICA_ROW_DEGENERATE;
-  } else {
-    const double b0 = g0 / gn, b1 = g1 / gn;
-    const double dm = wave_sum((b0 - bp0) * (b0 - bp0) + (b1 - bp1) * (b1 - bp1));
-    const double dp = wave_sum((b0 + bp0) * (b0 + bp0) + (b1 + bp1) * (b1 + bp1));
-    d = sqrt(dm < dp ? dm : dp);
-    if (n0 < N) brow[n0] = (float)b0;
-    if (n1 < N) brow[n1] = (float)b1;
-    if (lane == 0) {
-      iters[row] += 1;
-      if (d < tol) {
-        status[row] = OICA_ROW_CONV;
-      } else {
-        const int slot = atomicAdd(&ctl->kact[(pass + 1) & 1], 1);
-        act_next[slot] = row;
+  bool stay = false;
+  int stay_row = -1;
+  for (int r = 0; r < EPI_ROWS && posn0 + r < kact; ++r) {
+    const int posn = posn0 + r;
+    const int row = act_cur[posn];
+    double g0 = 0.0, g1 = 0.0, s4 = 0.0;
+    // second stage: group sums in group order, EPI_U loads in flight per lane
+    constexpr int EPI_U = 8;
+    for (int q0 = 0; q0 < groups; q0 += EPI_U) {
+      double v0[EPI_U], v1[EPI_U], v4[EPI_U];
+#pragma unroll
+      for (int u = 0; u < EPI_U; ++u) {
+        const int q = q0 + u;
+        const bool ok = q < groups;
+        const double *src = red + ((size_t)(ok ? q : 0) * kact + posn) * RS;
+        v0[u] = (ok && n0 < NP) ? src[n0] : 0.0;
+        v1[u] = (ok && n1 < NP) ? src[n1] : 0.0;
+        v4[u] = (ok && lane == 0) ? src[NP] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < EPI_U; ++u) {
+        g0 += v0[u];
+        g1 += v1[u];
+        s4 += v4[u];
       }
     }
+    float *brow = Bm + (size_t)row * N;
+    const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
+    const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
+    g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
+    g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+    const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
+    s4 = __shfl(s4, 0);
+    const double alpha = s4 * invT - 3.0;
+    double d;
+    if (!(gn > 0.0) || !isfinite(gn)) {
+      d = NAN;
+      if (lane == 0) status[row] = OICA_ROW_DEGENERATE;
+    } else {
+      const double b0 = g0 / gn, b1 = g1 / gn;
+      const double dm = wave_sum((b0 - bp0) * (b0 - bp0) + (b1 - bp1) * (b1 - bp1));
+      const double dp = wave_sum((b0 + bp0) * (b0 + bp0) + (b1 + bp1) * (b1 + bp1));
+      d = sqrt(dm < dp ? dm : dp);
+      if (n0 < N) brow[n0] = (float)b0;
+      if (n1 < N) brow[n1] = (float)b1;
+      if (lane == 0) {
+        iters[row] += 1;
+        if (d < tol) status[row] = OICA_ROW_CONV;
+      }
+      if (lane == r && !(d < tol)) {
+        stay = true;
+        stay_row = row;
+      }
+    }
+    if (lane == 0 && pass < traj_iters) {
+      traj[((size_t)row * traj_iters + pass) * 2 + 0] = (float)alpha;
+      traj[((size_t)row * traj_iters + pass) * 2 + 1] = (float)d;
+    }
   }
-  if (lane == 0 && pass < traj_iters) {
-    traj[((size_t)row * traj_iters + pass) * 2 + 0] = (float)alpha;
-    traj[((size_t)row * traj_iters + pass) * 2 + 1] = (float)d;
-  }
+  wave_append(stay, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
 }
 
 // Row initialisation: normalise W0 in FP64, mark zero/non-finite rows
@@ -260,28 +266,32 @@ __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *_
                             int *__restrict__ act0, FpControl *ctl, float *__restrict__ traj,
                             int traj_iters) {
   const int lane = threadIdx.x % 64;
-  const int row = blockIdx.x * 4 + threadIdx.x / 64;
-  if (row >= K) return;
-  const float *src = W0 + (size_t)row * N;
-  const int n0 = lane, n1 = lane + 64;
-  const double w0 = n0 < N ? (double)src[n0] : 0.0;
-  const double w1 = n1 < N ? (double)src[n1] : 0.0;
-  const double nrm = sqrt(wave_sum(w0 * w0 + w1 * w1));
-  const bool ok = nrm > 0.0 && isfinite(nrm);
-  float *dst = Bm + (size_t)row * N;
-  if (n0 < N) dst[n0] = (float)(w0 / nrm);
-  if (n1 < N) dst[n1] = (float)(w1 / nrm);
-  for (int t = lane; t < 2 * traj_iters; t += 64) traj[(size_t)row * traj_iters * 2 + t] = NAN;
-  if (lane == 0) {
-    iters[row] = 0;
-    if (ok) {
-      status[row] = OICA_ROW_NOTCONV;
-      const int slot = atomicAdd(&ctl->kact[0], 1);
-      act0[slot] = row;
-    } else {
-      status[row] = OICA_ROW_DEGENERATE;
+  const int row0 = (blockIdx.x * 4 + threadIdx.x / 64) * EPI_ROWS;  // EPI_ROWS rows per wave
+  if (row0 >= K) return;  // uniform over the wave
+  bool take = false;
+  int take_row = -1;
+  for (int r = 0; r < EPI_ROWS && row0 + r < K; ++r) {
+    const int row = row0 + r;
+    const float *src = W0 + (size_t)row * N;
+    const int n0 = lane, n1 = lane + 64;
+    const double w0 = n0 < N ? (double)src[n0] : 0.0;
+    const double w1 = n1 < N ? (double)src[n1] : 0.0;
+    const double nrm = sqrt(wave_sum(w0 * w0 + w1 * w1));
+    const bool ok = nrm > 0.0 && isfinite(nrm);
+    float *dst = Bm + (size_t)row * N;
+    if (n0 < N) dst[n0] = (float)(w0 / nrm);
+    if (n1 < N) dst[n1] = (float)(w1 / nrm);
+    for (int t = lane; t < 2 * traj_iters; t += 64) traj[(size_t)row * traj_iters * 2 + t] = NAN;
+    if (lane == 0) {
+      iters[row] = 0;
+      status[row] = ok ? OICA_ROW_NOTCONV : OICA_ROW_DEGENERATE;
+    }
+    if (lane == r) {
+      take = ok;
+      take_row = row;
     }
   }
+  wave_append(take, take_row, act0, &ctl->kact[0]);
 }
 
 // Active set of the FP32 phase after a BF16 loop, built in `dst`: the rows that
@@ -290,11 +300,10 @@ __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *_
 __global__ void k_refine_select(int K, uint8_t *__restrict__ status, int *__restrict__ dst,
                                 FpControl *ctl, const int *__restrict__ left_list, int left) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < K && status[i] == OICA_ROW_CONV) {
-    status[i] = OICA_ROW_NOTCONV;
-    dst[atomicAdd(&ctl->kact[0], 1)] = i;
-  }
-  if (i < left) dst[atomicAdd(&ctl->kact[0], 1)] = left_list[i];
+  const bool conv = i < K && status[i] == OICA_ROW_CONV;
+  if (conv) status[i] = OICA_ROW_NOTCONV;
+  wave_append(conv, i, dst, &ctl->kact[0]);
+  wave_append(i < left, i < left ? left_list[i] : -1, dst, &ctl->kact[0]);
 }
 
 // Rows pruned earlier go back into the active set (status NOTCONV), their
@@ -302,11 +311,9 @@ __global__ void k_refine_select(int K, uint8_t *__restrict__ status, int *__rest
 __global__ void k_unprune(int K, uint8_t *__restrict__ status, int *__restrict__ list,
                           FpControl *ctl) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= K) return;
-  if (status[row] == OICA_ROW_PRUNED) {
-    status[row] = OICA_ROW_NOTCONV;
-    list[atomicAdd(&ctl->kact[0], 1)] = row;
-  }
+  const bool back = row < K && status[row] == OICA_ROW_PRUNED;
+  if (back) status[row] = OICA_ROW_NOTCONV;
+  wave_append(back, row, list, &ctl->kact[0]);
 }
 
 hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpControl *ctl) {
@@ -371,8 +378,8 @@ __global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__r
 hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
                             int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
                             float *traj, int traj_iters) {
-  hipLaunchKernelGGL(k_init_rows, dim3((K + 3) / 4), dim3(256), 0, st, K, N, W0, B, iters, status,
-                     act0, ctl, traj, traj_iters);
+  hipLaunchKernelGGL(k_init_rows, dim3((K + 4 * EPI_ROWS - 1) / (4 * EPI_ROWS)), dim3(256), 0, st,
+                     K, N, W0, B, iters, status, act0, ctl, traj, traj_iters);
   return hipGetLastError();
 }
 
@@ -407,7 +414,8 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
   OICA_NP_SWITCH(np, {
     hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
                        (const FpControl *)ctl, pass, gpart, s4part, red);
-    hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 3) / 4), dim3(256), 0, st, p, N,
+    hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 4 * EPI_ROWS - 1) / (4 * EPI_ROWS)),
+                       dim3(256), 0, st, p, N,
                        (long long)T, B, act_cur, act_next, ctl, pass, (const double *)red, tol,
                        iters, status, traj, traj_iters);
   });
@@ -453,20 +461,24 @@ hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
 // non-representative group member goes to kurt_list.
 __global__ void k_group_lists(int K, const int *__restrict__ cluster, const int *__restrict__ reps,
                               const int *__restrict__ n_groups_dev, uint8_t *__restrict__ status,
+                              double *__restrict__ kurt_out,
                               int *__restrict__ refine_list, FpControl *ctl_refine,
                               const int *__restrict__ left_list, int left,
                               int *__restrict__ kurt_list, FpControl *ctl_kurt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < *n_groups_dev) {
-    const int r = reps[i];
-    status[r] = OICA_ROW_NOTCONV;
-    refine_list[atomicAdd(&ctl_refine->kact[0], 1)] = r;
-  }
-  if (i < left) refine_list[atomicAdd(&ctl_refine->kact[0], 1)] = left_list[i];
+  const bool rep = i < *n_groups_dev;
+  const int r = rep ? reps[i] : -1;
+  if (rep) status[r] = OICA_ROW_NOTCONV;
+  wave_append(rep, r, refine_list, &ctl_refine->kact[0]);
+  wave_append(i < left, i < left ? left_list[i] : -1, refine_list, &ctl_refine->kact[0]);
+  bool kurt = false;
   if (i < K) {
     const int c = cluster[i];
-    if (c < 0 || reps[c] == i) kurt_list[atomicAdd(&ctl_kurt->kact[0], 1)] = i;
+    const bool pruned = status[i] == OICA_ROW_PRUNED;  // left pruned: no kurtosis
+    kurt = (c < 0 && !pruned) || (c >= 0 && reps[c] == i);
+    if (pruned) kurt_out[i] = NAN;
   }
+  wave_append(kurt, i, kurt_list, &ctl_kurt->kact[0]);
 }
 
 // Group members take their representative's refined row (with their own
@@ -495,12 +507,12 @@ __global__ void k_propagate(int K, int N, const int *__restrict__ cluster,
 }
 
 hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
-                              const int *n_groups_dev, uint8_t *status, int *refine_list,
-                              FpControl *ctl_refine, const int *left_list, int left, int *kurt_list,
-                              FpControl *ctl_kurt) {
+                              const int *n_groups_dev, uint8_t *status, double *kurt,
+                              int *refine_list, FpControl *ctl_refine, const int *left_list,
+                              int left, int *kurt_list, FpControl *ctl_kurt) {
   hipLaunchKernelGGL(k_group_lists, dim3((K + 255) / 256), dim3(256), 0, st, K, cluster, reps,
-                     n_groups_dev, status, refine_list, ctl_refine, left_list, left, kurt_list,
-                     ctl_kurt);
+                     n_groups_dev, status, kurt, refine_list, ctl_refine, left_list, left,
+                     kurt_list, ctl_kurt);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ constexpr int MIN_SUB = 8;      // each sample split covers >= 8 sub-tiles (256 
 constexpr int GRID = 1024;      // work-groups per fused launch (multiple of 8)
 constexpr int SPLIT_GROUP = SPLIT_GROUP_HOST;  // splits per first-stage reduction item
 constexpr int RED_GRID = 2048;  // work-groups of the first-stage reduction
+constexpr int EPI_ROWS = 16;    // rows per wave in the per-row passes (epilogue, init)
 
 // Everything one (row block, sample split) work item needs.
 struct ItemCtx {

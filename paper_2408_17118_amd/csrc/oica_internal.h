@@ -100,6 +100,19 @@ inline bool cluster_in_one_wg(int K, bool many) { return K <= (many ? CW_MAX_K :
 hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
                              const ClusterJob &one, double tau);
 
+// Appends `item` to list[] for every lane with `take`, with one atomic on
+// *counter per wave (lanes in lane order).  Every lane of the wave must call it.
+__device__ inline void wave_append(bool take, int item, int *list, int *counter) {
+  const unsigned long long mask = __ballot(take);
+  if (mask == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+}
+
 // whiten.hip
 struct JacJob {        // one symmetric eigenproblem of the Jacobi solver
   int N;
@@ -154,10 +167,11 @@ hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t 
 hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            const float *X, int K, const float *W, double *s4part64,
                            double *kurt, const int *act = nullptr, const int *kact_dev = nullptr);
+// kurt: rows left PRUNED get NaN (they take no kurtosis pass)
 hipError_t launch_group_lists(hipStream_t st, int K, const int *cluster, const int *reps,
-                              const int *n_groups_dev, uint8_t *status, int *refine_list,
-                              FpControl *ctl_refine, const int *left_list, int left, int *kurt_list,
-                              FpControl *ctl_kurt);
+                              const int *n_groups_dev, uint8_t *status, double *kurt,
+                              int *refine_list, FpControl *ctl_refine, const int *left_list,
+                              int left, int *kurt_list, FpControl *ctl_kurt);
 hipError_t launch_propagate(hipStream_t st, int K, int N, const int *cluster, const int *reps,
                             float *W, uint8_t *status, double *kurt);
 hipError_t launch_refine_select(hipStream_t st, int K, uint8_t *status, int *dst, FpControl *ctl,

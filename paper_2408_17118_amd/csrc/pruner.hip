@@ -99,17 +99,19 @@ __global__ __launch_bounds__(256) void k_prune(const __half *__restrict__ w16, F
   load_weights_lds(w16, sw);
   const int n = *count_dev;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int row = list[i];
-  float f[PF], h1[PH];
-  load_features(traj, traj_stride, row, nm, f);
-  const float p = sigmoidf_stable(mlp_logit(sw, f, h1));
-  if (p < theta) {
-    status[row] = OICA_ROW_PRUNED;
-    atomicAdd(pruned_count, 1);
-  } else {
-    keep[atomicAdd(keep_count, 1)] = row;
+  bool prune = false;
+  int row = -1;
+  if (i < n) {
+    row = list[i];
+    float f[PF], h1[PH];
+    load_features(traj, traj_stride, row, nm, f);
+    const float p = sigmoidf_stable(mlp_logit(sw, f, h1));
+    prune = p < theta;
+    if (prune) status[row] = OICA_ROW_PRUNED;
   }
+  const unsigned long long pm = __ballot(prune);
+  if (__lane_id() == 0 && pm) atomicAdd(pruned_count, __popcll(pm));
+  wave_append(i < n && !prune, row, keep, keep_count);
 }
 
 __global__ void k_prune_commit(int *__restrict__ list, int *count_dev, const int *__restrict__ keep,
