@@ -254,9 +254,12 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
   int stalled = 0;
   *launched = 0;
   *kernel_ms = 0.0;
+  const FusedPlan narrow = narrow_plan(plan);
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
+    // at most one narrow row block active: the narrow plan (same splits)
+    const FusedPlan &pp = (plan.kwg > narrow.kwg && kmax <= narrow.kwg) ? narrow : plan;
     if (profile) {
       while ((int)ctx->events.size() < 2 * (pass + 1)) {
         hipEvent_t e;
@@ -265,11 +268,11 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       }
       HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass], ctx->stream));
     }
-    HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
+    HIP_TRY(ctx, launch_fused_update(ctx->stream, pp, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
                                      gpart, s4part, ctl, pass));
     if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
     *launched = pass + 1;
-    HIP_TRY(ctx, launch_epilogue(ctx->stream, plan, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
+    HIP_TRY(ctx, launch_epilogue(ctx->stream, pp, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
                                  s4part, red, tol, iters, status, traj, traj_iters));
     if (pruner && pass + 1 == prune_pass) {
       // the list of pass prune_pass is nxt, its count kact[prune_pass & 1]

@@ -21,6 +21,22 @@ int fused_np(int N) { return ((N + 31) / 32) * 32; }
 
 static inline int wk_for_np(int np) { return np <= 64 ? 2 : 1; }
 
+// Rows per wave of the per-row passes: one while that leaves enough waves to
+// fill the chip, up to EPI_ROWS for large K (fewer list-append atomics).
+static int rows_per_wave(int kmax) {
+  int r = kmax / 8192;
+  return r < 1 ? 1 : (r > EPI_ROWS ? EPI_ROWS : r);
+}
+
+// The same plan with one 32-row block per wave: for passes with at most
+// WAVES * 32 active rows (one row block either way, so the same sample splits
+// and the same arithmetic per row, with half the padded rows).
+FusedPlan narrow_plan(const FusedPlan &p) {
+  FusedPlan q = p;
+  q.kwg = WAVES * 32;
+  return q;
+}
+
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
   (void)kmax;
   (void)bf16;
@@ -184,13 +200,13 @@ __global__ __launch_bounds__(256) void k_epilogue(
     FusedPlan plan, int N, long long T, float *__restrict__ Bm, const int *__restrict__ act_cur,
     int *__restrict__ act_next, FpControl *ctl, int pass, const double *__restrict__ red,
     double tol, int32_t *__restrict__ iters, uint8_t *__restrict__ status,
-    float *__restrict__ traj, int traj_iters) {
+    float *__restrict__ traj, int traj_iters, int rows_per_wave) {
   constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
   const int lane = threadIdx.x % 64;
-  // EPI_ROWS rows per wave, one after the other; the rows that stay active
-  // are appended with one atomic per wave
-  const int posn0 = (blockIdx.x * 4 + threadIdx.x / 64) * EPI_ROWS;
+  // rows_per_wave (<= EPI_ROWS) rows per wave, one after the other; the rows
+  // that stay active are appended with one atomic per wave
+  const int posn0 = (blockIdx.x * 4 + threadIdx.x / 64) * rows_per_wave;
   if (posn0 >= kact) return;  // uniform over the wave
   const int n_kb = (kact + plan.kwg - 1) / plan.kwg;
   const int n_sp = plan_splits(plan, n_kb);
@@ -199,7 +215,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
   const double invT = 1.0 / (double)T;
   bool stay = false;
   int stay_row = -1;
-  for (int r = 0; r < EPI_ROWS && posn0 + r < kact; ++r) {
+  for (int r = 0; r < rows_per_wave && posn0 + r < kact; ++r) {
     const int posn = posn0 + r;
     const int row = act_cur[posn];
     double g0 = 0.0, g1 = 0.0, s4 = 0.0;
@@ -264,13 +280,13 @@ __global__ __launch_bounds__(256) void k_epilogue(
 __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *__restrict__ Bm,
                             int32_t *__restrict__ iters, uint8_t *__restrict__ status,
                             int *__restrict__ act0, FpControl *ctl, float *__restrict__ traj,
-                            int traj_iters) {
+                            int traj_iters, int rpw) {
   const int lane = threadIdx.x % 64;
-  const int row0 = (blockIdx.x * 4 + threadIdx.x / 64) * EPI_ROWS;  // EPI_ROWS rows per wave
+  const int row0 = (blockIdx.x * 4 + threadIdx.x / 64) * rpw;  // rpw rows per wave
   if (row0 >= K) return;  // uniform over the wave
   bool take = false;
   int take_row = -1;
-  for (int r = 0; r < EPI_ROWS && row0 + r < K; ++r) {
+  for (int r = 0; r < rpw && row0 + r < K; ++r) {
     const int row = row0 + r;
     const float *src = W0 + (size_t)row * N;
     const int n0 = lane, n1 = lane + 64;
@@ -378,8 +394,9 @@ __global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__r
 hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
                             int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
                             float *traj, int traj_iters) {
-  hipLaunchKernelGGL(k_init_rows, dim3((K + 4 * EPI_ROWS - 1) / (4 * EPI_ROWS)), dim3(256), 0, st,
-                     K, N, W0, B, iters, status, act0, ctl, traj, traj_iters);
+  const int rpw = rows_per_wave(K);
+  hipLaunchKernelGGL(k_init_rows, dim3((K + 4 * rpw - 1) / (4 * rpw)), dim3(256), 0, st, K, N, W0,
+                     B, iters, status, act0, ctl, traj, traj_iters, rpw);
   return hipGetLastError();
 }
 
@@ -388,20 +405,31 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
                                int kact_host, float *gpart, float *s4part, FpControl *ctl,
                                int pass) {
   const int np = fused_np(N);
+  const bool wk1 = p.kwg == WAVES * 32;  // one 32-row block per wave (narrow plan)
   if (bf16) {
     OICA_NP_SWITCH(np, {
-      constexpr int WK_ = NP_ <= 64 ? 2 : 1;
-      hipLaunchKernelGGL((k_fused_bf16<NP_, WK_>), dim3(p.grid), dim3(WAVES * 64), 0, st,
-                         (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
-                         s4part, ctl, pass);
+      constexpr int WK2 = NP_ <= 64 ? 2 : 1;  // the wide variant
+      if (!wk1)
+        hipLaunchKernelGGL((k_fused_bf16<NP_, WK2>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                           (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,
+                           gpart, s4part, ctl, pass);
+      else
+        hipLaunchKernelGGL((k_fused_bf16<NP_, 1>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                           (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,
+                           gpart, s4part, ctl, pass);
     });
     return hipGetLastError();
   }
   OICA_NP_SWITCH(np, {
-    constexpr int WK_ = NP_ <= 64 ? 2 : 1;
-    hipLaunchKernelGGL((k_fused_f32<NP_, WK_, false>), dim3(p.grid), dim3(WAVES * 64), 0, st,
-                       (const float *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
-                       s4part, (double *)nullptr, ctl, pass);
+    constexpr int WK2 = NP_ <= 64 ? 2 : 1;  // the wide variant
+    if (!wk1)
+      hipLaunchKernelGGL((k_fused_f32<NP_, WK2, false>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                         (const float *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
+                         s4part, (double *)nullptr, ctl, pass);
+    else
+      hipLaunchKernelGGL((k_fused_f32<NP_, 1, false>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                         (const float *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
+                         s4part, (double *)nullptr, ctl, pass);
   });
   return hipGetLastError();
 }
@@ -414,10 +442,10 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
   OICA_NP_SWITCH(np, {
     hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
                        (const FpControl *)ctl, pass, gpart, s4part, red);
-    hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 4 * EPI_ROWS - 1) / (4 * EPI_ROWS)),
-                       dim3(256), 0, st, p, N,
-                       (long long)T, B, act_cur, act_next, ctl, pass, (const double *)red, tol,
-                       iters, status, traj, traj_iters);
+    const int rpw = rows_per_wave(kmax);
+    hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 4 * rpw - 1) / (4 * rpw)), dim3(256), 0,
+                       st, p, N, (long long)T, B, act_cur, act_next, ctl, pass,
+                       (const double *)red, tol, iters, status, traj, traj_iters, rpw);
   });
   return hipGetLastError();
 }

@@ -146,6 +146,7 @@ size_t whiten_workspace_bytes(int N, int64_t T);
 
 // fixed_point.hip
 int fused_np(int N);  // padded feature count used by the kernels for N
+FusedPlan narrow_plan(const FusedPlan &p);
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16);
 size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
 
@@ -219,11 +220,13 @@ struct UJob {          // one unique-components problem
   double *key;
   int *cluster, *part_idx, *reps, *sizes, *ctl;
   float *Wt;
+  unsigned int *done;
 };
 struct ClusterWs {     // workspace of one clustering problem
   double *key;
   int *cluster, *reps, *sizes, *part_idx;
   float *Wt;           // N x K transposed rows
+  unsigned int *done;  // work-groups finished in the current round
 };
 size_t cluster_ws_bytes(int K, int N);
 ClusterWs carve_cluster_ws(void *ws, int K, int N);

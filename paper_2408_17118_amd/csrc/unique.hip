@@ -37,7 +37,7 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t cluster_ws_bytes(int K, int N) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
   return al256((size_t)K * 8) + 3 * al256((size_t)(K + 1) * 4) + al256((size_t)nb * 4) +
-         al256((size_t)K * N * 4);
+         al256((size_t)K * N * 4) + al256(sizeof(unsigned int));
 }
 
 ClusterWs carve_cluster_ws(void *ws, int K, int N) {
@@ -55,6 +55,7 @@ ClusterWs carve_cluster_ws(void *ws, int K, int N) {
   w.sizes = (int *)take((size_t)(K + 1) * 4);
   w.part_idx = (int *)take((size_t)nb * 4);
   w.Wt = (float *)take((size_t)K * N * 4);
+  w.done = (unsigned int *)take(sizeof(unsigned int));
   return w;
 }
 
@@ -89,6 +90,7 @@ __global__ void k_prep(const UJob *__restrict__ jobs, UJob one) {
   j.key[l] = cand ? upsilon_dev(a) : -INFINITY;
   j.cluster[l] = cand ? -1 : -2;
   j.sizes[l] = 0;
+  if (l == 0) *j.done = 0u;
   transpose_row(j.W, j.Wt, j.K, j.N, l);
 }
 
@@ -100,9 +102,10 @@ __global__ __launch_bounds__(U_BLOCK) void k_assign(int K, int N, const float *_
                                                     const float *__restrict__ Wt,
                                                     const double *__restrict__ key,
                                                     int *__restrict__ cluster,
-                                                    const int *__restrict__ reps, int r,
+                                                    int *__restrict__ reps, int r,
                                                     double tau, int *__restrict__ part_idx,
-                                                    const int *__restrict__ ctl) {
+                                                    int *__restrict__ ctl,
+                                                    unsigned int *__restrict__ done) {
   __shared__ double bk[U_BLOCK];
   __shared__ int bi[U_BLOCK];
   if (ctl[2]) return;  // finished in an earlier round
@@ -147,20 +150,21 @@ __global__ __launch_bounds__(U_BLOCK) void k_assign(int K, int N, const float *_
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part_idx[blockIdx.x] = bi[0];
-}
-
-__global__ __launch_bounds__(U_BLOCK) void k_pick(int nblocks, const double *__restrict__ key,
-                                                  const int *__restrict__ part_idx,
-                                                  int *__restrict__ reps, int r,
-                                                  int *__restrict__ ctl) {
-  __shared__ double bk[U_BLOCK];
-  __shared__ int bi[U_BLOCK];
-  if (ctl[2]) return;
+  // the last work-group to finish picks the next representative from the
+  // per-block arg-maxes (read past the L1, which may hold older values)
+  __shared__ bool s_last;
+  if (threadIdx.x == 0) {
+    part_idx[blockIdx.x] = bi[0];
+    __threadfence();
+    s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
   int best = -1;
   double bkv = -INFINITY;
-  for (int b = threadIdx.x; b < nblocks; b += U_BLOCK) {
-    const int i = part_idx[b];
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += U_BLOCK) {
+    const int i = __hip_atomic_load(&part_idx[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (i >= 0 && ranks_above(key[i], i, bkv, best)) {
       best = i;
       bkv = key[i];
@@ -185,16 +189,30 @@ __global__ __launch_bounds__(U_BLOCK) void k_pick(int nblocks, const double *__r
       ctl[2] = 1;
       ctl[1] = r + 1;
     }
+    *done = 0u;  // for the next round's launch
   }
 }
 
-__global__ void k_sizes(const UJob *__restrict__ jobs, UJob one) {
+// Cluster sizes: a work-group histogram in LDS for the first SIZE_BINS
+// cluster ids (the usual case), global atomics beyond.
+constexpr int SIZE_BINS = 1024;
+__global__ __launch_bounds__(U_BLOCK) void k_sizes(const UJob *__restrict__ jobs, UJob one) {
+  __shared__ int hist[SIZE_BINS];
   const UJob &j = ujob(jobs, one);
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= j.K) return;
-  const int c = j.cluster[l];
-  if (c >= 0) atomicAdd(&j.sizes[c], 1);
-  if (j.row_cluster) j.row_cluster[l] = c >= 0 ? c : -1;
+  for (int h = threadIdx.x; h < SIZE_BINS; h += U_BLOCK) hist[h] = 0;
+  __syncthreads();
+  const int l = blockIdx.x * U_BLOCK + threadIdx.x;
+  if (l < j.K) {
+    const int c = j.cluster[l];
+    if (c >= 0 && c < SIZE_BINS)
+      atomicAdd(&hist[c], 1);
+    else if (c >= SIZE_BINS)
+      atomicAdd(&j.sizes[c], 1);
+    if (j.row_cluster) j.row_cluster[l] = c >= 0 ? c : -1;
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < SIZE_BINS; h += U_BLOCK)
+    if (hist[h]) atomicAdd(&j.sizes[h], hist[h]);
 }
 
 // Output of the first min(U, cap) clusters, and the Gaussianity walk.
@@ -374,19 +392,15 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const Cl
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
   }
-  // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left
+  // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left.
+  // Each round is one launch; its last work-group picks the next representative.
   hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, Wt, key, cluster, reps,
-                     -1, tau, part_idx, ctl_dev);
-  hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, -1,
-                     ctl_dev);  // writes reps[0]
+                     -1, tau, part_idx, ctl_dev, cw.done);
   const int BATCH = 16;
   for (int r0 = 0; r0 <= K; r0 += BATCH) {
-    for (int r = r0; r < r0 + BATCH && r <= K; ++r) {
+    for (int r = r0; r < r0 + BATCH && r <= K; ++r)
       hipLaunchKernelGGL(k_assign, dim3(nb), dim3(U_BLOCK), 0, st, K, N, W, Wt, key, cluster,
-                         reps, r, tau, part_idx, ctl_dev);
-      hipLaunchKernelGGL(k_pick, dim3(1), dim3(U_BLOCK), 0, st, nb, key, part_idx, reps, r,
-                         ctl_dev);
-    }
+                         reps, r, tau, part_idx, ctl_dev, cw.done);
     hipError_t e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
@@ -405,6 +419,7 @@ __global__ void k_prep_groups(int K, int N, const uint8_t *__restrict__ status,
   const bool cand = status[l] == OICA_ROW_CONV;
   cw.key[l] = cand ? 0.0 : -INFINITY;
   cw.cluster[l] = cand ? -1 : -2;
+  if (l == 0) *cw.done = 0u;
   transpose_row(W, cw.Wt, K, N, l);
 }
 
@@ -436,6 +451,7 @@ static ClusterWs carve_ujob(UJob &j, void *ws) {
   j.reps = cw.reps;
   j.sizes = cw.sizes;
   j.Wt = cw.Wt;
+  j.done = cw.done;
   return cw;
 }
 
