@@ -125,8 +125,8 @@ def cpu_baseline(prob, rows: int, passes: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
-              "by start rows across GPUs but no multi-GPU run is part of this build.",
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path would "
+              "shard by start rows across GPUs, which this program does not run.",
               file=sys.stderr)
         return 2
     import torch
