@@ -237,15 +237,17 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
         if (q < N) {
           const double apq = a[p * LD + q];
           const double app = a[p * LD + p], aqq = a[q * LD + q];
-          if (fabs(apq) > dscale && fabs(apq) > thr * sqrt(fabs(app) * fabs(aqq))) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            double t;
-            if (fabs(theta) > 1e150)
-              t = 0.5 / theta;
-            else
-              t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
+          if (fabs(apq) > dscale && apq * apq > thr * thr * fabs(app * aqq)) {
+            // With x = a_qq - a_pp, y = 2 a_pq (cot 2phi = x / y) and r = |(x, y)|,
+            // the smaller rotation angle has t = tan phi = sgn(xy) |y| / (|x| + r),
+            // so cos phi = (|x| + r) / w and sin phi = sgn(xy) |y| / w with
+            // w = sqrt(2 r (r + |x|)): two square roots and one division.
+            const double x = aqq - app, y = 2.0 * apq;
+            const double r = sqrt(x * x + y * y);
+            const double u = r + fabs(x);
+            const double inv = 1.0 / sqrt(2.0 * r * u);
+            c = u * inv;
+            sn = ((x >= 0.0) == (y >= 0.0) ? 1.0 : -1.0) * fabs(y) * inv;
             rotated = 1;
           }
         }
