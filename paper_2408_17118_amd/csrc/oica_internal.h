@@ -206,6 +206,11 @@ hipError_t launch_prune(hipStream_t st, const PrunerState *p, const float *traj,
 hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpControl *ctl);
 
 // unique.hip
+struct CoopSlot {      // one work-group's arg-max in the all-rounds clustering
+  double key;
+  int idx;
+  int pad;
+};
 struct UJob {          // one unique-components problem
   int K, N;
   long long T;
@@ -221,12 +226,14 @@ struct UJob {          // one unique-components problem
   int *cluster, *part_idx, *reps, *sizes, *ctl;
   float *Wt;
   unsigned int *done;
+  CoopSlot *slots;
 };
 struct ClusterWs {     // workspace of one clustering problem
   double *key;
   int *cluster, *reps, *sizes, *part_idx;
   float *Wt;           // N x K transposed rows
-  unsigned int *done;  // work-groups finished in the current round
+  unsigned int *done;  // [0] arrivals / work-groups finished, [1] wait-bound flag
+  CoopSlot *slots;     // 2 x work-groups
 };
 size_t cluster_ws_bytes(int K, int N);
 ClusterWs carve_cluster_ws(void *ws, int K, int N);

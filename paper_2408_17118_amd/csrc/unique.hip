@@ -37,7 +37,8 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t cluster_ws_bytes(int K, int N) {
   const int nb = (K + U_BLOCK - 1) / U_BLOCK;
   return al256((size_t)K * 8) + 3 * al256((size_t)(K + 1) * 4) + al256((size_t)nb * 4) +
-         al256((size_t)K * N * 4) + al256(sizeof(unsigned int));
+         al256((size_t)K * N * 4) + al256(2 * sizeof(unsigned int)) +
+         al256((size_t)2 * nb * sizeof(CoopSlot));
 }
 
 ClusterWs carve_cluster_ws(void *ws, int K, int N) {
@@ -55,7 +56,8 @@ ClusterWs carve_cluster_ws(void *ws, int K, int N) {
   w.sizes = (int *)take((size_t)(K + 1) * 4);
   w.part_idx = (int *)take((size_t)nb * 4);
   w.Wt = (float *)take((size_t)K * N * 4);
-  w.done = (unsigned int *)take(sizeof(unsigned int));
+  w.done = (unsigned int *)take(2 * sizeof(unsigned int));
+  w.slots = (CoopSlot *)take((size_t)2 * nb * sizeof(CoopSlot));
   return w;
 }
 
@@ -90,7 +92,10 @@ __global__ void k_prep(const UJob *__restrict__ jobs, UJob one) {
   j.key[l] = cand ? upsilon_dev(a) : -INFINITY;
   j.cluster[l] = cand ? -1 : -2;
   j.sizes[l] = 0;
-  if (l == 0) *j.done = 0u;
+  if (l == 0) {
+    j.done[0] = 0u;
+    j.done[1] = 0u;
+  }
   transpose_row(j.W, j.Wt, j.K, j.N, l);
 }
 
@@ -373,6 +378,173 @@ hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
   return hipGetLastError();
 }
 
+// All rounds in one launch whose work-groups are all resident at once: each
+// thread keeps its candidate row in registers; a round is the dot products
+// with the current representative, a work-group arg-max, and a grid-wide
+// exchange of the per-group arg-maxes through `slots` (two sets, by round
+// parity) behind an arrival counter.  Every work-group reduces the same slots
+// in the same way, so all agree on the next representative.  A wait that
+// exceeds its bound (about half a second) sets done[1] and ends the kernel,
+// reported as a device error.  The dot products are
+// k_assign's, in the same order, so the partition is identical.
+constexpr int CO_BLOCK = 256;
+constexpr int CO_SPIN_LIMIT = 1 << 24;
+
+template <int NP>
+__global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const float *__restrict__ W,
+                                                           const double *__restrict__ key,
+                                                           int *__restrict__ cluster,
+                                                           int *__restrict__ reps, double tau,
+                                                           CoopSlot *slots, unsigned int *done,
+                                                           int *__restrict__ ctl) {
+  __shared__ double lw[NP];
+  __shared__ double wk[CO_BLOCK / 64];
+  __shared__ int wi[CO_BLOCK / 64];
+  __shared__ int s_leader;
+  const int nwg = gridDim.x;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int l = blockIdx.x * CO_BLOCK + tid;
+  const bool have = l < K;
+  int cl = have ? cluster[l] : -2;
+  const double kv = cl == -1 ? key[l] : -INFINITY;
+  float row[NP];
+#pragma unroll
+  for (int n = 0; n < NP; ++n) row[n] = (have && n < N) ? W[(size_t)l * N + n] : 0.f;
+  int leader = -1, r = -1;
+  for (unsigned int round = 0;; ++round) {
+    if (leader >= 0 && cl == -1) {
+      double dot = 0.0;
+#pragma unroll
+      for (int n = 0; n < NP; ++n)
+        if (n < N) dot = fma((double)row[n], lw[n], dot);
+      if (1.0 - fabs(dot) <= tau || l == leader) cl = r;
+    }
+    double bk = cl == -1 ? kv : -INFINITY;
+    int bi = cl == -1 ? l : -1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double k2 = __shfl_xor(bk, o);
+      const int i2 = __shfl_xor(bi, o);
+      if (ranks_above(k2, i2, bk, bi)) {
+        bk = k2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      wk[wave] = bk;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double k0 = wk[0];
+      int i0 = wi[0];
+      for (int w = 1; w < CO_BLOCK / 64; ++w)
+        if (ranks_above(wk[w], wi[w], k0, i0)) {
+          k0 = wk[w];
+          i0 = wi[w];
+        }
+      CoopSlot *sl = slots + (size_t)(round & 1) * nwg + blockIdx.x;
+      __hip_atomic_store(&sl->key, k0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&sl->idx, i0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&done[0], 1u);
+      const unsigned int target = (round + 1) * (unsigned int)nwg;
+      int spins = 0;
+      while (__hip_atomic_load(&done[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > CO_SPIN_LIMIT ||
+            __hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          atomicOr(&done[1], 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    // every work-group reduces the same slots to the next representative
+    double gk = -INFINITY;
+    int gi = -1;
+    for (int b = tid; b < nwg; b += CO_BLOCK) {
+      const CoopSlot *sl = slots + (size_t)(round & 1) * nwg + b;
+      const double k2 = __hip_atomic_load(&sl->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int i2 = __hip_atomic_load(&sl->idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ranks_above(k2, i2, gk, gi)) {
+        gk = k2;
+        gi = i2;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double k2 = __shfl_xor(gk, o);
+      const int i2 = __shfl_xor(gi, o);
+      if (ranks_above(k2, i2, gk, gi)) {
+        gk = k2;
+        gi = i2;
+      }
+    }
+    __syncthreads();  // wk / wi of this round have been read
+    if (lane == 0) {
+      wk[wave] = gk;
+      wi[wave] = gi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double k0 = wk[0];
+      int i0 = wi[0];
+      for (int w = 1; w < CO_BLOCK / 64; ++w)
+        if (ranks_above(wk[w], wi[w], k0, i0)) {
+          k0 = wk[w];
+          i0 = wi[w];
+        }
+      if (__hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) i0 = -1;
+      s_leader = i0;
+      if (blockIdx.x == 0) reps[r + 1] = i0;  // -1 after the last cluster
+    }
+    __syncthreads();
+    leader = s_leader;
+    if (leader < 0) break;
+    ++r;
+    for (int n = tid; n < N; n += CO_BLOCK) lw[n] = (double)W[(size_t)leader * N + n];
+    __syncthreads();
+  }
+  if (have) cluster[l] = cl;
+  if (blockIdx.x == 0 && tid == 0) {
+    ctl[1] = r + 1;
+    ctl[2] = 1;
+  }
+}
+
+// Launch of k_cluster_coop when every work-group fits on the device at once
+// (the stream is in order, so the device is otherwise free for it);
+// *launched = false (nothing enqueued) otherwise.
+static hipError_t launch_cluster_coop(hipStream_t st, int N, int K, const float *W,
+                                      const ClusterWs &cw, double tau, int *ctl_dev,
+                                      bool *launched) {
+  *launched = false;
+  const int grid = (K + CO_BLOCK - 1) / CO_BLOCK;
+  const int np = ((N + 31) / 32) * 32;
+  const void *fn = np <= 32   ? (const void *)k_cluster_coop<32>
+                   : np <= 64 ? (const void *)k_cluster_coop<64>
+                   : np <= 96 ? (const void *)k_cluster_coop<96>
+                              : (const void *)k_cluster_coop<128>;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CO_BLOCK, 0);
+  if (e != hipSuccess) return e;
+  if ((long long)per_cu * cus < grid) return hipSuccess;
+  const double *key = cw.key;
+  int *cluster = cw.cluster, *reps = cw.reps;
+  CoopSlot *slots = cw.slots;
+  unsigned int *done = cw.done;
+  void *args[] = {(void *)&K, (void *)&N, (void *)&W, (void *)&key, (void *)&cluster, (void *)&reps,
+                  (void *)&tau, (void *)&slots, (void *)&done, (void *)&ctl_dev};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st);
+  if (e == hipSuccess) *launched = true;
+  return e;
+}
+
 // Greedy leader clustering of the candidates (cluster[l] == -1 on entry) in
 // (key descending, row index) order; writes cluster ids, the representative of
 // every cluster (reps[0..n)), and n into ctl_dev[1] / ctl_host[1].
@@ -391,6 +563,21 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const Cl
     e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
+  }
+  {
+    bool launched = false;
+    hipError_t e = launch_cluster_coop(st, N, K, W, cw, tau, ctl_dev, &launched);
+    if (e != hipSuccess) return e;
+    if (launched) {
+      unsigned int flags[2] = {0u, 0u};
+      e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(flags, cw.done, sizeof flags, hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      return flags[1] ? hipErrorLaunchTimeOut : hipSuccess;
+    }
   }
   // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left.
   // Each round is one launch; its last work-group picks the next representative.
@@ -419,7 +606,10 @@ __global__ void k_prep_groups(int K, int N, const uint8_t *__restrict__ status,
   const bool cand = status[l] == OICA_ROW_CONV;
   cw.key[l] = cand ? 0.0 : -INFINITY;
   cw.cluster[l] = cand ? -1 : -2;
-  if (l == 0) *cw.done = 0u;
+  if (l == 0) {
+    cw.done[0] = 0u;
+    cw.done[1] = 0u;
+  }
   transpose_row(W, cw.Wt, K, N, l);
 }
 
@@ -452,6 +642,7 @@ static ClusterWs carve_ujob(UJob &j, void *ws) {
   j.sizes = cw.sizes;
   j.Wt = cw.Wt;
   j.done = cw.done;
+  j.slots = cw.slots;
   return cw;
 }
 
