@@ -83,6 +83,10 @@ __global__ void k_any_conv(const UJob *__restrict__ jobs, UJob one) {
 __global__ void k_prep(const UJob *__restrict__ jobs, UJob one) {
   const UJob &j = ujob(jobs, one);
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l == 0) {  // clustering counters
+    j.done[0] = 0u;
+    j.done[1] = 0u;
+  }
   if (l >= j.K) return;
   const bool any_conv = j.ctl[0] != 0;
   const uint8_t s = j.status[l];
@@ -92,10 +96,6 @@ __global__ void k_prep(const UJob *__restrict__ jobs, UJob one) {
   j.key[l] = cand ? upsilon_dev(a) : -INFINITY;
   j.cluster[l] = cand ? -1 : -2;
   j.sizes[l] = 0;
-  if (l == 0) {
-    j.done[0] = 0u;
-    j.done[1] = 0u;
-  }
   transpose_row(j.W, j.Wt, j.K, j.N, l);
 }
 
@@ -602,14 +602,14 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const Cl
 __global__ void k_prep_groups(int K, int N, const uint8_t *__restrict__ status,
                               const float *__restrict__ W, ClusterWs cw) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l == 0) {  // clustering counters
+    cw.done[0] = 0u;
+    cw.done[1] = 0u;
+  }
   if (l >= K) return;
   const bool cand = status[l] == OICA_ROW_CONV;
   cw.key[l] = cand ? 0.0 : -INFINITY;
   cw.cluster[l] = cand ? -1 : -2;
-  if (l == 0) {
-    cw.done[0] = 0u;
-    cw.done[1] = 0u;
-  }
   transpose_row(W, cw.Wt, K, N, l);
 }
 
