@@ -326,8 +326,9 @@ def bench_batched(args):
 
     def seq():
         return [oica.ordering_ica(ctx, X, W0, **kw) for X, W0 in zip(Xs, W0s)]
-    seq_ms, seq_res = timed(seq)
-    f32_ms, (f32_res, f32_st) = timed(lambda: step(precision="f32"))
+    if not args.no_compare:
+        seq_ms, seq_res = timed(seq)
+        f32_ms, (f32_res, f32_st) = timed(lambda: step(precision="f32"))
     out = {
         "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",
         "value": ti / (t1 - t0),
@@ -359,20 +360,21 @@ def bench_batched(args):
             "avg_launch_ms": upd_ms / launches if launches else None,
             "update_share_of_step": (upd_ms / args.steps) / ms_per_step,
         },
-        "one_call_per_dataset": {
+    }
+    if not args.no_compare:
+        out["one_call_per_dataset"] = {
             "form": "bf16 + fp32 finish, one ordering_ica call per dataset",
             "time_to_unique_ms": seq_ms,
             "speedup_of_batched": seq_ms / ms_per_step,
             "n_accepted_total": int(sum(r["n_accepted"] for r in seq_res)),
-        },
-        "batched_fp32": {
+        }
+        out["batched_fp32"] = {
             "form": "batched, fp32 data",
             "time_to_unique_ms": f32_ms,
             "thread_iters": f32_st["thread_iters"],
             "n_accepted_total": int(sum(r["n_accepted"] for r in f32_res)),
             "speedup_of_bf16": f32_ms / ms_per_step,
-        },
-    }
+        }
     ctx.close()
     print(json.dumps(out))
     return 0

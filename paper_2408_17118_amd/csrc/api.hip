@@ -347,7 +347,18 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
                             : params->traj_iters;
 
   const auto t0 = std::chrono::steady_clock::now();
-  const FusedPlan plan = make_plan(N, T, K, bf16);
+  // rows of X start on 16-byte boundaries for the vector loads of the passes:
+  // when T does not give that, the passes read padded copies
+  const long long ldx = aligned_ld(T, bf16 ? 2 : 4), ld32 = aligned_ld(T, 4);
+  const bool pad_x = ldx != T;
+  const bool pad_32 = ld32 != T && !(Xw_f32 == Xw && !bf16);
+  FusedPlan plan = make_plan(N, T, K, bf16);
+  plan.ld = ldx;
+  auto plan_f32 = [&]() {
+    FusedPlan q = make_plan(N, T, K, false);
+    q.ld = ld32;
+    return q;
+  };
   const size_t gfl = fp_workspace_floats(plan, N, K);
   const int np = fused_np(N);
   const size_t rows_max = gfl / np;
@@ -363,6 +374,8 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   need += unique_workspace_bytes(K, N) + 256;   // grouping of BF16 fixed points / guard
   if (pruner && !traj) need += (size_t)K * traj_n * 2 * sizeof(float) + 256;
   if (pruner) need += (size_t)gcap * (N * 8 + 8 + 8 + 4 + 4) + 5 * 256;
+  if (pad_x) need += (size_t)N * ldx * (bf16 ? 2 : 4) + 256;
+  if (pad_32) need += (size_t)N * ld32 * 4 + 256;
   rc = ensure_ws(ctx, need);
   if (rc) return rc;
   Carve cv{(char *)ctx->ws};
@@ -391,8 +404,20 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
     grep = cv.take<int32_t>(gcap);
     gsize = cv.take<int32_t>(gcap);
   }
-
+  const void *Xp = Xw;
+  const float *X32p = Xw_f32;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (pad_x) {
+    void *dst = cv.take<char>((size_t)N * ldx * (bf16 ? 2 : 4));
+    HIP_TRY(ctx, launch_pad_rows(ctx->stream, Xw, bf16 ? 2 : 4, N, T, dst, ldx));
+    Xp = dst;
+    if (!bf16 && Xw_f32 == Xw) X32p = (const float *)dst;
+  }
+  if (pad_32) {
+    float *dst = cv.take<float>((size_t)N * ld32);
+    HIP_TRY(ctx, launch_pad_rows(ctx->stream, Xw_f32, 4, N, T, dst, ld32));
+    X32p = dst;
+  }
   HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 4 * 256, ctx->stream));
   HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj_buf,
                                 traj_n));
@@ -414,7 +439,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
     int launched = 0;
     double kernel_ms = 0.0;
     const bool prune_now = pruner && attempt == 0;
-    rc = run_passes(ctx, plan, N, T, Xw, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
+    rc = run_passes(ctx, plan, N, T, Xp, bf16, K, W_out, act0, act1, gpart, s4part, red, ctl,
                     params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
                     status, attempt == 0 ? traj_buf : nullptr, attempt == 0 ? traj_n : 0, profile,
                     &launched, &kernel_ms, bf16_exit, bf16_stall, prune_now ? pruner : nullptr,
@@ -437,7 +462,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
       const int *left_list = (launched & 1) ? act1 : act0;
       const int budget_left = params->max_iter - launched;
       const int fp32_passes = budget_left > params->refine_iters ? budget_left : params->refine_iters;
-      const FusedPlan plan32 = make_plan(N, T, K, false);
+      const FusedPlan plan32 = plan_f32();
       int l2 = 0;
       double ms2 = 0.0;
       HIP_TRY(ctx, hipMemsetAsync(ctl2, 0, 2 * 256, ctx->stream));
@@ -452,12 +477,12 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, ctx->small_dev + 1, status,
                                         kurt, act2, ctl2, left_list, left_rows, kurt_list, ctl3));
         if (fp32_passes > 0) {
-          rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part, red,
+          rc = run_passes(ctx, plan32, N, T, X32p, false, K, W_out, act2, act0, gpart, s4part, red,
                           ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
                           false, &l2, &ms2);
           if (rc) return rc;
         }
-        HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, Xw_f32, K, W_out, s4part64, kurt,
+        HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, X32p, K, W_out, s4part64, kurt,
                                      kurt_list, &ctl3->kact[0]));
         HIP_TRY(ctx, launch_propagate(ctx->stream, K, N, cluster, reps, W_out, status, kurt));
         kurt_done = true;
@@ -465,7 +490,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         // FP32 passes for every row that converged on BF16 data or is still moving
         HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2, left_list, left_rows));
         if (fp32_passes > 0) {
-          rc = run_passes(ctx, plan32, N, T, Xw_f32, false, K, W_out, act2, act0, gpart, s4part,
+          rc = run_passes(ctx, plan32, N, T, X32p, false, K, W_out, act2, act0, gpart, s4part,
                           red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
                           0, false, &l2, &ms2);
           if (rc) return rc;
@@ -477,7 +502,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
       refine_ti += ((const FpControl *)ctx->small_host)->thread_iters;
     }
     if (!kurt_done)
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(N, T, K, false), N, T, Xw_f32, K, W_out,
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan_f32(), N, T, X32p, K, W_out,
                                    s4part64, kurt));
     if (!(prune_now && pruned > 0)) break;
     // guard: every one of the first guard_top accepted components must keep
@@ -755,6 +780,11 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     BatchDesc &b = hd[d];
     b.N = q.N; b.T = q.T; b.K = q.K;
     b.np = fused_np(q.N);
+    // 16-byte row starts for the passes' vector loads (padded copies otherwise)
+    b.ld = aligned_ld(q.T, bf16 ? 2 : 4);
+    b.ld32 = aligned_ld(q.T, 4);
+    if (b.ld != q.T) add((size_t)q.N * b.ld * (bf16 ? 2 : 4));
+    if (b.ld32 != q.T && !(q.Xw_f32 == q.Xw && !bf16)) add((size_t)q.N * b.ld32 * 4);
     b.n_sp = batch_splits(q.T);
     b.n_sub = (int)((q.T + 31) / 32);
     const size_t rows_cap = (size_t)q.K + 256;
@@ -782,6 +812,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   }
   rc = ensure_ws(ctx, need + 4096);
   if (rc) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
   Carve cv{(char *)ctx->ws};
   BatchDesc *ddesc = cv.take<BatchDesc>(D);
   BatchCtl *bctl = cv.take<BatchCtl>(1);
@@ -822,6 +853,17 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     b.ctl = (FpControl *)(ctl_base + (size_t)d * 256);
     b.X = q.Xw;
     b.X32 = q.Xw_f32;
+    if (b.ld != q.T) {
+      void *dst = cv.take<char>((size_t)q.N * b.ld * (bf16 ? 2 : 4));
+      HIP_TRY(ctx, launch_pad_rows(ctx->stream, q.Xw, bf16 ? 2 : 4, q.N, q.T, dst, b.ld));
+      b.X = dst;
+      if (!bf16 && q.Xw_f32 == q.Xw) b.X32 = (const float *)dst;
+    }
+    if (b.ld32 != q.T && !(q.Xw_f32 == q.Xw && !bf16)) {
+      float *dst = cv.take<float>((size_t)q.N * b.ld32);
+      HIP_TRY(ctx, launch_pad_rows(ctx->stream, q.Xw_f32, 4, q.N, q.T, dst, b.ld32));
+      b.X32 = dst;
+    }
     b.B = q.W_out;
     b.iters = q.iters;
     b.status = q.status;
@@ -1034,6 +1076,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       b.act1 = old0;
       b.ctl = c2;
       b.X = b.X32;
+      b.ld = b.ld32;
     }
     set_shapes(hd, wk32, wk64, false);
     HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
@@ -1059,8 +1102,10 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     for (int d = 0; d < D; ++d) {
       const oica_problem &q = pr[d];
       FpControl *c3 = (FpControl *)(ctl_base + (size_t)(D + d) * 256 + 128);
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T, q.Xw_f32,
-                                   q.K, q.W_out, s4part64, q.kurt, kurt_list[d], &c3->kact[0]));
+      FusedPlan kp = make_plan(q.N, q.T, q.K, false);
+      kp.ld = hd[d].ld32;
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4part64,
+                                   q.kurt, kurt_list[d], &c3->kact[0]));
       HIP_TRY(ctx, launch_propagate(ctx->stream, q.K, q.N, gjobs[d].cluster, gjobs[d].reps, q.W_out,
                                     q.status, q.kurt));
     }
@@ -1069,8 +1114,10 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     // final kurtosis of every row, FP32 data, FP64 sums
     for (int d = 0; d < D; ++d) {
       const oica_problem &q = pr[d];
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, make_plan(q.N, q.T, q.K, false), q.N, q.T,
-                                   q.Xw_f32, q.K, q.W_out, s4part64, q.kurt));
+      FusedPlan kp = make_plan(q.N, q.T, q.K, false);
+      kp.ld = hd[d].ld32;
+      HIP_TRY(ctx, launch_kurtosis(ctx->stream, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4part64,
+                                   q.kurt));
     }
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

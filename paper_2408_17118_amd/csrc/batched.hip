@@ -139,7 +139,7 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
     const int n_kb = (kact + b.kwg - 1) / b.kwg;
     const int local = item - s_start[d];
     const int kb = local % n_kb, sp = local / n_kb;
-    const ItemCtx c{b.X, b.N, b.T, b.n_sub, b.n_sp, n_kb * b.kwg, b.B,
+    const ItemCtx c{b.X, b.N, b.T, b.ld, b.n_sub, b.n_sp, n_kb * b.kwg, b.B,
                     (pass & 1) ? b.act1 : b.act0, kact, b.gpart, b.s4part, nullptr};
     if constexpr (!BF16) {
       float *xs32 = reinterpret_cast<float *>(buf);

@@ -13,6 +13,8 @@
 // The per-item device code is in fused_items.h.
 #include "fused_items.h"
 
+#include <algorithm>
+
 #include <math.h>
 
 namespace oica {
@@ -50,7 +52,32 @@ FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
   if (ms < 1) ms = 1;
   if (ms > GRID) ms = GRID;
   p.max_splits = (int)ms;
+  p.ld = T;
   return p;
+}
+
+template <typename E>
+__global__ void k_pad_rows(const E *__restrict__ src, int N, long long T, E *__restrict__ dst,
+                           long long ld) {
+  const long long total = (long long)N * T;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (long long)gridDim.x * 256) {
+    const long long n = i / T, m = i - n * T;
+    dst[n * ld + m] = src[i];
+  }
+}
+
+hipError_t launch_pad_rows(hipStream_t st, const void *src, int esize, int N, long long T,
+                           void *dst, long long ld) {
+  const long long total = (long long)N * T;
+  const int grid = (int)std::min<long long>((total + 255) / 256, 8192);
+  if (esize == 2)
+    hipLaunchKernelGGL(k_pad_rows<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)src, N,
+                       T, (uint16_t *)dst, ld);
+  else
+    hipLaunchKernelGGL(k_pad_rows<float>, dim3(grid), dim3(256), 0, st, (const float *)src, N, T,
+                       (float *)dst, ld);
+  return hipGetLastError();
 }
 
 // Partial-buffer rows per split: positions are padded to whole row blocks.
@@ -98,7 +125,8 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
   const int per_xcd_wgs = plan.grid / 8;
   const int xcd = blockIdx.x % 8;
   const int local = blockIdx.x / 8;
-  const ItemCtx c{X, N, T, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part, s4part64};
+  const ItemCtx c{X, N, T, plan.ld, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part,
+                  s4part64};
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
@@ -134,7 +162,8 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
   const int per_xcd_wgs = plan.grid / 8;
   const int xcd = blockIdx.x % 8;
   const int local = blockIdx.x / 8;
-  const ItemCtx c{X, N, T, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part, nullptr};
+  const ItemCtx c{X, N, T, plan.ld, plan.n_sub, n_sp, rows_pad, Bm, act, kact, gpart, s4part,
+                  nullptr};
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;

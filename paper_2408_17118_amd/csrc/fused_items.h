@@ -35,9 +35,10 @@ constexpr int EPI_ROWS = 16;    // rows per wave in the per-row passes (epilogue
 
 // Everything one (row block, sample split) work item needs.
 struct ItemCtx {
-  const void *X;
+  const void *X;       // N rows of T samples, row stride ld elements
   int N;
   long long T;
+  long long ld;
   int n_sub;
   int n_sp;
   int rows_pad;
@@ -117,7 +118,8 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
     // per load); with PF they are fetched one tile ahead, so the global-load
     // latency of tile i+1 overlaps the MFMA work of tile i.
     constexpr int F4 = NP * TT / 4 / (WAVES * 64);
-    const bool vec4 = (T % 4) == 0;
+    const long long ld = c.ld;
+    const bool vec4 = (ld % 4) == 0;  // 16-byte aligned rows
     f32x4 pre[F4];
     auto fetch = [&](long long mt) {
 #pragma unroll
@@ -125,7 +127,7 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
         const int e = tid + q * WAVES * 64;
         const int n = e / (TT / 4);
         const long long gm = mt + (e % (TT / 4)) * 4;
-        const float *src = X + (size_t)n * (size_t)T + (size_t)gm;
+        const float *src = X + (size_t)n * (size_t)ld + (size_t)gm;
         if (n < N && vec4 && gm + 4 <= t_end) {
           pre[q] = *reinterpret_cast<const f32x4 *>(src);
         } else {
@@ -280,7 +282,8 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
   const int lane = tid % 64;
   const int h = lane / 32;
   const int li = lane % 32;
-  const bool vec_ok = (T % 8) == 0;
+  const long long ld = c.ld;
+  const bool vec_ok = (ld % 8) == 0;  // 16-byte aligned rows
   {
     const long long sub0 = (long long)sp * c.n_sub / n_sp;
     const long long sub1 = (long long)(sp + 1) * c.n_sub / n_sp;
@@ -333,8 +336,8 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
         const int pp = u % PAIRS, c = u / PAIRS;
         const long long gm = mt + c * 8;
         const int n0 = 2 * pp;
-        const __bf16 *src0 = X + (size_t)n0 * (size_t)T + (size_t)gm;
-        const __bf16 *src1 = src0 + (size_t)T;
+        const __bf16 *src0 = X + (size_t)n0 * (size_t)ld + (size_t)gm;
+        const __bf16 *src1 = src0 + (size_t)ld;
         if (u < UNITS && n0 + 1 < N && vec_ok && gm + 8 <= t_end) {
           pre0[q] = *reinterpret_cast<const bf16x8 *>(src0);
           pre1[q] = *reinterpret_cast<const bf16x8 *>(src1);

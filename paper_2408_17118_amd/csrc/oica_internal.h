@@ -31,7 +31,17 @@ struct FusedPlan {
   int max_splits;   // cap on sample splits (each split >= a minimum length)
   int kwg;          // rows per work-group
   int n_sub;        // 32-sample sub-tiles covering T
+  long long ld;     // row stride of X in elements (T, or T rounded up for 16-byte rows)
 };
+
+// Row stride that makes every row of X start on a 16-byte boundary.
+inline long long aligned_ld(long long T, int esize) {
+  const long long per = 16 / esize;
+  return (T + per - 1) / per * per;
+}
+// Copy of an N x T matrix into rows of stride ld (ld >= T); esize 2 or 4.
+hipError_t launch_pad_rows(hipStream_t st, const void *src, int esize, int N, long long T,
+                           void *dst, long long ld);
 
 // Number of sample splits used when n_kb row blocks are active.  Host and
 // device evaluate the same expression.
@@ -69,6 +79,7 @@ struct BatchDesc {
   int32_t *iters;
   uint8_t *status;
   long long T;
+  long long ld, ld32;  // row strides of X and X32 (elements)
   int N, K, np, wk, kwg, n_sp, n_sub, variant;
 };
 
