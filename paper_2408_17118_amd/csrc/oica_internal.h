@@ -104,10 +104,10 @@ struct ClusterJob {
   int *ctl;            // out: ctl[1] = number of clusters, ctl[2] = 1
 };
 constexpr int CW_MAX_K = 4096;
-// One problem alone: the one-work-group form only while its rounds are short
-// (its row loads are latency-bound); many problems: whenever K fits, since
-// the problems then run side by side.
-inline bool cluster_in_one_wg(int K, bool many) { return K <= (many ? CW_MAX_K : 1024); }
+// One problem alone: the one-work-group form only for small K (its row loads
+// are latency-bound; larger problems use the all-rounds multi-work-group
+// kernel); many problems: whenever K fits, since they run side by side.
+inline bool cluster_in_one_wg(int K, bool many) { return K <= (many ? CW_MAX_K : 256); }
 hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
                              const ClusterJob &one, double tau);
 

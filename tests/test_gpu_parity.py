@@ -319,9 +319,11 @@ def test_unique_fallback_and_cap(ctx):
     assert res["n_accepted"] == 1
 
 
-def test_unique_round_by_round_path(ctx):
-    """K N above the one-work-group limit: the round-by-round kernels, against the oracle."""
-    B, labels = _planted(seed=7, N=32, n_clusters=20, per=1000)
+@pytest.mark.parametrize("N,per", [(32, 1000), (24, 3300)])
+def test_unique_large_problems(ctx, N, per):
+    """K = 20000 (all rounds in one launch over many work-groups) and K = 66000
+    (more work-groups than fit at once: round by round), against the oracle."""
+    B, labels = _planted(seed=7, N=N, n_clusters=20, per=per)
     K = len(labels)
     rng = np.random.default_rng(4)
     alpha = 6.0 - 0.25 * labels + 1e-6 * rng.standard_normal(K)
@@ -329,7 +331,6 @@ def test_unique_round_by_round_path(ctx):
     B32 = B.astype(np.float32)
     ref = ica.unique(B32.astype(np.float64), alpha, status, 5000, tau=1e-3, gaussianity_test=True)
     res = ctx.unique(dev(B32), dev(alpha), dev(status), 5000, tau=1e-3)
-    assert K * 32 > (1 << 19)
     assert res["n_unique"] == len(ref["U"]) == 20
     assert res["n_accepted"] == ref["n_accepted"]
     assert np.array_equal(host(res["rep"]), ref["rep"])
