@@ -222,7 +222,8 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
  * G = (Z o Z o Z) Xw^T / T - 3 B with Z = B Xw, and s4 = sum_m z^4 / T per row.
  * B: K x N FP32 (used as given, not normalised).  G: K x N FP64, s4: K FP64.
  * xw_t = OICA_F32 or OICA_BF16 selects the kernel family of oica_fixed_point's
- * passes (BF16: B and z^3 rounded to BF16, FP32 sums).  Does not synchronise. */
+ * passes (BF16: each row carried as a BF16 pair hi + lo with lo = b - hi, z^3
+ * rounded to BF16, FP32 sums).  Does not synchronise. */
 int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t, int K,
                 const float *B, double *G, double *s4);
 
