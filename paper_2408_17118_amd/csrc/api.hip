@@ -734,12 +734,14 @@ void tune_cache_store(const char *path, const std::string &key, const std::vecto
   fclose(f);
 }
 
+void set_wk(BatchDesc &b, int wk, bool bf16) {
+  b.wk = wk;
+  b.kwg = WAVES_PER_WG * wk * 32;
+  b.variant = variant_of(b.np, wk, bf16);
+}
+
 void set_shapes(std::vector<BatchDesc> &hd, int wk32, int wk64, bool bf16) {
-  for (auto &b : hd) {
-    b.wk = b.np == 32 ? wk32 : (b.np == 64 ? wk64 : 1);
-    b.kwg = WAVES_PER_WG * b.wk * 32;
-    b.variant = variant_of(b.np, b.wk, bf16);
-  }
+  for (auto &b : hd) set_wk(b, b.np == 32 ? wk32 : (b.np == 64 ? wk64 : 1), bf16);
 }
 
 }  // namespace
@@ -985,9 +987,15 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         const int par = (pass + 1) & 1;
         long long left = 0;
-        bool parked_now = false;
+        bool parked_now = false, reshaped = false;
         for (int d = 0; d < D; ++d) {
           int kd = ((const FpControl *)(ctl_host.data() + (size_t)d * 256))->kact[par];
+          // at most one narrow row block left: one 32-row block per wave from
+          // the next pass on (same sample splits, so the same arithmetic)
+          if (hd[d].wk > 1 && kd <= WAVES_PER_WG * 32) {
+            set_wk(hd[d], 1, data_bf16);
+            reshaped = true;
+          }
           if (park && park_count[d] < 0 && kd > 0) {
             stalled[d] = kd >= kprev[d] ? stalled[d] + 1 : 0;
             kprev[d] = kd;
@@ -1001,7 +1009,10 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
           }
           left += kd;
         }
-        if (parked_now) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (reshaped)
+          HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
+                                      hipMemcpyHostToDevice, ctx->stream));
+        if (parked_now || reshaped) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         if (left == 0) break;
         kmax = left;
       }
@@ -1078,7 +1089,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       b.X = b.X32;
       b.ld = b.ld32;
     }
-    set_shapes(hd, wk32, wk64, false);
+    // the FP32 passes update few rows per problem: one 32-row block per wave
+    set_shapes(hd, 1, 1, false);
     HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -11,6 +11,9 @@
 //                                Wh = D^(-1/2) E^T
 //   k_apply                      Xw = Wh (X - mu)       (FP64 tiles; FP32 / BF16 out)
 // Every pass is HBM-bound except the Jacobi solve, which is O(N^3) on N <= 128.
+// Every kernel takes a table of problems, so many datasets share each launch
+// (a single problem is passed by value); a problem's arithmetic does not
+// depend on the others.
 #include "oica_internal.h"
 
 #include <math.h>
@@ -47,13 +50,42 @@ static inline int n_cov_chunks(int N, int64_t T) {
   return n_chunks(T, N <= 64 ? MAX_COV_CHUNKS : MAX_COV_CHUNKS / 2);
 }
 
+// One problem of the statistics, canon and apply kernels.  Many problems run
+// in one launch from a device table; a single problem is passed by value.
+struct WJob {
+  const void *X;
+  int f64;              // raw data FP64 (else FP32)
+  int N;
+  long long T;
+  int ch, cch;          // sample chunks of the mean and covariance passes
+  double *mpart, *cpart;
+  double *mean, *C, *E, *Wh, *eig;
+  int *flags;
+  float *o32, *o32b;    // FP32 outputs (either may be null)
+  uint16_t *obf;        // BF16 output (may be null)
+};
+
+// Launch-wide ranges: problem d owns work-groups (or waves) [start[d],
+// start[d + 1]) of a launch.  start == nullptr: one problem, passed by value.
+enum { W_MEAN = 0, W_MEANF, W_COV4, W_COV8, W_COVF, W_APPLY, W_KINDS };
+
+__device__ inline int job_of(const int *start, int D, int b) {
+  int lo = 0, hi = D - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Partial row sums over a sample chunk; one wave per row (strided), lanes over samples.
 template <typename TIN>
-__global__ __launch_bounds__(256) void k_mean_part(const TIN *__restrict__ X, int N, long long T,
-                                                   int chunks, double *__restrict__ part,
-                                                   int *__restrict__ flags) {
-  const int c = blockIdx.x;
-  const long long t0 = (long long)c * T / chunks, t1 = (long long)(c + 1) * T / chunks;
+__device__ void mean_part_body(const WJob &j, int c) {
+  const TIN *X = (const TIN *)j.X;
+  const int N = j.N;
+  const long long T = j.T;
+  const long long t0 = (long long)c * T / j.ch, t1 = (long long)(c + 1) * T / j.ch;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
@@ -65,37 +97,53 @@ __global__ __launch_bounds__(256) void k_mean_part(const TIN *__restrict__ X, in
       s += v;
     }
     s = wsum(s);
-    if (bad) atomicOr(flags, 1);
-    if (lane == 0) part[(size_t)c * N + n] = s;
+    if (bad) atomicOr(j.flags, 1);
+    if (lane == 0) j.mpart[(size_t)c * N + n] = s;
   }
 }
 
-// One wave per row: lanes take chunks lane, lane + 64, ...; fixed shuffle tree.
-__global__ void k_mean_final(int N, long long T, int chunks, const double *__restrict__ part,
-                             double *__restrict__ mean) {
-  const int n = blockIdx.x * 4 + threadIdx.x / 64;
+__global__ __launch_bounds__(256) void k_mean_part(const WJob *__restrict__ jobs, WJob one,
+                                                   const int *__restrict__ start, int D) {
+  int c = blockIdx.x;
+  const int d = start ? job_of(start, D, c) : 0;
+  if (start) c -= start[d];
+  const WJob j = start ? jobs[d] : one;
+  if (j.f64) mean_part_body<double>(j, c);
+  else mean_part_body<float>(j, c);
+}
+
+// One wave per (problem, row): lanes take chunks lane, lane + 64, ...; fixed
+// shuffle tree.
+__global__ void k_mean_final(const WJob *__restrict__ jobs, WJob one, const int *__restrict__ start,
+                             int D, int total) {
+  int w = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
-  if (n >= N) return;
+  if (w >= total) return;
+  const int d = start ? job_of(start, D, w) : 0;
+  if (start) w -= start[d];
+  const WJob j = start ? jobs[d] : one;
+  const int n = w;
   double s = 0.0;
-  for (int c = lane; c < chunks; c += 64) s += part[(size_t)c * N + n];
+  for (int c = lane; c < j.ch; c += 64) s += j.mpart[(size_t)c * j.N + n];
   s = wsum(s);
-  if (lane == 0) mean[n] = s / (double)T;
+  if (lane == 0) j.mean[n] = s / (double)j.T;
 }
 
 // Partial centred second moments over a chunk.  256 threads = 16 x 16, each
 // owning an RB x RB block of the (padded 16 RB)^2 matrix (RB = 4 for N <= 64,
-// 8 for N <= 128).
+// 8 for N <= 128); blocks below the diagonal are skipped (the final pass reads
+// the upper triangle only).
 template <typename TIN, int RB>
-__global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int N, long long T,
-                                                  int chunks, const double *__restrict__ mean,
-                                                  double *__restrict__ part) {
+__device__ void cov_part_body(const WJob &j, int c, double *xs_flat) {
   constexpr int NP = 16 * RB;
-  __shared__ double xs[COV_TS][NP + 2];
-  const int c = blockIdx.x;
-  const long long t0 = (long long)c * T / chunks, t1 = (long long)(c + 1) * T / chunks;
+  double(*xs)[NP + 2] = reinterpret_cast<double(*)[NP + 2]>(xs_flat);
+  const TIN *X = (const TIN *)j.X;
+  const int N = j.N;
+  const long long T = j.T;
+  const long long t0 = (long long)c * T / j.cch, t1 = (long long)(c + 1) * T / j.cch;
   const int tid = threadIdx.x;
   const int ti = tid / 16, tj = tid % 16;
-  const bool active = (RB * ti < N) && (RB * tj < N);
+  const bool active = (RB * ti < N) && (RB * tj < N) && ti <= tj;
   double acc[RB][RB];
 #pragma unroll
   for (int a = 0; a < RB; ++a)
@@ -107,7 +155,7 @@ __global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int
       const int n = e / COV_TS, s = e % COV_TS;
       const long long m = m0 + s;
       double v = 0.0;
-      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)T + (size_t)m) - mean[n];
+      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)T + (size_t)m) - j.mean[n];
       xs[s][n] = v;
     }
     __syncthreads();
@@ -129,26 +177,43 @@ __global__ __launch_bounds__(256) void k_cov_part(const TIN *__restrict__ X, int
   if (active) {
     for (int p = 0; p < RB; ++p)
       for (int q = 0; q < RB; ++q) {
-        const int i = RB * ti + p, j = RB * tj + q;
-        if (i < N && j < N) part[((size_t)c * N + i) * N + j] = acc[p][q];
+        const int i = RB * ti + p, jj = RB * tj + q;
+        if (i < N && jj < N) j.cpart[((size_t)c * N + i) * N + jj] = acc[p][q];
       }
   }
 }
 
-// One wave per matrix element (lanes over chunks, fixed shuffle tree); the
-// upper-triangle partial is used for both (i, j) and (j, i), so C is exactly
-// symmetric.
-__global__ void k_cov_final(int N, long long T, int chunks, const double *__restrict__ part,
-                            double *__restrict__ C) {
-  const int e = blockIdx.x * 4 + threadIdx.x / 64;
+// RB = 4 for problems with N <= 64, 8 otherwise (one launch per class).
+template <int RB>
+__global__ __launch_bounds__(256) void k_cov_part(const WJob *__restrict__ jobs, WJob one,
+                                                  const int *__restrict__ start, int D) {
+  __shared__ double xs[COV_TS * (16 * RB + 2)];
+  int c = blockIdx.x;
+  const int d = start ? job_of(start, D, c) : 0;
+  if (start) c -= start[d];
+  const WJob j = start ? jobs[d] : one;
+  if (j.f64) cov_part_body<double, RB>(j, c, xs);
+  else cov_part_body<float, RB>(j, c, xs);
+}
+
+// One wave per (problem, matrix element) (lanes over chunks, fixed shuffle
+// tree); the upper-triangle partial is used for both (i, j) and (j, i), so C
+// is exactly symmetric.
+__global__ void k_cov_final(const WJob *__restrict__ jobs, WJob one, const int *__restrict__ start,
+                            int D, int total) {
+  int w = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
-  if (e >= N * N) return;
-  const int i = e / N, j = e % N;
-  const int a = i < j ? i : j, b = i < j ? j : i;
+  if (w >= total) return;
+  const int d = start ? job_of(start, D, w) : 0;
+  if (start) w -= start[d];
+  const WJob j = start ? jobs[d] : one;
+  const int N = j.N;
+  const int i = w / N, jj = w % N;
+  const int a = i < jj ? i : jj, b = i < jj ? jj : i;
   double s = 0.0;
-  for (int c = lane; c < chunks; c += 64) s += part[((size_t)c * N + a) * N + b];
+  for (int c = lane; c < j.cch; c += 64) s += j.cpart[((size_t)c * N + a) * N + b];
   s = wsum(s);
-  if (lane == 0) C[e] = s / (double)T;
+  if (lane == 0) j.C[w] = s / (double)j.T;
 }
 
 // Cyclic Jacobi with round-robin pairing: each round applies N/2 disjoint
@@ -364,9 +429,11 @@ hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const Ja
 }
 
 // Sort descending (rank by count, ties by index), sign rule, rank check,
-// whitening matrix Wh = D^(-1/2) E^T.
-__global__ void k_canon(int N, const double *__restrict__ E, double *__restrict__ Wh,
-                        double *__restrict__ eig_out, int *__restrict__ flags) {
+// whitening matrix Wh = D^(-1/2) E^T.  One work-group per problem.
+__global__ void k_canon(const WJob *__restrict__ jobs, WJob one) {
+  const WJob j = jobs ? jobs[blockIdx.x] : one;
+  const int N = j.N;
+  const double *E = j.E;
   const int i = threadIdx.x;  // one thread per eigenpair, N <= 128
   __shared__ double d[NMAX];
   __shared__ int rank_of[NMAX];
@@ -375,8 +442,8 @@ __global__ void k_canon(int N, const double *__restrict__ E, double *__restrict_
   __syncthreads();
   if (i < N) {
     int r = 0;
-    for (int j = 0; j < N; ++j)
-      if (d[j] > d[i] || (d[j] == d[i] && j < i)) ++r;
+    for (int k = 0; k < N; ++k)
+      if (d[k] > d[i] || (d[k] == d[i] && k < i)) ++r;
     rank_of[i] = r;
   }
   __syncthreads();
@@ -395,19 +462,19 @@ __global__ void k_canon(int N, const double *__restrict__ E, double *__restrict_
     const double sg = E[pm * N + i] < 0 ? -1.0 : 1.0;
     const double lam = d[i];
     const double sc = sg / sqrt(lam);
-    for (int col = 0; col < N; ++col) Wh[r * N + col] = sc * E[col * N + i];
-    eig_out[r] = lam;
+    for (int col = 0; col < N; ++col) j.Wh[r * N + col] = sc * E[col * N + i];
+    j.eig[r] = lam;
   }
   __syncthreads();
   if (i == 0) {
     double mx = -INFINITY, mn = INFINITY;
     bool fin = true;
-    for (int j = 0; j < N; ++j) {
-      mx = fmax(mx, d[j]);
-      mn = fmin(mn, d[j]);
-      fin &= isfinite(d[j]);
+    for (int k = 0; k < N; ++k) {
+      mx = fmax(mx, d[k]);
+      mn = fmin(mn, d[k]);
+      fin &= isfinite(d[k]);
     }
-    if (!fin || !(mx > 0.0) || !(mn > 1e-12 * mx)) atomicOr(flags, 2);
+    if (!fin || !(mx > 0.0) || !(mn > 1e-12 * mx)) atomicOr(j.flags, 2);
   }
 }
 
@@ -430,18 +497,21 @@ __device__ inline uint16_t bf16_rne(double x) {
 }
 
 // Xw = Wh (X - mu): 64 x 64 output tiles, 4 x 4 outputs per thread, FP64.
+// A problem's tiles are numbered sample tile fastest.
 constexpr int AP_T = 64;
 constexpr int AP_K = 16;
+static inline int apply_tiles(int N, long long T) {
+  return (int)((T + AP_T - 1) / AP_T) * ((N + AP_T - 1) / AP_T);
+}
 template <typename TIN>
-__global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N, long long T,
-                                               const double *__restrict__ Wh,
-                                               const double *__restrict__ mean,
-                                               float *__restrict__ out32, uint16_t *__restrict__ outbf,
-                                               float *__restrict__ out32b) {
-  __shared__ double ws[AP_T][AP_K + 1];
-  __shared__ double xs[AP_K][AP_T + 1];
-  const long long m_base = (long long)blockIdx.x * AP_T;
-  const int i_base = blockIdx.y * AP_T;
+__device__ void apply_body(const WJob &j, int tile, double (*ws)[AP_K + 1],
+                           double (*xs)[AP_T + 1]) {
+  const TIN *X = (const TIN *)j.X;
+  const int N = j.N;
+  const long long T = j.T;
+  const int tx = (int)((T + AP_T - 1) / AP_T);
+  const long long m_base = (long long)(tile % tx) * AP_T;
+  const int i_base = (tile / tx) * AP_T;
   const int tid = threadIdx.x;
   const int tr = tid / 16, tc = tid % 16;
   double acc[4][4];
@@ -453,14 +523,14 @@ __global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N,
     __syncthreads();
     for (int e = tid; e < AP_T * AP_K; e += 256) {
       const int r = e / AP_K, k = e % AP_K;
-      const int i = i_base + r, j = j0 + k;
-      ws[r][k] = (i < N && j < N) ? Wh[i * N + j] : 0.0;
+      const int i = i_base + r, jj = j0 + k;
+      ws[r][k] = (i < N && jj < N) ? j.Wh[i * N + jj] : 0.0;
     }
     for (int e = tid; e < AP_K * AP_T; e += 256) {
       const int k = e / AP_T, s = e % AP_T;
-      const int j = j0 + k;
+      const int jj = j0 + k;
       const long long m = m_base + s;
-      xs[k][s] = (j < N && m < T) ? ld(X, (size_t)j * (size_t)T + (size_t)m) - mean[j] : 0.0;
+      xs[k][s] = (jj < N && m < T) ? ld(X, (size_t)jj * (size_t)T + (size_t)m) - j.mean[jj] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -485,11 +555,23 @@ __global__ __launch_bounds__(256) void k_apply(const TIN *__restrict__ X, int N,
       const long long m = m_base + tc + 16 * b;
       if (m >= T) continue;
       const size_t o = (size_t)i * (size_t)T + (size_t)m;
-      if (out32) out32[o] = (float)acc[a][b];
-      if (outbf) outbf[o] = bf16_rne(acc[a][b]);
-      if (out32b) out32b[o] = (float)acc[a][b];
+      if (j.o32) j.o32[o] = (float)acc[a][b];
+      if (j.obf) j.obf[o] = bf16_rne(acc[a][b]);
+      if (j.o32b) j.o32b[o] = (float)acc[a][b];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_apply(const WJob *__restrict__ jobs, WJob one,
+                                               const int *__restrict__ start, int D) {
+  __shared__ double ws[AP_T][AP_K + 1];
+  __shared__ double xs[AP_K][AP_T + 1];
+  int t = blockIdx.x;
+  const int d = start ? job_of(start, D, t) : 0;
+  if (start) t -= start[d];
+  const WJob j = start ? jobs[d] : one;
+  if (j.f64) apply_body<double>(j, t, ws, xs);
+  else apply_body<float>(j, t, ws, xs);
 }
 
 // Per-problem buffers that live from the statistics to the apply phase.
@@ -502,11 +584,16 @@ struct WhitenBufs {
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// partial sums of the statistics phase (reused problem after problem)
-static size_t stats_scratch_bytes(int N, int64_t T) {
-  return al256((size_t)n_chunks(T) * N * sizeof(double)) +
-         al256((size_t)n_cov_chunks(N, T) * N * N * sizeof(double));
+// partial sums of the statistics kernels of one problem
+static size_t mean_part_bytes(int N, int64_t T) { return al256((size_t)n_chunks(T) * N * sizeof(double)); }
+static size_t cov_part_bytes(int N, int64_t T) {
+  return al256((size_t)n_cov_chunks(N, T) * N * N * sizeof(double));
 }
+static size_t stats_scratch_bytes(int N, int64_t T) { return mean_part_bytes(N, T) + cov_part_bytes(N, T); }
+
+// The batched statistics run on groups of problems whose partial sums fit
+// this many bytes together (a single larger problem forms a group alone).
+constexpr size_t PART_CAP = size_t(256) << 20;
 
 static size_t bufs_bytes(int N) {
   return al256((size_t)N * N * sizeof(double)) +            // C
@@ -537,122 +624,191 @@ static WhitenBufs carve_bufs(char *&p, int N, double *V_out, double *mean_out, d
   return b;
 }
 
+static WJob make_wjob(const WhitenJob &w, const WhitenBufs &b, double *mpart, double *cpart,
+                      int *flags) {
+  WJob j{};
+  j.X = w.X;
+  j.f64 = w.raw_t == OICA_F64;
+  j.N = w.N;
+  j.T = w.T;
+  j.ch = n_chunks(w.T);
+  j.cch = n_cov_chunks(w.N, w.T);
+  j.mpart = mpart;
+  j.cpart = cpart;
+  j.mean = b.mean;
+  j.C = b.C;
+  j.E = b.E;
+  j.Wh = b.Wh;
+  j.eig = b.eig;
+  j.flags = flags;
+  if (w.out_t == OICA_F32) {
+    j.o32 = (float *)w.Xw;
+  } else {
+    j.obf = (uint16_t *)w.Xw;
+    j.o32b = w.Xw_f32;
+  }
+  return j;
+}
+
+// Launch ranges (W_KINDS x (D + 1) ints) of the problems of one table.
+static void job_starts(const WJob *jj, int D, int *st) {
+  for (int k = 0; k < W_KINDS; ++k) st[k * (D + 1)] = 0;
+  for (int d = 0; d < D; ++d) {
+    const WJob &j = jj[d];
+    const int cnt[W_KINDS] = {j.ch, j.N, j.N <= 64 ? j.cch : 0, j.N <= 64 ? 0 : j.cch, j.N * j.N,
+                              apply_tiles(j.N, j.T)};
+    for (int k = 0; k < W_KINDS; ++k) st[k * (D + 1) + d + 1] = st[k * (D + 1) + d] + cnt[k];
+  }
+}
+
 size_t whiten_workspace_bytes(int N, int64_t T) {
   return stats_scratch_bytes(N, T) + bufs_bytes(N) + 1024;
 }
 
-size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
-  size_t scratch = 0, b = 0;
+// Groups of consecutive problems for the batched statistics.
+static std::vector<int> stats_groups(int D, const WhitenJob *jobs, size_t *part_bytes) {
+  std::vector<int> first = {0};
+  size_t cur = 0, mx = 0;
   for (int d = 0; d < D; ++d) {
-    scratch = std::max(scratch, stats_scratch_bytes(jobs[d].N, jobs[d].T));
-    b += bufs_bytes(jobs[d].N);
+    const size_t b = stats_scratch_bytes(jobs[d].N, jobs[d].T);
+    if (cur > 0 && cur + b > PART_CAP) {
+      first.push_back(d);
+      cur = 0;
+    }
+    cur += b;
+    mx = std::max(mx, cur);
   }
-  return scratch + b + al256((size_t)D * sizeof(JacJob)) + 1024;
+  first.push_back(D);
+  *part_bytes = mx;
+  return first;
 }
 
-// mean and covariance of one problem into bufs.C / bufs.mean
-template <typename TIN>
-static void stats_phase(hipStream_t st, int N, int64_t T, const TIN *X, char *scratch,
-                        const WhitenBufs &b, int *flags) {
-  const int ch = n_chunks(T);
-  const int cch = n_cov_chunks(N, T);
-  double *mpart = (double *)scratch;
-  double *cpart = (double *)(scratch + al256((size_t)ch * N * sizeof(double)));
-  hipLaunchKernelGGL((k_mean_part<TIN>), dim3(ch), dim3(256), 0, st, X, N, (long long)T, ch, mpart,
-                     flags);
-  hipLaunchKernelGGL(k_mean_final, dim3((N + 3) / 4), dim3(256), 0, st, N, (long long)T, ch,
-                     mpart, b.mean);
-  if (N <= 64)
-    hipLaunchKernelGGL((k_cov_part<TIN, 4>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
-                       b.mean, cpart);
-  else
-    hipLaunchKernelGGL((k_cov_part<TIN, 8>), dim3(cch), dim3(256), 0, st, X, N, (long long)T, cch,
-                       b.mean, cpart);
-  hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, N, (long long)T, cch,
-                     cpart, b.C);
-}
-
-// canonical order / sign, rank check, Xw = Wh (X - mean)
-template <typename TIN>
-static void apply_phase(hipStream_t st, int N, int64_t T, const TIN *X, void *Xw, oica_dtype out_t,
-                        float *Xw_f32, const WhitenBufs &b, int *flags) {
-  hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, N, b.E, b.Wh, b.eig, flags);
-  float *o32 = nullptr, *o32b = nullptr;
-  uint16_t *obf = nullptr;
-  if (out_t == OICA_F32) {
-    o32 = (float *)Xw;
-  } else {
-    obf = (uint16_t *)Xw;
-    o32b = Xw_f32;
-  }
-  dim3 g((unsigned)((T + AP_T - 1) / AP_T), (unsigned)((N + AP_T - 1) / AP_T));
-  hipLaunchKernelGGL((k_apply<TIN>), g, dim3(256), 0, st, X, N, (long long)T, b.Wh, b.mean, o32,
-                     obf, o32b);
-}
-
-static void stats_any(hipStream_t st, const WhitenJob &j, char *scratch, const WhitenBufs &b,
-                      int *flags) {
-  if (j.raw_t == OICA_F64)
-    stats_phase<double>(st, j.N, j.T, (const double *)j.X, scratch, b, flags);
-  else
-    stats_phase<float>(st, j.N, j.T, (const float *)j.X, scratch, b, flags);
-}
-
-static void apply_any(hipStream_t st, const WhitenJob &j, const WhitenBufs &b, int *flags) {
-  if (j.raw_t == OICA_F64)
-    apply_phase<double>(st, j.N, j.T, (const double *)j.X, j.Xw, j.out_t, j.Xw_f32, b, flags);
-  else
-    apply_phase<float>(st, j.N, j.T, (const float *)j.X, j.Xw, j.out_t, j.Xw_f32, b, flags);
+size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
+  size_t part = 0, b = 0;
+  stats_groups(D, jobs, &part);
+  for (int d = 0; d < D; ++d) b += bufs_bytes(jobs[d].N);
+  // tables: Jacobi jobs, problems, launch ranges (all problems, then per group)
+  return part + b + al256((size_t)D * sizeof(JacJob)) + al256((size_t)D * sizeof(WJob)) +
+         al256((size_t)W_KINDS * (D + 1) * sizeof(int)) +
+         al256((size_t)W_KINDS * 2 * (D + 1) * sizeof(int)) + 1024;
 }
 
 hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, void *Xw,
                          oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
                          double *eig_out, void *ws, size_t ws_bytes, int *flags_dev) {
   (void)ws_bytes;
-  const WhitenJob j{N, T, X, raw_t, Xw, out_t, Xw_f32, V_out, mean_out, eig_out};
+  const WhitenJob w{N, T, X, raw_t, Xw, out_t, Xw_f32, V_out, mean_out, eig_out};
   char *scratch = (char *)ws;
   char *p = scratch + stats_scratch_bytes(N, T);
   const WhitenBufs b = carve_bufs(p, N, V_out, mean_out, eig_out);
-  stats_any(st, j, scratch, b, flags_dev);
+  const WJob j = make_wjob(w, b, (double *)scratch, (double *)(scratch + mean_part_bytes(N, T)),
+                           flags_dev);
+  hipLaunchKernelGGL(k_mean_part, dim3(j.ch), dim3(256), 0, st, nullptr, j, nullptr, 1);
+  hipLaunchKernelGGL(k_mean_final, dim3((N + 3) / 4), dim3(256), 0, st, nullptr, j, nullptr, 1, N);
+  if (N <= 64)
+    hipLaunchKernelGGL(k_cov_part<4>, dim3(j.cch), dim3(256), 0, st, nullptr, j, nullptr, 1);
+  else
+    hipLaunchKernelGGL(k_cov_part<8>, dim3(j.cch), dim3(256), 0, st, nullptr, j, nullptr, 1);
+  hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, nullptr, j, nullptr, 1,
+                     N * N);
   const JacJob job{N, b.C, b.E, b.rot, b.pq, b.sweeps};
   hipError_t e = launch_jacobi(st, 1, nullptr, job, N);
   if (e != hipSuccess) return e;
-  apply_any(st, j, b, flags_dev);
+  hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, nullptr, j);
+  hipLaunchKernelGGL(k_apply, dim3(apply_tiles(N, T)), dim3(256), 0, st, nullptr, j, nullptr, 1);
   return hipGetLastError();
 }
 
-// Many problems: statistics problem after problem (HBM-bound, one reused set
-// of partial buffers), every eigenproblem in one launch of the Jacobi kernels
-// (one work-group each), then the apply phase problem after problem.
-// flags_dev: D ints, zero on entry; the job table is copied to the device
-// first and the stream synchronised, so `jobs` may be freed on return.
+// Many problems: the statistics kernels run on groups of problems (all the
+// problems of a group in one launch each, their partial sums side by side),
+// every eigenproblem in one launch of the Jacobi kernels (one work-group
+// each), then canon and apply for every problem in one launch each.  Each
+// problem's arithmetic is that of a single call.  flags_dev: D ints, zero on
+// entry; the job tables are copied to the device first and the stream
+// synchronised, so `jobs` may be freed on return.
 hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, void *ws,
                                  int *flags_dev) {
-  size_t scratch_bytes = 0;
+  size_t part_bytes = 0;
+  const std::vector<int> groups = stats_groups(D, jobs, &part_bytes);
   int n_max = 1;
-  for (int d = 0; d < D; ++d) {
-    scratch_bytes = std::max(scratch_bytes, stats_scratch_bytes(jobs[d].N, jobs[d].T));
-    n_max = std::max(n_max, jobs[d].N);
-  }
+  for (int d = 0; d < D; ++d) n_max = std::max(n_max, jobs[d].N);
   char *scratch = (char *)ws;
-  char *p = scratch + scratch_bytes;
-  JacJob *jobs_dev = (JacJob *)p;
+  char *p = scratch + part_bytes;
+  JacJob *jac_dev = (JacJob *)p;
   p += al256((size_t)D * sizeof(JacJob));
+  WJob *wj_dev = (WJob *)p;
+  p += al256((size_t)D * sizeof(WJob));
+  int *starts_dev = (int *)p;
+  p += al256((size_t)W_KINDS * (D + 1) * sizeof(int));
   std::vector<WhitenBufs> bufs(D);
   std::vector<JacJob> jj(D);
-  for (int d = 0; d < D; ++d) {
-    bufs[d] = carve_bufs(p, jobs[d].N, jobs[d].V, jobs[d].mean, jobs[d].eig);
-    jj[d] = JacJob{jobs[d].N, bufs[d].C, bufs[d].E, bufs[d].rot, bufs[d].pq, bufs[d].sweeps};
+  std::vector<WJob> wj(D);
+  // partial buffers: offsets restart at each group
+  size_t off = 0;
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    off = 0;
+    for (int d = groups[g]; d < groups[g + 1]; ++d) {
+      bufs[d] = carve_bufs(p, jobs[d].N, jobs[d].V, jobs[d].mean, jobs[d].eig);
+      jj[d] = JacJob{jobs[d].N, bufs[d].C, bufs[d].E, bufs[d].rot, bufs[d].pq, bufs[d].sweeps};
+      double *mp = (double *)(scratch + off);
+      double *cp = (double *)(scratch + off + mean_part_bytes(jobs[d].N, jobs[d].T));
+      off += stats_scratch_bytes(jobs[d].N, jobs[d].T);
+      wj[d] = make_wjob(jobs[d], bufs[d], mp, cp, flags_dev + d);
+    }
   }
-  hipError_t e = hipMemcpyAsync(jobs_dev, jj.data(), (size_t)D * sizeof(JacJob),
+  // launch ranges: per group for the statistics kernels (ranges start at the
+  // group's first problem), over all problems for canon and apply
+  std::vector<int> starts((size_t)W_KINDS * (D + 1));
+  std::vector<int> gstarts;  // per group: W_KINDS x (size + 1)
+  std::vector<size_t> gofs;
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    const int n = groups[g + 1] - groups[g];
+    gofs.push_back(gstarts.size());
+    gstarts.resize(gstarts.size() + (size_t)W_KINDS * (n + 1));
+    job_starts(wj.data() + groups[g], n, gstarts.data() + gofs.back());
+  }
+  job_starts(wj.data(), D, starts.data());
+  int *gstarts_dev = nullptr;
+  hipError_t e = hipMemcpyAsync(jac_dev, jj.data(), (size_t)D * sizeof(JacJob),
                                 hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(wj_dev, wj.data(), (size_t)D * sizeof(WJob), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(starts_dev, starts.data(), starts.size() * sizeof(int),
+                       hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  // group ranges go after the problems' buffers
+  gstarts_dev = (int *)p;
+  e = hipMemcpyAsync(gstarts_dev, gstarts.data(), gstarts.size() * sizeof(int),
+                     hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
-  for (int d = 0; d < D; ++d) stats_any(st, jobs[d], scratch, bufs[d], flags_dev + d);
-  e = launch_jacobi(st, D, jobs_dev, jj[0], n_max);
+  for (size_t g = 0; g + 1 < groups.size(); ++g) {
+    const int d0 = groups[g], n = groups[g + 1] - groups[g];
+    const int *gs = gstarts.data() + gofs[g];
+    const int *gd = gstarts_dev + gofs[g];
+    auto tot = [&](int kind) { return gs[kind * (n + 1) + n]; };
+    auto rng = [&](int kind) { return gd + kind * (n + 1); };
+    const WJob &j0 = wj[d0];
+    hipLaunchKernelGGL(k_mean_part, dim3(tot(W_MEAN)), dim3(256), 0, st, wj_dev + d0, j0,
+                       rng(W_MEAN), n);
+    hipLaunchKernelGGL(k_mean_final, dim3((tot(W_MEANF) + 3) / 4), dim3(256), 0, st, wj_dev + d0,
+                       j0, rng(W_MEANF), n, tot(W_MEANF));
+    if (tot(W_COV4) > 0)
+      hipLaunchKernelGGL(k_cov_part<4>, dim3(tot(W_COV4)), dim3(256), 0, st, wj_dev + d0, j0,
+                         rng(W_COV4), n);
+    if (tot(W_COV8) > 0)
+      hipLaunchKernelGGL(k_cov_part<8>, dim3(tot(W_COV8)), dim3(256), 0, st, wj_dev + d0, j0,
+                         rng(W_COV8), n);
+    hipLaunchKernelGGL(k_cov_final, dim3((tot(W_COVF) + 3) / 4), dim3(256), 0, st, wj_dev + d0, j0,
+                       rng(W_COVF), n, tot(W_COVF));
+  }
+  e = launch_jacobi(st, D, jac_dev, jj[0], n_max);
   if (e != hipSuccess) return e;
-  for (int d = 0; d < D; ++d) apply_any(st, jobs[d], bufs[d], flags_dev + d);
+  hipLaunchKernelGGL(k_canon, dim3(D), dim3(NMAX), 0, st, wj_dev, wj[0]);
+  hipLaunchKernelGGL(k_apply, dim3(starts[W_APPLY * (D + 1) + D]), dim3(256), 0, st, wj_dev, wj[0],
+                     starts_dev + W_APPLY * (D + 1), D);
   return hipGetLastError();
 }
 
