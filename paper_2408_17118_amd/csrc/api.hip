@@ -738,7 +738,33 @@ void set_wk(BatchDesc &b, int wk, bool bf16) {
   b.wk = wk;
   b.kwg = WAVES_PER_WG * wk * 32;
   b.variant = variant_of(b.np, wk, bf16);
+  b.n_sp = batch_splits(b.T);
 }
+
+// FP32 data, few active rows (thin_max_rows): the thin items, one 32-row
+// block per item and one split per wave, with THIN_SPLITS times as many
+// splits (rows are padded to 32 instead of 128, and the waves of a work-group
+// all work on live rows)
+void set_thin(BatchDesc &b) {
+  b.wk = 1;
+  b.kwg = 32;
+  b.variant = THIN_VARIANT + b.np / 32 - 1;
+  b.n_sp = THIN_SPLITS * batch_splits(b.T);
+}
+
+// Most active rows for the thin items: their partials (THIN_SPLITS times the
+// splits, rows padded to 32) must fit the buffers sized for K + 256 rows.
+int thin_max_rows(int K) { return K >= 256 ? 128 : 32; }
+
+// First-stage reduction sums of one problem: enough for the regular shapes
+// (up to K rows) and for the thin ones.
+size_t red_doubles(int n_sp, int K, int np) {
+  const size_t wide = (size_t)((n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) * K;
+  const size_t thin = (size_t)((THIN_SPLITS * n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) *
+                      thin_max_rows(K);
+  return std::max(wide, thin) * (size_t)(np + 1);
+}
+bool is_thin(const BatchDesc &b) { return b.variant >= THIN_VARIANT; }
 
 void set_shapes(std::vector<BatchDesc> &hd, int wk32, int wk64, bool bf16) {
   for (auto &b : hd) set_wk(b, b.np == 32 ? wk32 : (b.np == 64 ? wk64 : 1), bf16);
@@ -792,7 +818,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     const size_t rows_cap = (size_t)q.K + 256;
     add((size_t)b.n_sp * rows_cap * b.np * 4);                              // gpart
     add((size_t)b.n_sp * rows_cap * 4);                                     // s4part
-    add((size_t)((b.n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) * q.K * (b.np + 1) * 8);  // red
+    add(red_doubles(b.n_sp, q.K, b.np) * 8);                                // red
     add((size_t)q.K * 4 * 3);                                               // act lists
     ktot += q.K;
     const FusedPlan kp = make_plan(q.N, q.T, q.K, false);
@@ -848,7 +874,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     const size_t rows_cap = (size_t)q.K + 256;
     b.gpart = cv.take<float>((size_t)b.n_sp * rows_cap * b.np);
     b.s4part = cv.take<float>((size_t)b.n_sp * rows_cap);
-    b.red = cv.take<double>((size_t)((b.n_sp + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST) * q.K * (b.np + 1));
+    b.red = cv.take<double>(red_doubles(b.n_sp, q.K, b.np));
     b.act0 = cv.take<int>(q.K);
     b.act1 = cv.take<int>(q.K);
     act2[d] = cv.take<int>(q.K);
@@ -996,6 +1022,10 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
             set_wk(hd[d], 1, data_bf16);
             reshaped = true;
           }
+          if (!data_bf16 && !is_thin(hd[d]) && kd <= thin_max_rows(hd[d].K)) {
+            set_thin(hd[d]);
+            reshaped = true;
+          }
           if (park && park_count[d] < 0 && kd > 0) {
             stalled[d] = kd >= kprev[d] ? stalled[d] + 1 : 0;
             kprev[d] = kd;
@@ -1089,8 +1119,16 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       b.X = b.X32;
       b.ld = b.ld32;
     }
-    // the FP32 passes update few rows per problem: one 32-row block per wave
+    // the FP32 passes update few rows per problem: one 32-row block per wave,
+    // and the thin items where few enough rows start
     set_shapes(hd, 1, 1, false);
+    HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data() + (size_t)D * 256, ctl_base + (size_t)D * 256,
+                                (size_t)D * 256, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int d = 0; d < D; ++d)
+      if (((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->kact[0] <=
+          thin_max_rows(hd[d].K))
+        set_thin(hd[d]);
     HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -25,8 +25,15 @@ namespace oica {
 
 constexpr int BATCH_SPLIT = 4096;   // samples per split in the batched form
 constexpr int MAX_D = 1024;         // datasets per call
-constexpr int BUF_BYTES_F32 = 36 * 1024;
+// FP32: one shared tile, or four one-wave tiles (NP = 128) for thin problems
+constexpr int BUF_BYTES_F32 = WAVES * 128 * ThinF32::sx * 4;
 constexpr int BUF_BYTES_BF16 = 2 * (128 * BSX + BT * (128 + 8)) * 2;  // two BF16 buffers at NP = 128
+
+// Work items per row block: one per split, or one per THIN_SPLITS splits for
+// thin problems (one split per wave).
+__host__ __device__ inline int split_items(const BatchDesc &b) {
+  return b.variant >= THIN_VARIANT ? (b.n_sp + THIN_SPLITS - 1) / THIN_SPLITS : b.n_sp;
+}
 
 int batch_splits(int64_t T) {
   int64_t s = (T + BATCH_SPLIT / 2) / BATCH_SPLIT;
@@ -56,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(const BatchDesc *__restrict
     long long red = 0;
     if (kact > 0) {
       const int n_kb = (kact + b.kwg - 1) / b.kwg;
-      items = n_kb * b.n_sp;
+      items = n_kb * split_items(b);
       const int groups = (b.n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
       red = (long long)groups * kact * (b.np + 1);
       epi = kact;
@@ -117,6 +124,11 @@ __device__ __noinline__ void call_bf16(const ItemCtx &c, int kb, int sp, __bf16 
   item_bf16<NP, WK>(c, kb, sp, xs, xt);
 }
 
+template <int NP>
+__device__ __noinline__ void call_f32_thin(const ItemCtx &c, int kb, int sp, float *xs) {
+  item_f32_wave<NP>(c, kb, sp, xs);
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc *__restrict__ descs,
                                                                  int D, BatchCtl *bctl,
@@ -143,6 +155,20 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
                     (pass & 1) ? b.act1 : b.act0, kact, b.gpart, b.s4part, nullptr};
     if constexpr (!BF16) {
       float *xs32 = reinterpret_cast<float *>(buf);
+      if (b.variant >= THIN_VARIANT) {
+        // thin: each wave takes its own split of the item's THIN_SPLITS
+        const int wave = threadIdx.x / 64;
+        const int spw = sp * THIN_SPLITS + wave;
+        float *xw = xs32 + wave * 128 * ThinF32::sx;
+        if (spw < b.n_sp) switch (b.variant) {
+            case THIN_VARIANT + 0: call_f32_thin<32>(c, kb, spw, xw); break;
+            case THIN_VARIANT + 1: call_f32_thin<64>(c, kb, spw, xw); break;
+            case THIN_VARIANT + 2: call_f32_thin<96>(c, kb, spw, xw); break;
+            case THIN_VARIANT + 3: call_f32_thin<128>(c, kb, spw, xw); break;
+            default: break;
+          }
+        continue;
+      }
       switch (b.variant) {
         case 0: call_f32<32, 1>(c, kb, sp, xs32); break;
         case 1: call_f32<32, 2>(c, kb, sp, xs32); break;

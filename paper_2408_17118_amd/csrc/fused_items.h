@@ -233,6 +233,146 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
 }
 
 // ---------------------------------------------------------------------------
+// One-wave FP32 item: rows kb*32 .. kb*32+31 of the active list over the
+// samples of split sp, computed by one wave alone in its own LDS tile
+// (NP x ThinF32::sx floats), so the four waves of a work-group take four
+// splits of a problem with at most 32 active rows instead of three of them
+// multiplying padding rows.  The arithmetic per row is that of item_f32 on
+// the same split: the same 32-sample sub-tiles in the same order and the
+// same MFMA sequence on each, so the partials are identical.
+// ---------------------------------------------------------------------------
+struct ThinF32 {
+  static constexpr int tt = 32;
+  static constexpr int sx = tt + 1;
+};
+
+// Orders this wave's LDS accesses before and after the point (the LDS tile
+// is private to the wave, so no work-group barrier is involved).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef __attribute__((address_space(3))) float lds_f32;
+
+template <int NP>
+__device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, float *xs_any) {
+  // the tile is in LDS: say so, so the accesses are LDS instructions with
+  // 32-bit addresses even when this runs in a separate (not inlined) function
+  lds_f32 *xs = (lds_f32 *)xs_any;
+  constexpr int HALF = NP / 2;
+  constexpr int TT = ThinF32::tt;
+  constexpr int SX = ThinF32::sx;
+  const float *__restrict__ X = (const float *)c.X;
+  const int N = c.N;
+  const long long T = c.T;
+  const int rows_pad = c.rows_pad;
+  const int kact = c.kact;
+  const float *__restrict__ Bm = c.Bm;
+  const int *__restrict__ act = c.act;
+  float *__restrict__ gpart = c.gpart;
+  float *__restrict__ s4part = c.s4part;
+  const long long ld = c.ld;
+  const int lane = threadIdx.x % 64;
+  const int h = lane / 32;
+  const int li = lane % 32;
+  const long long sub0 = (long long)sp * c.n_sub / c.n_sp;
+  const long long sub1 = (long long)(sp + 1) * c.n_sub / c.n_sp;
+  const long long t_begin = sub0 * 32;
+  long long t_end = sub1 * 32;
+  if (t_end > T) t_end = T;
+
+  const int pos = kb * 32 + li;
+  int row = -1;
+  if (pos < kact) row = act ? act[pos] : pos;
+  float breg[HALF];
+#pragma unroll
+  for (int s = 0; s < HALF; ++s) {
+    const int n = HALF * h + s;
+    breg[s] = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
+  }
+  f32x16 gacc[NP / 32];
+  float s4acc = 0.f;
+#pragma unroll
+  for (int nb = 0; nb < NP / 32; ++nb) gacc[nb] = f32x16{0.f};
+
+  constexpr int F4 = NP * TT / 4 / 64;  // 16-byte loads per lane per tile
+  constexpr int CH = 4;                 // loads in flight per lane
+  const bool vec4 = (ld % 4) == 0;
+  for (long long m_tile = t_begin; m_tile < t_end; m_tile += TT) {
+    wave_lds_sync();  // the previous tile's reads are done
+#pragma unroll 1
+    for (int q0 = 0; q0 < F4; q0 += CH) {
+      f32x4 pre[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = lane + (q0 + u) * 64;
+        const int n = e / (TT / 4);
+        const long long gm = m_tile + (e % (TT / 4)) * 4;
+        const float *src = X + (size_t)n * (size_t)ld + (size_t)gm;
+        if (n < N && vec4 && gm + 4 <= t_end) {
+          pre[u] = *reinterpret_cast<const f32x4 *>(src);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pre[u][j] = (n < N && gm + j < t_end) ? src[j] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = lane + (q0 + u) * 64;
+        const int n = e / (TT / 4);
+        const int m4 = (e % (TT / 4)) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[n * SX + m4 + j] = pre[u][j];
+      }
+    }
+    wave_lds_sync();  // the tile is in LDS
+    f32x16 zacc = f32x16{0.f};
+#pragma unroll
+    for (int s = 0; s < HALF; ++s) {
+      const float a = xs[(HALF * h + s) * SX + li];
+      zacc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, breg[s], zacc, 0, 0, 0);
+    }
+    f32x16 p3;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float z = zacc[v];
+      const float z2 = z * z;
+      p3[v] = z2 * z;
+      s4acc = fmaf(z2, z2, s4acc);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = 8 * (v / 4) + 4 * h + (v % 4);
+        const float a = xs[(nb * 32 + li) * SX + m];
+        gacc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, p3[v], gacc[nb], 0, 0, 0);
+      }
+    }
+  }
+  const float tot = s4acc + __shfl_xor(s4acc, 32);
+  if (pos < kact) {
+    if (h == 0) s4part[(size_t)sp * rows_pad + pos] = tot;
+    float *dst = gpart + ((size_t)sp * rows_pad + pos) * NP;
+#pragma unroll
+    for (int nb = 0; nb < NP / 32; ++nb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f32x4 v4;
+        v4[0] = gacc[nb][4 * q + 0];
+        v4[1] = gacc[nb][4 * q + 1];
+        v4[2] = gacc[nb][4 * q + 2];
+        v4[3] = gacc[nb][4 * q + 3];
+        *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // BF16 pass kernel: X stored in BF16, both contractions on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation; z^3 rounded to BF16
 // (nearest even) to feed GEMM2.  Each row b is split once per work item into

@@ -83,6 +83,13 @@ struct BatchDesc {
   int N, K, np, wk, kwg, n_sp, n_sub, variant;
 };
 
+// Batched FP32 variants from THIN_VARIANT on (+ np / 32 - 1), for problems
+// with few active rows: one 32-row block per work item, THIN_SPLITS
+// times the problem's usual splits, each wave of the work-group on its own
+// split (an item covers THIN_SPLITS consecutive splits).
+constexpr int THIN_VARIANT = 16;
+constexpr int THIN_SPLITS = WAVES_PER_WG;
+
 // Batch-wide counters of one pass.
 struct BatchCtl {
   int counter[2];      // work-queue heads, by pass parity
