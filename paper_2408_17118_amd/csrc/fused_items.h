@@ -19,6 +19,19 @@ namespace oica {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of the item's pointers.  The items also run inside
+// separate (not inlined) functions of the batched kernel, where pointers read
+// from a context struct are generic: spelled out as global, their loads and
+// stores are global (not flat) instructions, which do not hold up the LDS
+// waits of the MFMA loop.
+#define OICA_GLOBAL __attribute__((address_space(1)))
+typedef OICA_GLOBAL const float g_cf32;
+typedef OICA_GLOBAL float g_f32;
+typedef OICA_GLOBAL double g_f64;
+typedef OICA_GLOBAL const int g_cint;
+typedef OICA_GLOBAL const f32x4 g_cf32x4;
+typedef OICA_GLOBAL f32x4 g_f32x4;
+
 constexpr int WAVES = WAVES_PER_WG;  // waves per work-group
 // FP32 X tile in LDS: tt samples (32-sample sub-tiles) x NP features with an
 // odd row stride, so column reads hit distinct banks.  The widest variant
@@ -64,17 +77,17 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
   constexpr int HALF = NP / 2;
   constexpr int TT = TileF32<NP>::tt;
   constexpr int SX = TileF32<NP>::sx;
-  const float *__restrict__ X = (const float *)c.X;
+  g_cf32 *__restrict__ X = (g_cf32 *)c.X;
   const int N = c.N;
   const long long T = c.T;
   const int n_sp = c.n_sp;
   const int rows_pad = c.rows_pad;
-  const float *__restrict__ Bm = c.Bm;
-  const int *__restrict__ act = c.act;
+  g_cf32 *__restrict__ Bm = (g_cf32 *)c.Bm;
+  g_cint *__restrict__ act = (g_cint *)c.act;
   const int kact = c.kact;
-  float *__restrict__ gpart = c.gpart;
-  float *__restrict__ s4part = c.s4part;
-  double *__restrict__ s4part64 = c.s4part64;
+  g_f32 *__restrict__ gpart = (g_f32 *)c.gpart;
+  g_f32 *__restrict__ s4part = (g_f32 *)c.s4part;
+  g_f64 *__restrict__ s4part64 = (g_f64 *)c.s4part64;
   const int tid = threadIdx.x;
   const int wave = tid / 64;
   const int lane = tid % 64;
@@ -127,9 +140,9 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
         const int e = tid + q * WAVES * 64;
         const int n = e / (TT / 4);
         const long long gm = mt + (e % (TT / 4)) * 4;
-        const float *src = X + (size_t)n * (size_t)ld + (size_t)gm;
+        g_cf32 *src = X + (size_t)n * (size_t)ld + (size_t)gm;
         if (n < N && vec4 && gm + 4 <= t_end) {
-          pre[q] = *reinterpret_cast<const f32x4 *>(src);
+          pre[q] = *reinterpret_cast<g_cf32x4 *>(src);
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) pre[q][j] = (n < N && gm + j < t_end) ? src[j] : 0.f;
@@ -213,7 +226,7 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
         const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
         if (pos[w] < kact) {
           if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
-          float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
+          g_f32 *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
 #pragma unroll
           for (int nb = 0; nb < NP / 32; ++nb) {
 #pragma unroll
@@ -223,7 +236,7 @@ __device__ __forceinline__ void item_f32(const ItemCtx &c, int kb, int sp, float
               v4[1] = gacc[w][nb][4 * q + 1];
               v4[2] = gacc[w][nb][4 * q + 2];
               v4[3] = gacc[w][nb][4 * q + 3];
-              *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+              *reinterpret_cast<g_f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
             }
           }
         }
@@ -265,15 +278,15 @@ __device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, 
   constexpr int HALF = NP / 2;
   constexpr int TT = ThinF32::tt;
   constexpr int SX = ThinF32::sx;
-  const float *__restrict__ X = (const float *)c.X;
+  g_cf32 *__restrict__ X = (g_cf32 *)c.X;
   const int N = c.N;
   const long long T = c.T;
   const int rows_pad = c.rows_pad;
   const int kact = c.kact;
-  const float *__restrict__ Bm = c.Bm;
-  const int *__restrict__ act = c.act;
-  float *__restrict__ gpart = c.gpart;
-  float *__restrict__ s4part = c.s4part;
+  g_cf32 *__restrict__ Bm = (g_cf32 *)c.Bm;
+  g_cint *__restrict__ act = (g_cint *)c.act;
+  g_f32 *__restrict__ gpart = (g_f32 *)c.gpart;
+  g_f32 *__restrict__ s4part = (g_f32 *)c.s4part;
   const long long ld = c.ld;
   const int lane = threadIdx.x % 64;
   const int h = lane / 32;
@@ -311,9 +324,9 @@ __device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, 
         const int e = lane + (q0 + u) * 64;
         const int n = e / (TT / 4);
         const long long gm = m_tile + (e % (TT / 4)) * 4;
-        const float *src = X + (size_t)n * (size_t)ld + (size_t)gm;
+        g_cf32 *src = X + (size_t)n * (size_t)ld + (size_t)gm;
         if (n < N && vec4 && gm + 4 <= t_end) {
-          pre[u] = *reinterpret_cast<const f32x4 *>(src);
+          pre[u] = *reinterpret_cast<g_cf32x4 *>(src);
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) pre[u][j] = (n < N && gm + j < t_end) ? src[j] : 0.f;
@@ -356,7 +369,7 @@ __device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, 
   const float tot = s4acc + __shfl_xor(s4acc, 32);
   if (pos < kact) {
     if (h == 0) s4part[(size_t)sp * rows_pad + pos] = tot;
-    float *dst = gpart + ((size_t)sp * rows_pad + pos) * NP;
+    g_f32 *dst = gpart + ((size_t)sp * rows_pad + pos) * NP;
 #pragma unroll
     for (int nb = 0; nb < NP / 32; ++nb) {
 #pragma unroll
@@ -366,7 +379,7 @@ __device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, 
         v4[1] = gacc[nb][4 * q + 1];
         v4[2] = gacc[nb][4 * q + 2];
         v4[3] = gacc[nb][4 * q + 3];
-        *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+        *reinterpret_cast<g_f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
       }
     }
   }
@@ -389,6 +402,8 @@ __device__ __forceinline__ void item_f32_wave(const ItemCtx &c, int kb, int sp, 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef OICA_GLOBAL const __bf16 g_cbf16;
+typedef OICA_GLOBAL const bf16x8 g_cbf16x8;
 constexpr int BT = 64;          // samples per LDS tile
 // xs row stride (bf16): 136 bytes = 34 banks, so the 8-byte GEMM2 operand
 // reads of 32 consecutive rows hit 32 distinct bank pairs; rows are written
@@ -407,16 +422,16 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
                                           __bf16 *xt_base) {
   constexpr int KWG = WAVES * WK * 32;
   constexpr int XTS = BfStride<NP>::v;
-  const __bf16 *__restrict__ X = (const __bf16 *)c.X;
+  g_cbf16 *__restrict__ X = (g_cbf16 *)c.X;
   const int N = c.N;
   const long long T = c.T;
   const int n_sp = c.n_sp;
   const int rows_pad = c.rows_pad;
-  const float *__restrict__ Bm = c.Bm;
-  const int *__restrict__ act = c.act;
+  g_cf32 *__restrict__ Bm = (g_cf32 *)c.Bm;
+  g_cint *__restrict__ act = (g_cint *)c.act;
   const int kact = c.kact;
-  float *__restrict__ gpart = c.gpart;
-  float *__restrict__ s4part = c.s4part;
+  g_f32 *__restrict__ gpart = (g_f32 *)c.gpart;
+  g_f32 *__restrict__ s4part = (g_f32 *)c.s4part;
   const int tid = threadIdx.x;
   const int wave = tid / 64;
   const int lane = tid % 64;
@@ -476,11 +491,11 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
         const int pp = u % PAIRS, c = u / PAIRS;
         const long long gm = mt + c * 8;
         const int n0 = 2 * pp;
-        const __bf16 *src0 = X + (size_t)n0 * (size_t)ld + (size_t)gm;
-        const __bf16 *src1 = src0 + (size_t)ld;
+        g_cbf16 *src0 = X + (size_t)n0 * (size_t)ld + (size_t)gm;
+        g_cbf16 *src1 = src0 + (size_t)ld;
         if (u < UNITS && n0 + 1 < N && vec_ok && gm + 8 <= t_end) {
-          pre0[q] = *reinterpret_cast<const bf16x8 *>(src0);
-          pre1[q] = *reinterpret_cast<const bf16x8 *>(src1);
+          pre0[q] = *reinterpret_cast<g_cbf16x8 *>(src0);
+          pre1[q] = *reinterpret_cast<g_cbf16x8 *>(src1);
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
@@ -580,7 +595,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
       if (pos[w] < kact) {
         if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
-        float *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
+        g_f32 *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
 #pragma unroll
         for (int nb = 0; nb < NP / 32; ++nb) {
 #pragma unroll
@@ -590,7 +605,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
             v4[1] = gacc[w][nb][4 * q + 1];
             v4[2] = gacc[w][nb][4 * q + 2];
             v4[3] = gacc[w][nb][4 * q + 3];
-            *reinterpret_cast<f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
+            *reinterpret_cast<g_f32x4 *>(dst + nb * 32 + 8 * q + 4 * h) = v4;
           }
         }
       }
