@@ -1088,7 +1088,10 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
         HIP_TRY(ctx, hipMemcpyAsync(gjobs_dev, small.data(), small.size() * sizeof(ClusterJob),
                                     hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // `small` is a local table
-        HIP_TRY(ctx, launch_cluster_wg(ctx->stream, (int)small.size(), gjobs_dev, small[0], 1e-6));
+        int k_small = 0;
+        for (const ClusterJob &j : small) k_small = std::max(k_small, j.K);
+        HIP_TRY(ctx, launch_cluster_wg(ctx->stream, (int)small.size(), gjobs_dev, small[0], 1e-6,
+                                       k_small));
       }
       for (int d = 0; d < D; ++d)
         if (!cluster_in_one_wg(pr[d].K, true)) {

@@ -391,21 +391,25 @@ __global__ void k_update_out(FusedPlan plan, int N, long long T, int K, const fl
   }
 }
 
+// One wave per row: lanes take splits lane, lane + 64, ..., then a fixed
+// shuffle tree (the splits' partial sums are independent loads in flight).
 template <int NP>
 __global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__restrict__ s4part64,
                            double *__restrict__ kurt, const int *__restrict__ act,
                            const int *__restrict__ kact_dev) {
-  const int posn = blockIdx.x * blockDim.x + threadIdx.x;
+  const int posn = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   const int kact = kact_dev ? kact_dev[0] : K;
-  if (posn >= kact) return;
+  if (posn >= kact) return;  // uniform over the wave
   const int row = act ? act[posn] : posn;
   const int kwg = plan.kwg;
   const int n_kb = (kact + kwg - 1) / kwg;
   const int n_sp = plan_splits(plan, n_kb);
   const int rows_pad = n_kb * kwg;
   double s = 0.0;
-  for (int sp = 0; sp < n_sp; ++sp) s += s4part64[(size_t)sp * rows_pad + posn];
-  kurt[row] = s / (double)T - 3.0;
+  for (int sp = lane; sp < n_sp; sp += 64) s += s4part64[(size_t)sp * rows_pad + posn];
+  s = wave_sum(s);
+  if (lane == 0) kurt[row] = s / (double)T - 3.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -506,7 +510,7 @@ hipError_t launch_kurtosis(hipStream_t st, const FusedPlan &p, int N, int64_t T,
     hipLaunchKernelGGL((k_fused_f32<NP_, WK_, true>), dim3(p.grid), dim3(WAVES * 64), 0, st, X, N,
                        (long long)T, p, W, act, kact_dev, K, (float *)nullptr, (float *)nullptr,
                        s4part64, (FpControl *)nullptr, 0);
-    hipLaunchKernelGGL((k_kurt_out<NP_>), dim3((K + 255) / 256), dim3(256), 0, st, p,
+    hipLaunchKernelGGL((k_kurt_out<NP_>), dim3((K + 3) / 4), dim3(256), 0, st, p,
                        (long long)T, K, s4part64, kurt, act, kact_dev);
   });
   return hipGetLastError();

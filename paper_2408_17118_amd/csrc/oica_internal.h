@@ -116,7 +116,7 @@ constexpr int CW_MAX_K = 4096;
 // kernel); many problems: whenever K fits, since they run side by side.
 inline bool cluster_in_one_wg(int K, bool many) { return K <= (many ? CW_MAX_K : 256); }
 hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
-                             const ClusterJob &one, double tau);
+                             const ClusterJob &one, double tau, int k_max);
 
 // Appends `item` to list[] for every lane with `take`, with one atomic on
 // *counter per wave (lanes in lane order).  Every lane of the wave must call it.

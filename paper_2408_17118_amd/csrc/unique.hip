@@ -284,9 +284,12 @@ __device__ inline void cw_better(double &bk, int &bi, double k2, int i2) {
   }
 }
 
+// R rows per thread (K <= R * CW_THREADS); each row's dot product loads C
+// features before their FMAs (R = 1: up to 1024 rows, longer chunks keep more
+// loads in flight).
+template <int R, int C>
 __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__restrict__ jobs,
                                                            ClusterJob one, double tau) {
-  constexpr int R = CW_MAX_K / CW_THREADS;  // rows per thread
   __shared__ double lw[OICA_MAX_N];
   __shared__ double wk[CW_THREADS / 64];
   __shared__ int wi[CW_THREADS / 64];
@@ -312,7 +315,6 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
       double dot[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) dot[i] = 0.0;
-      constexpr int C = DOT_CHUNK / 2;
       for (int n0 = 0; n0 < N; n0 += C) {
         float v[R][C];  // every load of the chunk first, then the FMAs in order
 #pragma unroll
@@ -373,8 +375,12 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
 }
 
 hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
-                             const ClusterJob &one, double tau) {
-  hipLaunchKernelGGL(k_cluster_wg, dim3(D), dim3(CW_THREADS), 0, st, jobs_dev, one, tau);
+                             const ClusterJob &one, double tau, int k_max) {
+  if (k_max <= CW_THREADS)
+    hipLaunchKernelGGL((k_cluster_wg<1, 16>), dim3(D), dim3(CW_THREADS), 0, st, jobs_dev, one, tau);
+  else
+    hipLaunchKernelGGL((k_cluster_wg<CW_MAX_K / CW_THREADS, DOT_CHUNK / 2>), dim3(D),
+                       dim3(CW_THREADS), 0, st, jobs_dev, one, tau);
   return hipGetLastError();
 }
 
@@ -558,7 +564,7 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const Cl
   const float *Wt = cw.Wt;
   if (cluster_in_one_wg(K, false)) {
     const ClusterJob job{K, N, W, Wt, key, cluster, reps, ctl_dev};
-    hipError_t e = launch_cluster_wg(st, 1, nullptr, job, tau);
+    hipError_t e = launch_cluster_wg(st, 1, nullptr, job, tau, K);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(ctl_host, ctl_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
@@ -717,7 +723,9 @@ hipError_t launch_unique_batched(hipStream_t st, int D, UJob *jobs, void *ws, in
   hipLaunchKernelGGL(k_any_conv, dim3(nb, D), dim3(U_BLOCK), 0, st, jobs_dev, none);
   hipLaunchKernelGGL(k_prep, dim3(nb, D), dim3(U_BLOCK), 0, st, jobs_dev, none);
   if (!small.empty()) {
-    e = launch_cluster_wg(st, (int)small.size(), cjobs_dev, small[0], jobs[0].tau);
+    int k_small = 0;
+    for (const ClusterJob &j : small) k_small = std::max(k_small, j.K);
+    e = launch_cluster_wg(st, (int)small.size(), cjobs_dev, small[0], jobs[0].tau, k_small);
     if (e != hipSuccess) return e;
   }
   for (int d = 0; d < D; ++d)
