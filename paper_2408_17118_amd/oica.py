@@ -146,11 +146,21 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _dev(t, name):
+def _dev(t, name, dtype=None, shape=None):
+    """Check a device argument before its pointer crosses the C ABI, which
+    cannot see dtypes or sizes: dtype (one or a tuple) and shape (None entries
+    match any size) as the call documents."""
     if not (isinstance(t, torch.Tensor) and t.is_cuda):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if dtype is not None:
+        ok = dtype if isinstance(dtype, tuple) else (dtype,)
+        if t.dtype not in ok:
+            raise TypeError(f"{name} must have dtype {' or '.join(str(d) for d in ok)}, not {t.dtype}")
+    if shape is not None:
+        if t.dim() != len(shape) or any(w is not None and w != v for w, v in zip(shape, t.shape)):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
     return t
 
 
@@ -194,7 +204,7 @@ class Context:
     def whiten(self, X: torch.Tensor, out_dtype=torch.float32, want_f32=True):
         """X: N x T raw data (float64 or float32, device).  Returns
         (Xw, Xw_f32, V, mean, eigval); Xw_f32 is Xw itself for FP32 output."""
-        _dev(X, "X")
+        _dev(X, "X", (torch.float64, torch.float32), (None, None))
         N, T = X.shape
         dev = self._tdev()
         Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
@@ -219,7 +229,7 @@ class Context:
         dev = self._tdev()
         outs = []
         for d, X in enumerate(Xs):
-            _dev(X, "X")
+            _dev(X, "X", (torch.float64, torch.float32), (None, None))
             N, T = X.shape
             Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
             Xw32 = None
@@ -241,15 +251,13 @@ class Context:
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
                     tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
                     refine_groups=True, pruner=None, prune_pass=8, guard_top=20, guard_min=4):
-        _dev(Xw, "Xw")
-        _dev(W0, "W0")
-        if W0.dtype != torch.float32:
-            raise TypeError("W0 must be float32")
+        _dev(Xw, "Xw", torch.bfloat16 if precision == "bf16" else torch.float32, (None, None))
         N, T = Xw.shape
+        _dev(W0, "W0", torch.float32, (None, N))
         K = W0.shape[0]
         if Xw_f32 is None:
             Xw_f32 = Xw
-        _dev(Xw_f32, "Xw_f32")
+        _dev(Xw_f32, "Xw_f32", torch.float32, (N, T))
         dev = self._tdev()
         W = torch.empty((K, N), dtype=torch.float32, device=dev)
         kurt = torch.empty(K, dtype=torch.float64, device=dev)
@@ -282,10 +290,11 @@ class Context:
         outs = []
         dev = self._tdev()
         for d, q in enumerate(problems):
-            Xw = _dev(q["Xw"], "Xw")
-            X32 = _dev(q.get("Xw_f32", Xw), "Xw_f32")
-            W0 = _dev(q["W0"], "W0")
+            Xw = _dev(q["Xw"], f"problem {d} Xw",
+                      torch.bfloat16 if precision == "bf16" else torch.float32, (None, None))
             N, T = Xw.shape
+            X32 = _dev(q.get("Xw_f32", Xw), f"problem {d} Xw_f32", torch.float32, (N, T))
+            W0 = _dev(q["W0"], f"problem {d} W0", torch.float32, (None, N))
             K = W0.shape[0]
             o = {"W": torch.empty((K, N), dtype=torch.float32, device=dev),
                  "kurt": torch.empty(K, dtype=torch.float64, device=dev),
@@ -311,9 +320,9 @@ class Context:
         return outs, stats
 
     def update(self, Xw, B):
-        _dev(Xw, "Xw")
-        _dev(B, "B")
+        _dev(Xw, "Xw", (torch.float32, torch.bfloat16), (None, None))
         N, T = Xw.shape
+        _dev(B, "B", torch.float32, (None, N))
         K = B.shape[0]
         G = torch.empty((K, N), dtype=torch.float64, device=self._tdev())
         s4 = torch.empty(K, dtype=torch.float64, device=self._tdev())
@@ -322,9 +331,9 @@ class Context:
         return G, s4
 
     def kurtosis(self, Xw_f32, W):
-        _dev(Xw_f32, "Xw_f32")
-        _dev(W, "W")
+        _dev(Xw_f32, "Xw_f32", torch.float32, (None, None))
         N, T = Xw_f32.shape
+        _dev(W, "W", torch.float32, (None, N))
         K = W.shape[0]
         kurt = torch.empty(K, dtype=torch.float64, device=self._tdev())
         rc = self.lib.oica_kurtosis(self.h, N, T, _ptr(Xw_f32), K, _ptr(W), _ptr(kurt))
@@ -334,8 +343,10 @@ class Context:
     # ---- a12-a13 ----------------------------------------------------------------
     def unique(self, W, kurt, status, T, tau=1e-3, gaussianity_test=True, n_top=0, cap=None,
                row_cluster=False):
-        _dev(W, "W")
+        _dev(W, "W", torch.float32, (None, None))
         K, N = W.shape
+        _dev(kurt, "kurt", torch.float64, (K,))
+        _dev(status, "status", torch.uint8, (K,))
         cap = K if cap is None else cap
         dev = self._tdev()
         U = torch.empty((max(cap, 1), N), dtype=torch.float64, device=dev)
@@ -364,8 +375,10 @@ class Context:
         dev = self._tdev()
         outs = []
         for d, (W, kurt, status, T) in enumerate(items):
-            _dev(W, "W")
+            _dev(W, f"item {d} W", torch.float32, (None, None))
             K, N = W.shape
+            _dev(kurt, f"item {d} kurt", torch.float64, (K,))
+            _dev(status, f"item {d} status", torch.uint8, (K,))
             o = {"U": torch.empty((K, N), dtype=torch.float64, device=dev),
                  "alpha": torch.empty(K, dtype=torch.float64, device=dev),
                  "upsilon": torch.empty(K, dtype=torch.float64, device=dev),
@@ -431,7 +444,7 @@ class Pruner:
         self.theta = float(theta)
 
     def predict(self, traj):
-        _dev(traj, "traj")
+        _dev(traj, "traj", torch.float32, (None, 8, 2))
         R = traj.shape[0]
         prob = torch.empty(R, dtype=torch.float32, device=traj.device)
         self.ctx._check(self.ctx.lib.oica_pruner_predict(self.ctx.h, self.h, _ptr(traj), R,
@@ -439,7 +452,9 @@ class Pruner:
         return prob
 
     def grad(self, traj, labels, w_pos):
+        _dev(traj, "traj", torch.float32, (None, 8, 2))
         R = traj.shape[0]
+        _dev(labels, "labels", torch.uint8, (R,))
         g = torch.empty(self.N_PARAMS, dtype=torch.float32, device=traj.device)
         loss = C.c_double()
         self.ctx._check(self.ctx.lib.oica_pruner_grad(self.ctx.h, self.h, _ptr(traj), _ptr(labels),
@@ -447,7 +462,9 @@ class Pruner:
         return g, loss.value
 
     def train_step(self, traj, labels, w_pos, lr=1e-3):
+        _dev(traj, "traj", torch.float32, (None, 8, 2))
         R = traj.shape[0]
+        _dev(labels, "labels", torch.uint8, (R,))
         loss = C.c_double()
         self.ctx._check(self.ctx.lib.oica_pruner_train_step(self.ctx.h, self.h, _ptr(traj),
                                                             _ptr(labels), R, float(w_pos),

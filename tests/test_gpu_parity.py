@@ -135,6 +135,36 @@ def test_whiten_errors(ctx):
     assert e.value.code == -7
 
 
+def test_binding_rejects_wrong_dtypes_and_shapes(ctx):
+    """The C ABI takes plain pointers, so the binding checks every tensor's dtype
+    and shape before a call: a BF16 tensor where the FP32 copy belongs, or a row
+    block of the wrong width, raise on the host and no kernel runs."""
+    import torch
+    N, T, K = 8, 1000, 16
+    Xb = torch.zeros((N, T), dtype=torch.bfloat16, device="cuda")
+    X32 = torch.zeros((N, T), dtype=torch.float32, device="cuda")
+    W0 = torch.ones((K, N), dtype=torch.float32, device="cuda")
+    with pytest.raises(TypeError):
+        ctx.fixed_point(Xb, W0, precision="bf16")              # Xw_f32 defaults to Xw
+    with pytest.raises(TypeError):
+        ctx.fixed_point(Xb, W0, Xw_f32=Xb, precision="bf16")
+    with pytest.raises(TypeError):
+        ctx.fixed_point(X32, W0, precision="bf16")             # data type of the precision
+    with pytest.raises(ValueError):
+        ctx.fixed_point(X32, W0[:, :4].contiguous())
+    with pytest.raises(ValueError):
+        ctx.fixed_point(Xb, W0, Xw_f32=X32[:, :500].contiguous(), precision="bf16")
+    with pytest.raises(TypeError):
+        ctx.fixed_point_batched([{"Xw": Xb, "Xw_f32": Xb, "W0": W0}], precision="bf16")
+    with pytest.raises(TypeError):
+        ctx.kurtosis(Xb, W0)
+    with pytest.raises(TypeError):
+        ctx.unique(W0, torch.zeros(K, dtype=torch.float32, device="cuda"),
+                   torch.zeros(K, dtype=torch.uint8, device="cuda"), T)
+    with pytest.raises(TypeError):
+        ctx.whiten(torch.zeros((N, T), dtype=torch.float16, device="cuda"))
+
+
 def test_whiten_batched_equals_single(ctx):
     """One batched call gives every dataset exactly the single call's outputs
     (same kernels, one Jacobi launch for all eigenproblems)."""
