@@ -192,9 +192,12 @@ def main():
     peak = PEAK_BF16_MFMA_TFLOPS if bf16 else PEAK_FP32_MFMA_TFLOPS
     np_ = ((N + 31) // 32) * 32
     wk_ = 2 if np_ <= 64 else 1
-    tail = f"; <{np_},1> in passes with <= 128 active rows" if wk_ == 2 else ""
-    kname = (f"k_fused_bf16<{np_},{wk_}> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA{tail})"
-             if bf16 else f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA{tail})")
+    if bf16:
+        tail = f"; <{np_},1> in passes with <= 128 active rows" if wk_ == 2 else ""
+        kname = f"k_fused_bf16<{np_},{wk_}> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA{tail})"
+    else:
+        kname = (f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA; "
+                 f"k_fused_f32_thin<{np_}> in passes with <= 128 active rows)")
     last = runs[-1]
     out = {
         "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",

@@ -254,12 +254,14 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
   int stalled = 0;
   *launched = 0;
   *kernel_ms = 0.0;
-  const FusedPlan narrow = narrow_plan(plan);
+  // at most one narrow row block active: one 32-row block per wave (same
+  // splits, BF16), or the thin items (FP32)
+  const FusedPlan narrow = bf16 ? narrow_plan(plan) : thin_plan(plan);
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
-    // at most one narrow row block active: the narrow plan (same splits)
-    const FusedPlan &pp = (plan.kwg > narrow.kwg && kmax <= narrow.kwg) ? narrow : plan;
+    const FusedPlan &pp = kmax <= WAVES_PER_WG * 32 && (plan.kwg > WAVES_PER_WG * 32 || !bf16)
+                              ? narrow : plan;
     if (profile) {
       while ((int)ctx->events.size() < 2 * (pass + 1)) {
         hipEvent_t e;

@@ -39,6 +39,15 @@ FusedPlan narrow_plan(const FusedPlan &p) {
   return q;
 }
 
+// FP32 passes with at most WAVES * 32 active rows: thin items (rows padded to
+// 32, each wave on its own split, WAVES times the splits).
+FusedPlan thin_plan(const FusedPlan &p) {
+  FusedPlan q = p;
+  q.kwg = 32;
+  q.thin = 1;
+  return q;
+}
+
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
   (void)kmax;
   (void)bf16;
@@ -89,10 +98,17 @@ size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax) {
   int np = fused_np(N);
   size_t worst = 0;
   // the partial buffer holds n_splits(n_kb) * n_kb * kwg rows; take the max
-  // over every n_kb a run can reach
+  // over every n_kb a run can reach, with the plan and with its thin form
+  // (used while at most WAVES * 32 rows are active)
   int kb_max = (kmax + p.kwg - 1) / p.kwg;
   for (int nkb = 1; nkb <= kb_max; ++nkb) {
     size_t rows = (size_t)plan_splits(p, nkb) * (size_t)nkb * (size_t)p.kwg;
+    if (rows > worst) worst = rows;
+  }
+  const FusedPlan t = thin_plan(p);
+  const int thin_rows = kmax < WAVES * 32 ? kmax : WAVES * 32;
+  for (int nkb = 1; nkb <= (thin_rows + 31) / 32; ++nkb) {
+    size_t rows = (size_t)plan_splits(t, nkb) * (size_t)nkb * 32;
     if (rows > worst) worst = rows;
   }
   return worst * (size_t)np;
@@ -131,6 +147,43 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32(
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
     item_f32<NP, WK, KURT>(c, w_item % n_kb, w_item / n_kb, xs);
+  }
+}
+
+// FP32 pass with the thin plan: work item (32-row block kb, split group g),
+// wave w of the work-group on split WAVES * g + w with its own LDS tile.
+template <int NP>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32_thin(
+    const float *__restrict__ X, int N, long long T, FusedPlan plan,
+    const float *__restrict__ Bm, const int *__restrict__ act, const int *__restrict__ kact_dev,
+    int kact_host, float *__restrict__ gpart, float *__restrict__ s4part, FpControl *ctl,
+    int pass) {
+  __shared__ float xs[WAVES * NP * ThinF32::sx];
+  const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
+  if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->kact[(pass + 1) & 1] = 0;
+    if (kact > 0) {
+      ctl->passes = pass + 1;
+      ctl->thread_iters += kact;
+    }
+  }
+  if (kact <= 0) return;
+  const int n_kb = (kact + 31) / 32;
+  const int n_sp = plan_splits(plan, n_kb);
+  const int groups = (n_sp + WAVES - 1) / WAVES;
+  const int work = n_kb * groups;
+  const int per_xcd_items = (work + 7) / 8;
+  const int per_xcd_wgs = plan.grid / 8;
+  const int xcd = blockIdx.x % 8;
+  const int local = blockIdx.x / 8;
+  const int wave = threadIdx.x / 64;
+  const ItemCtx c{X, N, T, plan.ld, plan.n_sub, n_sp, n_kb * 32, Bm, act, kact, gpart, s4part,
+                  nullptr};
+  for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
+    const int w_item = xcd * per_xcd_items + it;
+    if (w_item >= work) break;
+    const int sp = (w_item / n_kb) * WAVES + wave;
+    if (sp < n_sp) item_f32_wave<NP>(c, w_item % n_kb, sp, xs + wave * NP * ThinF32::sx);
   }
 }
 
@@ -450,6 +503,14 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
         hipLaunchKernelGGL((k_fused_bf16<NP_, 1>), dim3(p.grid), dim3(WAVES * 64), 0, st,
                            (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,
                            gpart, s4part, ctl, pass);
+    });
+    return hipGetLastError();
+  }
+  if (p.thin) {
+    OICA_NP_SWITCH(np, {
+      hipLaunchKernelGGL((k_fused_f32_thin<NP_>), dim3(p.grid), dim3(WAVES * 64), 0, st,
+                         (const float *)X, N, (long long)T, p, B, act, kact_dev, kact_host, gpart,
+                         s4part, ctl, pass);
     });
     return hipGetLastError();
   }

@@ -32,6 +32,8 @@ struct FusedPlan {
   int kwg;          // rows per work-group
   int n_sub;        // 32-sample sub-tiles covering T
   long long ld;     // row stride of X in elements (T, or T rounded up for 16-byte rows)
+  int thin = 0;     // FP32 only: one 32-row block per item, each wave of a
+                    // work-group on its own split (WAVES_PER_WG times the splits)
 };
 
 // Row stride that makes every row of X start on a 16-byte boundary.
@@ -47,7 +49,7 @@ hipError_t launch_pad_rows(hipStream_t st, const void *src, int esize, int N, lo
 // device evaluate the same expression.
 __host__ __device__ inline int plan_splits(const FusedPlan &p, int n_kb) {
   if (n_kb <= 0) return 0;
-  int s = p.grid / n_kb;
+  int s = (p.thin ? WAVES_PER_WG * p.grid : p.grid) / n_kb;
   if (s > p.max_splits) s = p.max_splits;
   if (s < 1) s = 1;
   return s;
@@ -165,6 +167,7 @@ size_t whiten_workspace_bytes(int N, int64_t T);
 // fixed_point.hip
 int fused_np(int N);  // padded feature count used by the kernels for N
 FusedPlan narrow_plan(const FusedPlan &p);
+FusedPlan thin_plan(const FusedPlan &p);
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16);
 size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
 

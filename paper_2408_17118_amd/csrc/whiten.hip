@@ -237,6 +237,8 @@ __global__ void k_cov_final(const WJob *__restrict__ jobs, WJob one, const int *
 //                     log round by round.
 // Several matrices (the batched whitening) run in one launch, one job each.
 constexpr int JAC_THREADS = 1024;
+// 2 x 2 blocks per thread and round, at most: npair (npair / 2 + 1) blocks
+constexpr int JAC_UNITS = ((NMAX / 2) * (NMAX / 4 + 1) + JAC_THREADS - 1) / JAC_THREADS;
 constexpr int JAC_MAX_SWEEPS = 30;
 constexpr double JAC_EPS = 2.220446049250313e-16;
 constexpr int JV_ROWS = 8;       // rows of E per work-group
@@ -326,20 +328,37 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
       }
       __syncthreads();
       // block (k, l), l = k + m (mod npair): every unordered pair of index
-      // pairs once (m = H twice when npair is even: keep k < H)
-      for (int u = tid; u < units; u += JAC_THREADS) {
+      // pairs once (m = H twice when npair is even: keep k < H).  The blocks
+      // of a round hold disjoint elements, so a thread loads all of its
+      // blocks before it stores any (one LDS latency per round, not one per
+      // block).
+      double b[JAC_UNITS][4];
+      int kk[JAC_UNITS], ll[JAC_UNITS];
+#pragma unroll
+      for (int j = 0; j < JAC_UNITS; ++j) {
+        const int u = tid + j * JAC_THREADS;
+        kk[j] = -1;
+        if (u >= units) continue;
         const int m = u / npair, k = u - m * npair;
         if (m == H && !((npair & 1) || k < H)) continue;
         int l = k + m;
         if (l >= npair) l -= npair;
-        const double sk = rs[k], sl = rs[l];
-        if (sk == 0.0 && sl == 0.0) continue;
-        const double ck = rc[k], cl = rc[l];
+        if (rs[k] == 0.0 && rs[l] == 0.0) continue;
+        kk[j] = k;
+        ll[j] = l;
         const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
-        const double b00 = a[jac_sym(pk, pl, LD)];
-        const double b01 = ql >= 0 ? a[jac_sym(pk, ql, LD)] : 0.0;
-        const double b10 = qk >= 0 ? a[jac_sym(qk, pl, LD)] : 0.0;
-        const double b11 = (qk >= 0 && ql >= 0) ? a[jac_sym(qk, ql, LD)] : 0.0;
+        b[j][0] = a[jac_sym(pk, pl, LD)];
+        b[j][1] = ql >= 0 ? a[jac_sym(pk, ql, LD)] : 0.0;
+        b[j][2] = qk >= 0 ? a[jac_sym(qk, pl, LD)] : 0.0;
+        b[j][3] = (qk >= 0 && ql >= 0) ? a[jac_sym(qk, ql, LD)] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < JAC_UNITS; ++j) {
+        const int k = kk[j], l = ll[j];
+        if (k < 0) continue;
+        const double sk = rs[k], sl = rs[l], ck = rc[k], cl = rc[l];
+        const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
+        const double b00 = b[j][0], b01 = b[j][1], b10 = b[j][2], b11 = b[j][3];
         // rows of pair k, then columns of pair l
         const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
         const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
