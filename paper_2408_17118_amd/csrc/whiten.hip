@@ -411,20 +411,29 @@ __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__r
       pqs[x] = jb.pq[(size_t)r0 * npair + x];
     }
     __syncthreads();
+    // a row of E is one wave's alone: lane k applies pair k of every round in
+    // turn, and the wave's LDS accesses complete in order, so the rounds of a
+    // chunk need no work-group barrier
+    const int lane = tid % 64, wave = tid / 64;
     for (int rr = 0; rr < nr; ++rr) {
-      for (int u = tid; u < rows * npair; u += JV_THREADS) {
-        const int i = u / npair, k = u - i * npair;
-        const double2 v = cs[rr * npair + k];
-        if (v.y == 0.0) continue;
-        const int pq = pqs[rr * npair + k];
-        const int p = pq & 0xFFFF, q = pq >> 16;
-        const double x0 = e[i][p], x1 = e[i][q];
-        e[i][p] = v.x * x0 - v.y * x1;
-        e[i][q] = v.y * x0 + v.x * x1;
+      if (lane < npair) {
+        const double2 v = cs[rr * npair + lane];
+        if (v.y != 0.0) {
+          const int pq = pqs[rr * npair + lane];
+          const int p = pq & 0xFFFF, q = pq >> 16;
+          for (int i = wave; i < rows; i += JV_THREADS / 64) {
+            const double x0 = e[i][p], x1 = e[i][q];
+            e[i][p] = v.x * x0 - v.y * x1;
+            e[i][q] = v.y * x0 + v.x * x1;
+          }
+        }
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+  __syncthreads();
   for (int x = tid; x < rows * N; x += JV_THREADS) {
     const int i = x / N, j = x % N;
     jb.E[(size_t)(row0 + i) * N + j] = e[i][j];
