@@ -1028,6 +1028,15 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
             set_thin(hd[d]);
             reshaped = true;
           }
+          // BF16, few rows: THIN_SPLITS times the splits (shorter items, so the
+          // long latency-bound items of a few problems no longer set the pass);
+          // the partial buffers (K + 256 rows per split) must hold the
+          // THIN_SPLITS x 128 padded rows
+          if (data_bf16 && hd[d].wk == 1 && hd[d].n_sp == batch_splits(hd[d].T) &&
+              kd <= thin_max_rows(hd[d].K) && THIN_SPLITS * hd[d].kwg <= hd[d].K + 256) {
+            hd[d].n_sp = THIN_SPLITS * batch_splits(hd[d].T);
+            reshaped = true;
+          }
           if (park && park_count[d] < 0 && kd > 0) {
             stalled[d] = kd >= kprev[d] ? stalled[d] + 1 : 0;
             kprev[d] = kd;
