@@ -254,14 +254,15 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
   int stalled = 0;
   *launched = 0;
   *kernel_ms = 0.0;
-  // at most one narrow row block active: one 32-row block per wave (same
-  // splits, BF16), or the thin items (FP32)
+  // few rows active: the thin items (FP32, up to THIN_PLAN_ROWS rows), or one
+  // 32-row block per wave (BF16, at most one such row block; same splits)
   const FusedPlan narrow = bf16 ? narrow_plan(plan) : thin_plan(plan);
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
-    const FusedPlan &pp = kmax <= WAVES_PER_WG * 32 && (plan.kwg > WAVES_PER_WG * 32 || !bf16)
-                              ? narrow : plan;
+    const bool few = bf16 ? (kmax <= WAVES_PER_WG * 32 && plan.kwg > WAVES_PER_WG * 32)
+                          : kmax <= THIN_PLAN_ROWS;
+    const FusedPlan &pp = few ? narrow : plan;
     if (profile) {
       while ((int)ctx->events.size() < 2 * (pass + 1)) {
         hipEvent_t e;

@@ -39,8 +39,8 @@ FusedPlan narrow_plan(const FusedPlan &p) {
   return q;
 }
 
-// FP32 passes with at most WAVES * 32 active rows: thin items (rows padded to
-// 32, each wave on its own split, WAVES times the splits).
+// FP32 passes with at most THIN_PLAN_ROWS active rows: thin items (rows padded
+// to 32, each wave on its own split, WAVES times the splits).
 FusedPlan thin_plan(const FusedPlan &p) {
   FusedPlan q = p;
   q.kwg = 32;
@@ -99,14 +99,14 @@ size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax) {
   size_t worst = 0;
   // the partial buffer holds n_splits(n_kb) * n_kb * kwg rows; take the max
   // over every n_kb a run can reach, with the plan and with its thin form
-  // (used while at most WAVES * 32 rows are active)
+  // (used while at most THIN_PLAN_ROWS rows are active)
   int kb_max = (kmax + p.kwg - 1) / p.kwg;
   for (int nkb = 1; nkb <= kb_max; ++nkb) {
     size_t rows = (size_t)plan_splits(p, nkb) * (size_t)nkb * (size_t)p.kwg;
     if (rows > worst) worst = rows;
   }
   const FusedPlan t = thin_plan(p);
-  const int thin_rows = kmax < WAVES * 32 ? kmax : WAVES * 32;
+  const int thin_rows = kmax < THIN_PLAN_ROWS ? kmax : THIN_PLAN_ROWS;
   for (int nkb = 1; nkb <= (thin_rows + 31) / 32; ++nkb) {
     size_t rows = (size_t)plan_splits(t, nkb) * (size_t)nkb * 32;
     if (rows > worst) worst = rows;

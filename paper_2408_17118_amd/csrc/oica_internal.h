@@ -168,6 +168,9 @@ size_t whiten_workspace_bytes(int N, int64_t T);
 int fused_np(int N);  // padded feature count used by the kernels for N
 FusedPlan narrow_plan(const FusedPlan &p);
 FusedPlan thin_plan(const FusedPlan &p);
+// Most active rows for the thin FP32 plan (rows padded to 32 instead of the
+// plan's 128 or 256).
+constexpr int THIN_PLAN_ROWS = 2 * WAVES_PER_WG * 32;
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16);
 size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
 
