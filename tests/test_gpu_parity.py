@@ -212,8 +212,12 @@ def _rowwise_abs_cos(A, B):
 
 
 @pytest.mark.parametrize("N,T,K,seed", [(8, 10_000, 256, 0), (24, 20_000, 700, 1),
-                                        (64, 30_000, 1024, 2)])
+                                        (64, 30_000, 1024, 2), (128, 30_011, 200, 3),
+                                        (90, 15_000, 333, 4)])
 def test_fixed_point_matches_oracle(ctx, N, T, K, seed):
+    """Per-row agreement with the oracle from the same starts.  The cases cover
+    every padded width (32 ... 128), ragged T, and runs that start on the thin
+    items (K <= 256) or switch to them as rows converge."""
     if N == 8:
         p = synth.small_mixture()
     else:
