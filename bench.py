@@ -197,7 +197,7 @@ def main():
         kname = f"k_fused_bf16<{np_},{wk_}> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA{tail})"
     else:
         kname = (f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA; "
-                 f"k_fused_f32_thin<{np_}> in passes with <= 128 active rows)")
+                 f"k_fused_f32_thin<{np_}> in passes with <= 256 active rows)")
     last = runs[-1]
     out = {
         "metric": "thread-iterations/sec (K*N*T MACs) + time-to-unique-components vs plain FP32",

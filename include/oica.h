@@ -92,23 +92,28 @@ int oica_set_stream(oica_ctx *ctx, void *hip_stream);
  *   C = E D E^T, eigenvalues descending, each eigenvector's largest-magnitude
  *   entry positive;  V = D^(-1/2) E^T;  Xw = V (X - mean).
  *
- * N in [1, OICA_MAX_N], T > N.  X_raw: N x T of raw_t (OICA_F64 or OICA_F32).
+ * N in [1, OICA_MAX_N], T > N.  X_raw: N x T of raw_t (OICA_F64 or OICA_F32),
+ *   row n starting at element n * ld_raw (ld_raw >= T, in elements; ld_raw == T
+ *   for a contiguous array), so that a window of a longer recording is read in
+ *   place.  Only the first T elements of each row are read.
  * Xw: N x T of out_t (OICA_F32 or OICA_BF16, round to nearest even).
  * Xw_f32: optional extra FP32 copy (N x T) written when out_t == OICA_BF16,
  *   needed later by the FP32 refinement and by the final kurtosis; NULL to skip.
  * V (N x N), mean (N), eigval (N): FP64 outputs; any may be NULL.
- * Synchronises.  Errors: OICA_E_ARG, OICA_E_UNSUPPORTED (N > OICA_MAX_N),
- * OICA_E_NONFINITE (NaN/Inf in X_raw), OICA_E_RANK (smallest eigenvalue
- * <= 1e-12 x largest), OICA_E_NOMEM, OICA_E_DEVICE.
+ * Synchronises.  Errors: OICA_E_ARG, OICA_E_SHAPE (ld_raw < T),
+ * OICA_E_UNSUPPORTED (N > OICA_MAX_N), OICA_E_NONFINITE (NaN/Inf in X_raw),
+ * OICA_E_RANK (smallest eigenvalue <= 1e-12 x largest), OICA_E_NOMEM,
+ * OICA_E_DEVICE.
  * ------------------------------------------------------------------------- */
 int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t,
-                void *Xw, oica_dtype out_t, float *Xw_f32,
+                int64_t ld_raw, void *Xw, oica_dtype out_t, float *Xw_f32,
                 double *V, double *mean, double *eigval);
 
 /* Batched whitening: D problems, each exactly as in oica_whiten (same outputs,
- * same arithmetic), with every covariance eigenproblem solved in one launch
- * (one work-group per problem) instead of D.  The statistics and apply passes
- * run problem after problem on the stream.
+ * same arithmetic).  Every pass covers all problems in one launch: the
+ * statistics passes (in groups when their partial sums would exceed a fixed
+ * scratch cap), the covariance eigenproblems (one work-group per problem) and
+ * the apply pass.
  *
  * problems: host array of D (1..1024) descriptors; every pointer in it is a
  * device pointer as in oica_whiten.  out_t applies to every problem.  status
@@ -121,6 +126,7 @@ typedef struct {
   int64_t T;
   const void *X_raw;
   oica_dtype raw_t;
+  int64_t ld_raw;       /* row stride of X_raw in elements, >= T */
   void *Xw;
   float *Xw_f32;        /* nullable */
   double *V, *mean, *eigval;  /* nullable */
@@ -263,6 +269,20 @@ int oica_pruner_grad(oica_ctx *ctx, const oica_pruner *p, const float *traj,
  * given; the loss before the step goes to *loss (host, may be NULL). */
 int oica_pruner_train_step(oica_ctx *ctx, oica_pruner *p, const float *traj,
                            const uint8_t *labels, int64_t R, float w_pos, float lr, double *loss);
+/* Training run: epochs passes over the R rows (traj: R x 8 x 2 FP32, labels:
+ * R, device), each in a fresh pseudo-random order drawn from seed and the
+ * epoch number (a keyed permutation evaluated on the device, so the same seed
+ * gives the same weights), cut into consecutive steps of batch rows (the last
+ * one shorter); every step is oica_pruner_train_step on its rows.  w_pos: the
+ * positive-class weight, or 0 for n_negative / n_positive of the labels.
+ * epoch_loss: host, epochs doubles (may be NULL): the mean over the epoch's
+ * steps of each step's loss before its update.  Synchronises when it counts
+ * the labels or reports losses.  Errors: OICA_E_ARG (null pointers, R < 1,
+ * epochs outside [1, 100000], batch < 1, lr <= 0, w_pos < 0, all labels
+ * positive with w_pos 0), OICA_E_NOMEM, OICA_E_DEVICE. */
+int oica_pruner_train(oica_ctx *ctx, oica_pruner *p, const float *traj, const uint8_t *labels,
+                      int64_t R, int epochs, int batch, float w_pos, float lr, uint64_t seed,
+                      double *epoch_loss);
 
 /* ---------------------------------------------------------------------------
  * Batched form: D independent problems of uneven N, T and K run the passes of

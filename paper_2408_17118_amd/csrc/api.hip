@@ -150,8 +150,9 @@ int oica_set_stream(oica_ctx *ctx, void *hip_stream) {
 }
 
 // ---------------------------------------------------------------------------
-int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t, void *Xw,
-                oica_dtype out_t, float *Xw_f32, double *V, double *mean, double *eigval) {
+int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t,
+                int64_t ld_raw, void *Xw, oica_dtype out_t, float *Xw_f32, double *V,
+                double *mean, double *eigval) {
   if (!ctx) return OICA_E_ARG;
   ctx->err.clear();
   int rc = check_dims(ctx, N, T);
@@ -159,13 +160,16 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
   if (!X_raw || !Xw) return fail(ctx, OICA_E_ARG, "X_raw and Xw must be non-null");
   if (raw_t != OICA_F64 && raw_t != OICA_F32)
     return fail(ctx, OICA_E_UNSUPPORTED, "raw_t must be OICA_F64 or OICA_F32");
+  if (ld_raw < T)
+    return fail(ctx, OICA_E_SHAPE, "ld_raw (%lld) must be >= T (%lld)", (long long)ld_raw,
+                (long long)T);
   if (out_t != OICA_F32 && out_t != OICA_BF16)
     return fail(ctx, OICA_E_UNSUPPORTED, "out_t must be OICA_F32 or OICA_BF16");
   rc = ensure_ws(ctx, whiten_workspace_bytes(N, T));
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
-  HIP_TRY(ctx, launch_whiten(ctx->stream, N, T, X_raw, raw_t, Xw, out_t, Xw_f32, V, mean, eigval,
+  HIP_TRY(ctx, launch_whiten(ctx->stream, N, T, X_raw, raw_t, ld_raw, Xw, out_t, Xw_f32, V, mean, eigval,
                              ctx->ws, ctx->ws_bytes, ctx->small_dev));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small_dev, sizeof(int), hipMemcpyDeviceToHost,
                               ctx->stream));
@@ -195,7 +199,11 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
     if (!q.X_raw || !q.Xw) return fail(ctx, OICA_E_ARG, "problem %d: X_raw and Xw must be non-null", d);
     if (q.raw_t != OICA_F64 && q.raw_t != OICA_F32)
       return fail(ctx, OICA_E_UNSUPPORTED, "problem %d: raw_t must be OICA_F64 or OICA_F32", d);
-    jobs[d] = oica::WhitenJob{q.N, q.T, q.X_raw, q.raw_t, q.Xw, out_t, q.Xw_f32, q.V, q.mean, q.eigval};
+    if (q.ld_raw < q.T)
+      return fail(ctx, OICA_E_SHAPE, "problem %d: ld_raw (%lld) must be >= T (%lld)", d,
+                  (long long)q.ld_raw, (long long)q.T);
+    jobs[d] = oica::WhitenJob{q.N,  q.T,     q.X_raw,  q.raw_t, q.ld_raw, q.Xw,
+                              out_t, q.Xw_f32, q.V, q.mean,  q.eigval};
   }
   const size_t main_bytes = whiten_batched_workspace_bytes(D, jobs.data());
   int rc = ensure_ws(ctx, main_bytes + (size_t)D * sizeof(int) + 256);
@@ -614,7 +622,8 @@ static int pruner_grad_impl(oica_ctx *ctx, const oica_pruner *p, const float *tr
   if (rc) return rc;
   double *loss_dev = (double *)((char *)ctx->ws + ctx->ws_bytes - 256);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, launch_pruner_grad(ctx->stream, &p->st, traj, labels, R, w_pos, ctx->ws, grad, loss_dev));
+  HIP_TRY(ctx, launch_pruner_grad(ctx->stream, &p->st, traj, labels, R, RowPerm{}, 0, w_pos, ctx->ws,
+                                  grad, loss_dev));
   if (loss) {
     HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, loss_dev, sizeof(double), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -644,6 +653,64 @@ int oica_pruner_train_step(oica_ctx *ctx, oica_pruner *p, const float *traj, con
   rc = pruner_grad_impl(ctx, p, traj, labels, R, w_pos, grad, loss);
   if (rc) return rc;
   HIP_TRY(ctx, launch_pruner_adam(ctx->stream, &p->st, grad, lr));
+  return OICA_OK;
+}
+
+int oica_pruner_train(oica_ctx *ctx, oica_pruner *p, const float *traj, const uint8_t *labels,
+                      int64_t R, int epochs, int batch, float w_pos, float lr, uint64_t seed,
+                      double *epoch_loss) {
+  if (!ctx || !p) return OICA_E_ARG;
+  ctx->err.clear();
+  if (!traj || !labels || R < 1) return fail(ctx, OICA_E_ARG, "traj, labels non-null and R >= 1 required");
+  if (epochs < 1 || epochs > 100000) return fail(ctx, OICA_E_ARG, "epochs must be in [1, 100000]");
+  if (batch < 1) return fail(ctx, OICA_E_ARG, "batch must be >= 1");
+  if (!(lr > 0.f)) return fail(ctx, OICA_E_ARG, "lr must be > 0");
+  if (!(w_pos >= 0.f)) return fail(ctx, OICA_E_ARG, "w_pos must be >= 0 (0: from the labels)");
+  const int64_t bs = std::min<int64_t>(batch, R);
+  const int64_t nbat = (R + bs - 1) / bs;
+  if ((double)nbat * epochs > 1e8) return fail(ctx, OICA_E_ARG, "too many training steps");
+  // workspace: gradient partials of one step | gradient | per-step losses | counter
+  const size_t part = (pruner_grad_workspace_bytes(bs) + 255) & ~(size_t)255;
+  const size_t gbytes = ((size_t)OICA_PRUNER_PARAMS * 4 + 255) & ~(size_t)255;
+  const size_t lbytes = (size_t)nbat * epochs * sizeof(double);
+  int rc = ensure_ws(ctx, part + gbytes + lbytes + 1024);
+  if (rc) return rc;
+  char *w = (char *)ctx->ws;
+  float *grad = (float *)(w + part);
+  double *losses = (double *)(w + part + gbytes);
+  unsigned long long *npos_dev =
+      (unsigned long long *)(w + ((part + gbytes + lbytes + 255) & ~(size_t)255));
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (w_pos == 0.f) {
+    HIP_TRY(ctx, hipMemsetAsync(npos_dev, 0, sizeof(unsigned long long), ctx->stream));
+    HIP_TRY(ctx, launch_count_pos(ctx->stream, labels, R, npos_dev));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, npos_dev, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const unsigned long long npos = *(const unsigned long long *)ctx->small_host;
+    w_pos = (float)((double)(R - (int64_t)npos) / (double)std::max<unsigned long long>(npos, 1));
+    if (!(w_pos > 0.f)) return fail(ctx, OICA_E_ARG, "every label is positive: w_pos would be 0");
+  }
+  for (int ep = 0; ep < epochs; ++ep) {
+    const RowPerm perm = make_row_perm(R, seed, ep);
+    for (int64_t b = 0; b < nbat; ++b) {
+      const int64_t base = b * bs, rows = std::min<int64_t>(bs, R - base);
+      HIP_TRY(ctx, launch_pruner_grad(ctx->stream, &p->st, traj, labels, rows, perm, base, w_pos,
+                                      ctx->ws, grad, losses + (size_t)ep * nbat + b));
+      HIP_TRY(ctx, launch_pruner_adam(ctx->stream, &p->st, grad, lr));
+    }
+  }
+  if (epoch_loss) {
+    std::vector<double> lh((size_t)nbat * epochs);
+    HIP_TRY(ctx, hipMemcpyAsync(lh.data(), losses, lbytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int ep = 0; ep < epochs; ++ep) {
+      double s = 0.0;
+      for (int64_t b = 0; b < nbat; ++b)
+        s += lh[(size_t)ep * nbat + b] / (double)std::min<int64_t>(bs, R - b * bs);
+      epoch_loss[ep] = s / (double)nbat;
+    }
+  }
   return OICA_OK;
 }
 

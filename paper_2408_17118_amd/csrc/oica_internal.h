@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/oica.h"
+#include "row_perm.h"
 
 namespace oica {
 
@@ -148,6 +149,7 @@ struct WhitenJob {     // one problem of the batched whitening
   int64_t T;
   const void *X;
   oica_dtype raw_t;
+  int64_t ld;              // row stride of X in elements, >= T
   void *Xw;
   oica_dtype out_t;
   float *Xw_f32;
@@ -158,7 +160,7 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
                                  int *flags_dev);
 hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
                          int n_max);
-hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t,
+hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, int64_t ld,
                          void *Xw, oica_dtype out_t, float *Xw_f32, double *V_out,
                          double *mean_out, double *eig_out, void *ws, size_t ws_bytes,
                          int *flags_dev);
@@ -220,9 +222,13 @@ void pruner_free(PrunerState *p);
 hipError_t launch_pruner_predict(hipStream_t st, const PrunerState *p, const float *traj, long long R,
                                  const int *list, const int *count_dev, float *prob);
 size_t pruner_grad_workspace_bytes(long long R);
+// Loss and gradient over the R rows base .. base + R - 1 of the order perm.
 hipError_t launch_pruner_grad(hipStream_t st, const PrunerState *p, const float *traj,
-                              const uint8_t *labels, long long R, float w_pos, void *ws,
-                              float *grad, double *loss_dev);
+                              const uint8_t *labels, long long R, const RowPerm &perm,
+                              long long base, float w_pos, void *ws, float *grad,
+                              double *loss_dev);
+hipError_t launch_count_pos(hipStream_t st, const uint8_t *labels, long long R,
+                            unsigned long long *count_dev);
 hipError_t launch_pruner_adam(hipStream_t st, PrunerState *p, const float *grad, float lr);
 hipError_t launch_prune(hipStream_t st, const PrunerState *p, const float *traj, int traj_stride,
                         int *list, int *count_dev, int kmax, uint8_t *status, int *keep,

@@ -123,10 +123,13 @@ __global__ void k_prune_commit(int *__restrict__ list, int *count_dev, const int
 }
 
 // Loss and gradient partials of one block of GB rows (one thread per row).
+// Rows i = 0..R-1 of the step are source rows base + i, or, with perm.on,
+// row_perm(perm, base + i).
 __global__ __launch_bounds__(GB) void k_mlp_grad_block(const __half *__restrict__ w16, FeatNorm nm,
                                                        const float *__restrict__ traj,
                                                        const uint8_t *__restrict__ labels,
-                                                       long long R, float w_pos,
+                                                       long long R, RowPerm perm,
+                                                       long long base, float w_pos,
                                                        float *__restrict__ gpart,
                                                        double *__restrict__ lpart) {
   __shared__ float sw[N_PAR];
@@ -142,9 +145,10 @@ __global__ __launch_bounds__(GB) void k_mlp_grad_block(const __half *__restrict_
   float dz = 0.f;
   double lrow = 0.0;
   if (valid) {
-    load_features(traj, 16, row, nm, f);
+    const long long src = perm.on ? row_perm(perm, base + row) : base + row;
+    load_features(traj, 16, src, nm, f);
     const float z = mlp_logit(sw, f, h1);
-    const float y = labels[row] ? 1.f : 0.f;
+    const float y = labels[src] ? 1.f : 0.f;
     const float s = sigmoidf_stable(z);
     dz = ((1.f - y) * s - w_pos * y * (1.f - s)) / (float)R;
     // softplus(-z) and softplus(z), stable
@@ -327,13 +331,15 @@ size_t pruner_grad_workspace_bytes(long long R) {
 }
 
 hipError_t launch_pruner_grad(hipStream_t st, const PrunerState *p, const float *traj,
-                              const uint8_t *labels, long long R, float w_pos, void *ws,
-                              float *grad, double *loss_dev) {
+                              const uint8_t *labels, long long R, const RowPerm &perm,
+                              long long base, float w_pos, void *ws, float *grad,
+                              double *loss_dev) {
   const int nb = (int)((R + GB - 1) / GB);
   float *gpart = (float *)ws;
   double *lpart = (double *)((char *)ws + (((size_t)nb * N_PAR * sizeof(float) + 255) & ~(size_t)255));
   hipLaunchKernelGGL(k_mlp_grad_block, dim3(nb), dim3(GB), 0, st, (const __half *)p->w16,
-                     make_norm(p->mean, p->stdv), traj, labels, R, w_pos, gpart, lpart);
+                     make_norm(p->mean, p->stdv), traj, labels, R, perm, base, w_pos, gpart,
+                     lpart);
   hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((N_PAR + 255) / 256), dim3(256), 0, st, nb, gpart,
                      lpart, grad, loss_dev);
   return hipGetLastError();
@@ -356,6 +362,30 @@ hipError_t launch_prune(hipStream_t st, const PrunerState *p, const float *traj,
                      status, keep, keep_count, pruned_count);
   hipLaunchKernelGGL(k_prune_commit, dim3((kmax + 255) / 256 < 1024 ? (kmax + 255) / 256 : 1024),
                      dim3(256), 0, st, list, count_dev, keep, keep_count);
+  return hipGetLastError();
+}
+
+
+// Number of non-zero labels (one 64-bit counter, zeroed by the caller).
+__global__ __launch_bounds__(256) void k_count_pos(const uint8_t *__restrict__ labels, long long R,
+                                                   unsigned long long *__restrict__ count) {
+  __shared__ unsigned int part[4];
+  unsigned int c = 0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < R;
+       i += (long long)gridDim.x * 256)
+    c += labels[i] != 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+  if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(count, (unsigned long long)(part[0] + part[1] + part[2] + part[3]));
+}
+
+hipError_t launch_count_pos(hipStream_t st, const uint8_t *labels, long long R,
+                            unsigned long long *count_dev) {
+  const long long want = (R + 255) / 256;
+  const int grid = (int)(want < 1024 ? want : 1024);
+  hipLaunchKernelGGL(k_count_pos, dim3(grid), dim3(256), 0, st, labels, R, count_dev);
   return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct WJob {
   int f64;              // raw data FP64 (else FP32)
   int N;
   long long T;
+  long long ld;         // row stride of X in elements
   int ch, cch;          // sample chunks of the mean and covariance passes
   double *mpart, *cpart;
   double *mean, *C, *E, *Wh, *eig;
@@ -90,7 +91,7 @@ __device__ void mean_part_body(const WJob &j, int c) {
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
     bool bad = false;
-    const TIN *row = X + (size_t)n * (size_t)T;
+    const TIN *row = X + (size_t)n * (size_t)j.ld;
     for (long long m = t0 + lane; m < t1; m += 64) {
       const double v = ld(row, (size_t)m);
       bad |= !isfinite(v);
@@ -155,7 +156,7 @@ __device__ void cov_part_body(const WJob &j, int c, double *xs_flat) {
       const int n = e / COV_TS, s = e % COV_TS;
       const long long m = m0 + s;
       double v = 0.0;
-      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)T + (size_t)m) - j.mean[n];
+      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)j.ld + (size_t)m) - j.mean[n];
       xs[s][n] = v;
     }
     __syncthreads();
@@ -558,7 +559,7 @@ __device__ void apply_body(const WJob &j, int tile, double (*ws)[AP_K + 1],
       const int k = e / AP_T, s = e % AP_T;
       const int jj = j0 + k;
       const long long m = m_base + s;
-      xs[k][s] = (jj < N && m < T) ? ld(X, (size_t)jj * (size_t)T + (size_t)m) - j.mean[jj] : 0.0;
+      xs[k][s] = (jj < N && m < T) ? ld(X, (size_t)jj * (size_t)j.ld + (size_t)m) - j.mean[jj] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -659,6 +660,7 @@ static WJob make_wjob(const WhitenJob &w, const WhitenBufs &b, double *mpart, do
   j.f64 = w.raw_t == OICA_F64;
   j.N = w.N;
   j.T = w.T;
+  j.ld = w.ld;
   j.ch = n_chunks(w.T);
   j.cch = n_cov_chunks(w.N, w.T);
   j.mpart = mpart;
@@ -721,11 +723,12 @@ size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
          al256((size_t)W_KINDS * 2 * (D + 1) * sizeof(int)) + 1024;
 }
 
-hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, void *Xw,
-                         oica_dtype out_t, float *Xw_f32, double *V_out, double *mean_out,
-                         double *eig_out, void *ws, size_t ws_bytes, int *flags_dev) {
+hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t,
+                         int64_t ld, void *Xw, oica_dtype out_t, float *Xw_f32, double *V_out,
+                         double *mean_out, double *eig_out, void *ws, size_t ws_bytes,
+                         int *flags_dev) {
   (void)ws_bytes;
-  const WhitenJob w{N, T, X, raw_t, Xw, out_t, Xw_f32, V_out, mean_out, eig_out};
+  const WhitenJob w{N, T, X, raw_t, ld, Xw, out_t, Xw_f32, V_out, mean_out, eig_out};
   char *scratch = (char *)ws;
   char *p = scratch + stats_scratch_bytes(N, T);
   const WhitenBufs b = carve_bufs(p, N, V_out, mean_out, eig_out);

@@ -49,7 +49,7 @@ class FpStats(C.Structure):
 
 class WhitenProblem(C.Structure):
     _fields_ = [("N", C.c_int), ("T", C.c_int64), ("X_raw", C.c_void_p), ("raw_t", C.c_int),
-                ("Xw", C.c_void_p), ("Xw_f32", C.c_void_p), ("V", C.c_void_p),
+                ("ld_raw", C.c_int64), ("Xw", C.c_void_p), ("Xw_f32", C.c_void_p), ("V", C.c_void_p),
                 ("mean", C.c_void_p), ("eigval", C.c_void_p), ("status", C.c_int)]
 
 
@@ -91,7 +91,8 @@ _SIGS = {
     "oica_status_string": (C.c_char_p, [C.c_int]),
     "oica_last_error": (C.c_char_p, [_P]),
     "oica_set_stream": (C.c_int, [_P, _P]),
-    "oica_whiten": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P, _P, _P, _P]),
+    "oica_whiten": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, C.c_int64, _P, C.c_int, _P, _P,
+                              _P, _P]),
     "oica_whiten_batched": (C.c_int, [_P, C.c_int, C.POINTER(WhitenProblem), C.c_int]),
     "oica_fixed_point": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.c_int, _P,
                                    C.POINTER(FpParams), _P, _P, _P, _P, _P, C.POINTER(FpStats)]),
@@ -109,6 +110,8 @@ _SIGS = {
                                    C.POINTER(C.c_double)]),
     "oica_pruner_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float,
                                          C.POINTER(C.c_double)]),
+    "oica_pruner_train": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int, C.c_int, C.c_float,
+                                    C.c_float, C.c_uint64, _P]),
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
                               C.c_int, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int),
                               C.POINTER(C.c_int)]),
@@ -146,13 +149,25 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _dev(t, name, dtype=None, shape=None):
+def _ld(X):
+    """Row stride in elements of a checked row-strided matrix (a single row's
+    stride is meaningless, so its length stands in)."""
+    return X.stride(0) if X.shape[0] > 1 else X.shape[1]
+
+
+def _dev(t, name, dtype=None, shape=None, row_strided=False):
     """Check a device argument before its pointer crosses the C ABI, which
     cannot see dtypes or sizes: dtype (one or a tuple) and shape (None entries
-    match any size) as the call documents."""
+    match any size) as the call documents.  row_strided: a 2-D matrix whose
+    rows are contiguous but may lie further apart than their length (the call
+    takes the row stride)."""
     if not (isinstance(t, torch.Tensor) and t.is_cuda):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if not t.is_contiguous():
+    if row_strided and t.dim() == 2:
+        if (t.shape[1] > 1 and t.stride(1) != 1) or (t.shape[0] > 1 and t.stride(0) < t.shape[1]):
+            raise ValueError(f"{name} must have contiguous rows (stride(1) == 1, "
+                             f"stride(0) >= {t.shape[1]}), not strides {tuple(t.stride())}")
+    elif not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if dtype is not None:
         ok = dtype if isinstance(dtype, tuple) else (dtype,)
@@ -202,9 +217,10 @@ class Context:
 
     # ---- a1-a3 ------------------------------------------------------------
     def whiten(self, X: torch.Tensor, out_dtype=torch.float32, want_f32=True):
-        """X: N x T raw data (float64 or float32, device).  Returns
+        """X: N x T raw data (float64 or float32, device; rows contiguous, and
+        may be a column window of a longer recording).  Returns
         (Xw, Xw_f32, V, mean, eigval); Xw_f32 is Xw itself for FP32 output."""
-        _dev(X, "X", (torch.float64, torch.float32), (None, None))
+        _dev(X, "X", (torch.float64, torch.float32), (None, None), row_strided=True)
         N, T = X.shape
         dev = self._tdev()
         Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
@@ -214,8 +230,8 @@ class Context:
         V = torch.empty((N, N), dtype=torch.float64, device=dev)
         mean = torch.empty(N, dtype=torch.float64, device=dev)
         eig = torch.empty(N, dtype=torch.float64, device=dev)
-        rc = self.lib.oica_whiten(self.h, N, T, _ptr(X), _DT[X.dtype], _ptr(Xw), _DT[out_dtype],
-                                  _ptr(Xw32), _ptr(V), _ptr(mean), _ptr(eig))
+        rc = self.lib.oica_whiten(self.h, N, T, _ptr(X), _DT[X.dtype], _ld(X), _ptr(Xw),
+                                  _DT[out_dtype], _ptr(Xw32), _ptr(V), _ptr(mean), _ptr(eig))
         self._check(rc)
         return Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig
 
@@ -229,7 +245,7 @@ class Context:
         dev = self._tdev()
         outs = []
         for d, X in enumerate(Xs):
-            _dev(X, "X", (torch.float64, torch.float32), (None, None))
+            _dev(X, "X", (torch.float64, torch.float32), (None, None), row_strided=True)
             N, T = X.shape
             Xw = torch.empty((N, T), dtype=out_dtype, device=dev)
             Xw32 = None
@@ -238,8 +254,8 @@ class Context:
             V = torch.empty((N, N), dtype=torch.float64, device=dev)
             mean = torch.empty(N, dtype=torch.float64, device=dev)
             eig = torch.empty(N, dtype=torch.float64, device=dev)
-            arr[d] = WhitenProblem(N, T, _ptr(X), _DT[X.dtype], _ptr(Xw), _ptr(Xw32), _ptr(V),
-                                   _ptr(mean), _ptr(eig), 0)
+            arr[d] = WhitenProblem(N, T, _ptr(X), _DT[X.dtype], _ld(X), _ptr(Xw), _ptr(Xw32),
+                                   _ptr(V), _ptr(mean), _ptr(eig), 0)
             outs.append((Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig))
         rc = self.lib.oica_whiten_batched(self.h, D, arr, _DT[out_dtype])
         if return_status and rc in (-3, -4):
@@ -470,6 +486,21 @@ class Pruner:
                                                             _ptr(labels), R, float(w_pos),
                                                             float(lr), C.byref(loss)))
         return loss.value
+
+    def train(self, traj, labels, epochs=4, batch=65536, lr=2e-3, seed=0, w_pos=0.0):
+        """Whole training run in the library (shuffled epochs of batch-row Adam
+        steps); w_pos 0 weighs positives by n_neg / n_pos.  Returns the mean
+        loss of each epoch."""
+        import numpy as np
+        _dev(traj, "traj", torch.float32, (None, 8, 2))
+        R = traj.shape[0]
+        _dev(labels, "labels", torch.uint8, (R,))
+        out = np.zeros(int(epochs), dtype=np.float64)
+        self.ctx._check(self.ctx.lib.oica_pruner_train(self.ctx.h, self.h, _ptr(traj), _ptr(labels),
+                                                       R, int(epochs), int(batch), float(w_pos),
+                                                       float(lr), int(seed) & (2**64 - 1),
+                                                       out.ctypes.data))
+        return [float(x) for x in out]
 
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,

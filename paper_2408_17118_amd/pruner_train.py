@@ -8,7 +8,8 @@ least that of the ``r_top``-th one, less a relative 1e-3 (components tied with
 the ``r_top``-th, such as the sinusoids, which all have kurtosis -1.5, are all
 top or all not).  Only rows still moving after pass 8 are training rows (the
 others are never pruned).  The network is trained with the library's own
-forward/backward/Adam kernels (binary cross-entropy weighted by n_neg / n_pos).
+forward/backward/Adam kernels (binary cross-entropy weighted by n_neg / n_pos),
+in shuffled epochs drawn on the device (oica_pruner_train).
 The threshold is the largest value that keeps, in every top component of every
 calibration dataset, min(``keep_min``, its size) rows, times a safety factor.
 
@@ -95,22 +96,16 @@ def collect(ctx, seeds, r_top, log=print):
 
 
 def train(ctx, traj, labels, epochs=4, batch=65536, lr=2e-3, seed=0, log=print):
+    """Shuffled epochs of Adam steps, run by the library (oica_pruner_train)."""
     th = traj.cpu().numpy()
     mean, std = feature_stats(th)
     pr = oica.Pruner(ctx, init_weights(np.random.default_rng(seed)), mean, std)
     n = traj.shape[0]
     n_pos = int(labels.sum())
-    w_pos = float((n - n_pos) / max(n_pos, 1))
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    hist = []
-    for ep in range(epochs):
-        perm = torch.randperm(n, generator=g).to(traj.device)
-        losses = []
-        for i in range(0, n, batch):
-            idx = perm[i:i + batch]
-            losses.append(pr.train_step(traj[idx].contiguous(), labels[idx].contiguous(), w_pos, lr))
-        hist.append(float(np.mean(losses)))
-        log(f"epoch {ep}: mean loss {hist[-1]:.4f}")
+    w_pos = float(np.float32((n - n_pos) / max(n_pos, 1)))
+    hist = pr.train(traj, labels, epochs=epochs, batch=batch, lr=lr, seed=seed, w_pos=w_pos)
+    for ep, l in enumerate(hist):
+        log(f"epoch {ep}: mean loss {l:.4f}")
     return pr, {"w_pos": w_pos, "rows": n, "pos": n_pos, "loss": hist}
 
 

@@ -52,7 +52,7 @@ def test_status_strings_and_version():
 
 def test_null_context_is_an_argument_error():
     lib = _lib()
-    assert lib.oica_whiten(None, 4, 100, None, 0, None, 1, None, None, None, None) == -1
+    assert lib.oica_whiten(None, 4, 100, None, 0, 100, None, 1, None, None, None, None) == -1
     assert lib.oica_fixed_point(None, 4, 100, None, 1, None, 8, None, None, None, None, None,
                                 None, None, None) == -1
     nu, na = C.c_int(), C.c_int()

@@ -8,6 +8,7 @@ Tolerances (FP32 path):
   * fixed points: |cos| >= 1 - 1e-6 against the oracle, kurtosis within
     1e-5 * max(|alpha|, 0.1).
 """
+import ctypes as C
 import math
 
 import numpy as np
@@ -183,6 +184,42 @@ def test_whiten_batched_equals_single(ctx):
     Vr = ica.whiten(host(Xs[-1]).astype(np.float64))[1]
     V = host(outs[-1][2])
     assert np.allclose(V, Vr, rtol=1e-8, atol=1e-8 * np.abs(Vr).max())
+
+
+def test_whiten_reads_a_window_in_place(ctx):
+    """X_raw with a row stride ld_raw > T (a window of a longer recording): the
+    outputs equal those of the contiguous copy bit for bit, single and batched,
+    and samples outside the window (here NaN) are never read."""
+    from paper_2408_17118_amd import oica
+    L = 12_000
+    cases = [(9, 5000, 700, np.float64), (64, 7001, 1234, np.float32), (1, 999, 3, np.float64)]
+    wins, refs = [], []
+    for i, (N, T, a, dt) in enumerate(cases):
+        rec = _mixture(N, L, 1, seed=700 + i).X.astype(dt) + 0.5
+        rec[:, :a] = np.nan
+        rec[:, a + T:] = np.nan
+        R = dev(rec)
+        W = R[:, a:a + T]
+        assert W.stride(0) == L and (N == 1 or not W.is_contiguous())
+        wins.append(W)
+        refs.append(W.contiguous())
+    for out_dtype in (torch.float32, torch.bfloat16):
+        for W, Wc in zip(wins, refs):
+            for x, y in zip(ctx.whiten(W, out_dtype=out_dtype), ctx.whiten(Wc, out_dtype=out_dtype)):
+                assert torch.equal(x, y)
+        for o, Wc in zip(ctx.whiten_batched(wins, out_dtype=out_dtype), refs):
+            for x, y in zip(o, ctx.whiten(Wc, out_dtype=out_dtype)):
+                assert torch.equal(x, y)
+    Vr = ica.whiten(host(refs[0]))[1]
+    assert np.allclose(host(ctx.whiten(wins[0])[2]), Vr, rtol=1e-8, atol=1e-8 * np.abs(Vr).max())
+    # a stride shorter than a row is refused on the host; so is a column-strided view
+    lib, N, T = ctx.lib, 9, 5000
+    Xw = torch.empty((N, T), dtype=torch.float32, device="cuda")
+    rc = lib.oica_whiten(ctx.h, N, T, C.c_void_p(refs[0].data_ptr()), oica.OICA_F64, T - 1,
+                         C.c_void_p(Xw.data_ptr()), oica.OICA_F32, None, None, None, None)
+    assert rc == -2
+    with pytest.raises(ValueError):
+        ctx.whiten(dev(np.ones((T, N))).t())
 
 
 def test_whiten_batched_status(ctx):

@@ -103,6 +103,54 @@ def test_training_reduces_loss(ctx):
     assert acc > 0.85
 
 
+def test_train_run_one_batch_equals_train_step(ctx):
+    """A one-epoch run with one batch of all rows is one Adam step on the whole
+    set, whatever the order: the loss (FP64 row sums) agrees to rounding, a
+    dropped or repeated row would move it by about 1/R, and the weights agree
+    except where a gradient component is at rounding level."""
+    from paper_2408_17118_amd import oica
+    pa, t, y, w0, mean, std = _make(ctx, seed=6)
+    pb = oica.Pruner(ctx, w0, mean, std)
+    T, Y = torch.from_numpy(t).cuda(), torch.from_numpy(y).cuda()
+    R = t.shape[0]
+    w_pos = float((y == 0).sum() / max((y == 1).sum(), 1))
+    la = pa.train(T, Y, epochs=1, batch=R, lr=1e-3, seed=11, w_pos=w_pos)
+    lb = pb.train_step(T, Y, w_pos, lr=1e-3)
+    assert len(la) == 1 and abs(la[0] - lb) <= 1e-12 * abs(lb), (la, lb)
+    d = np.abs(pa.weights().astype(np.float64) - pb.weights())
+    assert np.mean(d <= 1e-6) >= 0.99 and d.max() <= 2.5e-3
+
+
+def test_train_run_weights_and_order(ctx):
+    """w_pos 0 is n_neg / n_pos of the labels; a seed fixes the weights; another
+    seed (several steps per epoch) gives other weights; many epochs of small
+    steps fit the training rows."""
+    from paper_2408_17118_amd import oica
+    _, t, y, w0, mean, std = _make(ctx, seed=7)
+    T, Y = torch.from_numpy(t).cuda(), torch.from_numpy(y).cuda()
+    w_pos = float(np.float32((y == 0).sum() / max((y == 1).sum(), 1)))
+
+    def run(seed, wp, epochs=2):
+        pr = oica.Pruner(ctx, w0, mean, std)
+        return pr, pr.train(T, Y, epochs=epochs, batch=700, lr=3e-3, seed=seed, w_pos=wp)
+
+    a, la = run(5, 0.0)
+    b, lb = run(5, w_pos)
+    c, _ = run(6, 0.0)
+    assert np.array_equal(a.weights(), b.weights()) and la == lb
+    assert not np.array_equal(a.weights(), c.weights())
+    d, ld = run(5, 0.0, epochs=60)
+    assert ld[:2] == la and ld[-1] < 0.6 * ld[0], ld
+    acc = ((d.predict(T).cpu().numpy() > 0.5) == (y == 1)).mean()
+    assert acc > 0.85
+    with pytest.raises(oica.OicaError):
+        d.train(T, Y, epochs=0)
+    with pytest.raises(oica.OicaError):
+        d.train(T, Y, batch=0)
+    with pytest.raises(oica.OicaError):
+        d.train(T, torch.ones_like(Y))          # every label positive and w_pos 0
+
+
 def test_pruning_paths(ctx):
     from paper_2408_17118_amd import oica
     prob = synth.make_problem(synth.eeg_kinds(16), T=20_000, K=2048, seed=4)
