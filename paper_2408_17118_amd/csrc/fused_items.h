@@ -546,17 +546,51 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       for (int sub = 0; sub < BT / 32; ++sub) {
         if (m_tile + sub * 32 >= t_end) break;
         const int m0 = sub * 32;
+        // Operand reads run three steps ahead of the MFMAs that use them (three
+        // register buffers per GEMM, the second GEMM's first reads issued
+        // before the cube), so each wait on LDS overlaps two steps of MFMA
+        // work.  Scheduling fences keep that order: without them the scheduler
+        // moves each read next to its use and every step waits on LDS.
+        constexpr int S1 = NP / 16;      // GEMM1 steps (K = 16 features each)
+        constexpr int S2 = NP / 16;      // GEMM2 steps (32 features x 16 samples each)
+        constexpr int AH = 4;            // reads in flight
+        auto ga = [&](int s) {
+          return *reinterpret_cast<const bf16x8 *>(&xt[(m0 + li) * XTS + 16 * s + 8 * h]);
+        };
+        constexpr int NB = NP / 32;      // GEMM2 accumulators; step j: block j % NB, half j / NB
+        auto gb = [&](int j) {
+          const int nb = j % NB, q = j / NB;
+          const __bf16 *src = &xs[(nb * 32 + li) * BSX + m0 + 16 * q + 4 * h];
+          const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(src);
+          const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(src + 8);
+          bf16x8 a;
+          a[0] = lo[0]; a[1] = lo[1]; a[2] = lo[2]; a[3] = lo[3];
+          a[4] = hi[0]; a[5] = hi[1]; a[6] = hi[2]; a[7] = hi[3];
+          return a;
+        };
         f32x16 zacc[WK];
 #pragma unroll
         for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
+        bf16x8 abuf[AH];
+        // buffer s holds GEMM1 operand s, or for s >= S1 GEMM2 operand s - S1
 #pragma unroll
-        for (int s = 0; s < NP / 16; ++s) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&xt[(m0 + li) * XTS + 16 * s + 8 * h]);
+        for (int s = 0; s < AH; ++s) {
+          if (s < S1) abuf[s] = ga(s);
+          else if (s - S1 < S2) abuf[s] = gb(s - S1);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < S1; ++s) {
+          const bf16x8 a = abuf[s % AH];
 #pragma unroll
           for (int w = 0; w < WK; ++w) {
             zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, breg[w][s], zacc[w], 0, 0, 0);
             zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[w][s], zacc[w], 0, 0, 0);
           }
+          __builtin_amdgcn_sched_barrier(0);
+          if (s + AH < S1) abuf[s % AH] = ga(s + AH);
+          else if (s + AH - S1 < S2) abuf[s % AH] = gb(s + AH - S1);
+          __builtin_amdgcn_sched_barrier(0);
         }
         bf16x8 p3[WK][2];
 #pragma unroll
@@ -569,20 +603,18 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
             s4acc[w] = fmaf(z2, z2, s4acc[w]);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
+        // GEMM2 operand j sits in abuf[(S1 + j) % AH]
 #pragma unroll
-        for (int nb = 0; nb < NP / 32; ++nb) {
+        for (int j = 0; j < S2; ++j) {
+          const bf16x8 a = abuf[(S1 + j) % AH];
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const __bf16 *src = &xs[(nb * 32 + li) * BSX + m0 + 16 * q + 4 * h];
-            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(src);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(src + 8);
-            bf16x8 a;
-            a[0] = lo[0]; a[1] = lo[1]; a[2] = lo[2]; a[3] = lo[3];
-            a[4] = hi[0]; a[5] = hi[1]; a[6] = hi[2]; a[7] = hi[3];
-#pragma unroll
-            for (int w = 0; w < WK; ++w)
-              gacc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, p3[w][q], gacc[w][nb], 0, 0, 0);
-          }
+          for (int w = 0; w < WK; ++w)
+            gacc[w][j % NB] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, p3[w][j / NB], gacc[w][j % NB], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if (j + AH < S2) abuf[(S1 + j) % AH] = gb(j + AH);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       if (m_tile + BT < t_end) stage(cur ^ 1);
