@@ -279,12 +279,14 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       }
       HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass], ctx->stream));
     }
+    // the z^4 sums only feed the trajectory; BF16 passes past it skip them
+    float *s4p = (bf16 && pass >= traj_iters) ? nullptr : s4part;
     HIP_TRY(ctx, launch_fused_update(ctx->stream, pp, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
-                                     gpart, s4part, ctl, pass));
+                                     gpart, s4p, ctl, pass));
     if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
     *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, pp, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
-                                 s4part, red, tol, iters, status, traj, traj_iters));
+                                 s4p, red, tol, iters, status, traj, traj_iters));
     if (pruner && pass + 1 == prune_pass) {
       // the list of pass prune_pass is nxt, its count kact[prune_pass & 1]
       HIP_TRY(ctx, hipMemsetAsync(prune_counts, 0, sizeof(int), ctx->stream));

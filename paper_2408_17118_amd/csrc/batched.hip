@@ -121,7 +121,7 @@ __device__ __noinline__ void call_f32(const ItemCtx &c, int kb, int sp, float *x
 }
 template <int NP, int WK>
 __device__ __noinline__ void call_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs, __bf16 *xt) {
-  item_bf16<NP, WK>(c, kb, sp, xs, xt);
+  item_bf16<NP, WK, false>(c, kb, sp, xs, xt);   // no trajectories in the batched form
 }
 
 template <int NP>

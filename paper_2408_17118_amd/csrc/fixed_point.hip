@@ -220,7 +220,10 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
-    item_bf16<NP, WK>(c, w_item % n_kb, w_item / n_kb, xs, xt);
+    if (s4part)
+      item_bf16<NP, WK, true>(c, w_item % n_kb, w_item / n_kb, xs, xt);
+    else
+      item_bf16<NP, WK, false>(c, w_item % n_kb, w_item / n_kb, xs, xt);
   }
 }
 
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(256) void k_split_reduce(FusedPlan plan, const FpCo
       v[u] = 0.f;
       if (sp < n_sp)
         v[u] = n < NP ? gpart[((size_t)sp * rows_pad + posn) * NP + n]
-                      : s4part[(size_t)sp * rows_pad + posn];
+                      : (s4part ? s4part[(size_t)sp * rows_pad + posn] : 0.f);
     }
     double acc = 0.0;
 #pragma unroll

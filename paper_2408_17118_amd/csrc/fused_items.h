@@ -417,7 +417,10 @@ template <int NP> struct BfTile {
   static constexpr int xt_elems = BT * BfStride<NP>::v;
 };
 
-template <int NP, int WK>
+// S4: also form the per-row sums of z^4 (the kurtosis of the rows before the
+// update, recorded only in the passes whose trajectory is kept); without it
+// the sums are skipped and a non-null s4part receives zeros.
+template <int NP, int WK, bool S4 = true>
 __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs_base,
                                           __bf16 *xt_base) {
   constexpr int KWG = WAVES * WK * 32;
@@ -600,7 +603,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
             const float z = zacc[w][v];
             const float z2 = z * z;
             p3[w][v / 8][v % 8] = (__bf16)(z2 * z);
-            s4acc[w] = fmaf(z2, z2, s4acc[w]);
+            if constexpr (S4) s4acc[w] = fmaf(z2, z2, s4acc[w]);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -626,7 +629,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
     for (int w = 0; w < WK; ++w) {
       const float tot = s4acc[w] + __shfl_xor(s4acc[w], 32);
       if (pos[w] < kact) {
-        if (h == 0) s4part[(size_t)sp * rows_pad + pos[w]] = tot;
+        if (h == 0 && s4part) s4part[(size_t)sp * rows_pad + pos[w]] = S4 ? tot : 0.f;
         g_f32 *dst = gpart + ((size_t)sp * rows_pad + pos[w]) * NP;
 #pragma unroll
         for (int nb = 0; nb < NP / 32; ++nb) {
