@@ -9,7 +9,7 @@
 //                                                        from the logged rotations)
 //   k_canon                      descending order, sign rule, rank check,
 //                                Wh = D^(-1/2) E^T
-//   k_apply                      Xw = Wh (X - mu)       (FP64 tiles; FP32 / BF16 out)
+//   k_apply<BIG>                 Xw = Wh (X - mu)       (FP64 MFMA; FP32 / BF16 out)
 // Every pass is HBM-bound except the Jacobi solve, which is O(N^3) on N <= 128.
 // Every kernel takes a table of problems, so many datasets share each launch
 // (a single problem is passed by value); a problem's arithmetic does not
@@ -68,7 +68,7 @@ struct WJob {
 
 // Launch-wide ranges: problem d owns work-groups (or waves) [start[d],
 // start[d + 1]) of a launch.  start == nullptr: one problem, passed by value.
-enum { W_MEAN = 0, W_MEANF, W_COV4, W_COV8, W_COVF, W_APPLY, W_KINDS };
+enum { W_MEAN = 0, W_MEANF, W_COV4, W_COV8, W_COVF, W_APPLY4, W_APPLY8, W_KINDS };
 
 __device__ inline int job_of(const int *start, int D, int b) {
   int lo = 0, hi = D - 1;
@@ -525,82 +525,175 @@ __device__ inline uint16_t bf16_rne(double x) {
   return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)mant);
 }
 
-// Xw = Wh (X - mu): 64 x 64 output tiles, 4 x 4 outputs per thread, FP64.
-// A problem's tiles are numbered sample tile fastest.
-constexpr int AP_T = 64;
-constexpr int AP_K = 16;
+// Xw = Wh (X - mu) on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r holds
+// D[l / 16 + 4 r][l % 16]).  A work-group takes apply_cols(N) consecutive
+// samples of one problem (1024 for N > 64, where loading Wh into LDS costs
+// the most; 256 below, so that short problems still spread over the CUs).  Wh, zero-padded to 16 * NRB rows and columns, sits in LDS
+// with a row stride of 2 mod 32 doubles, so the 16 rows x 2 columns that one
+// A-operand read touches per half-wave fall in distinct banks.  Each wave
+// takes 16-sample column blocks in turn; its B operands (4 features x 16
+// samples of X per step, less the means) come straight from global memory
+// into registers, the next block's loads issued before the current block's
+// MFMAs, so the reduction over features needs no barrier.  A problem's work
+// items are numbered in sample order.
+constexpr int AP_MAX_RB = NMAX / 16;
+__host__ __device__ constexpr int apply_cols(int N) { return N > 64 ? 1024 : 256; }
 static inline int apply_tiles(int N, long long T) {
-  return (int)((T + AP_T - 1) / AP_T) * ((N + AP_T - 1) / AP_T);
+  return (int)((T + apply_cols(N) - 1) / apply_cols(N));
 }
-template <typename TIN>
-__device__ void apply_body(const WJob &j, int tile, double (*ws)[AP_K + 1],
-                           double (*xs)[AP_T + 1]) {
-  const TIN *X = (const TIN *)j.X;
+__host__ __device__ constexpr int wh_ld(int nrb) {
+  return nrb * 16 + ((2 - (nrb * 16) % 32) + 32) % 32;
+}
+static size_t apply_lds_bytes(int N) {
+  const int nrb = (N + 15) / 16;
+  return ((size_t)wh_ld(nrb) * nrb * 16 + (size_t)nrb * 16) * sizeof(double);
+}
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int NRB, typename TIN>
+__device__ __forceinline__ void apply_body(const WJob &j, int item, double *lds) {
+  typedef __attribute__((address_space(1))) const TIN gin;
+  typedef __attribute__((address_space(1))) float gf32;
+  typedef __attribute__((address_space(1))) uint16_t gu16;
+  constexpr int NP = NRB * 16;
+  constexpr int NK = NRB * 4;          // steps of 4 features
+  constexpr int LD = wh_ld(NRB);
+  double *whs = lds;                   // NP x LD
+  double *mus = lds + NP * LD;         // NP means (0 past N)
+  gin *X = (gin *)j.X;
+  gf32 *o32 = (gf32 *)j.o32, *o32b = (gf32 *)j.o32b;
+  gu16 *obf = (gu16 *)j.obf;
   const int N = j.N;
   const long long T = j.T;
-  const int tx = (int)((T + AP_T - 1) / AP_T);
-  const long long m_base = (long long)(tile % tx) * AP_T;
-  const int i_base = (tile / tx) * AP_T;
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int j0 = 0; j0 < N; j0 += AP_K) {
-    __syncthreads();
-    for (int e = tid; e < AP_T * AP_K; e += 256) {
-      const int r = e / AP_K, k = e % AP_K;
-      const int i = i_base + r, jj = j0 + k;
-      ws[r][k] = (i < N && jj < N) ? j.Wh[i * N + jj] : 0.0;
-    }
-    for (int e = tid; e < AP_K * AP_T; e += 256) {
-      const int k = e / AP_T, s = e % AP_T;
-      const int jj = j0 + k;
-      const long long m = m_base + s;
-      xs[k][s] = (jj < N && m < T) ? ld(X, (size_t)jj * (size_t)j.ld + (size_t)m) - j.mean[jj] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < AP_K; ++k) {
-      double wv[4], xv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) wv[a] = ws[tr + 16 * a][k];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) xv[b] = xs[k][tc + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(wv[a], xv[b], acc[a][b]);
-    }
+  const long long ldx = j.ld;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int li = lane % 16, lk = lane / 16;
+  for (int e = tid; e < NP * NP; e += 256) {
+    const int r = e / NP, c = e % NP;
+    whs[r * LD + c] = (r < N && c < N) ? j.Wh[r * N + c] : 0.0;
   }
+  for (int e = tid; e < NP; e += 256) mus[e] = e < N ? j.mean[e] : 0.0;
+  __syncthreads();
+  constexpr int COLS = apply_cols(NP);
+  const long long m_item = (long long)item * COLS;
+  long long m_end = m_item + COLS;
+  if (m_end > T) m_end = T;
+  // raw X of feature step s at sample m (already clamped into the problem's
+  // range).  Indices are clamped into the data instead of masked: a feature
+  // past N meets a zero column of Wh (the data are finite, or the call has
+  // already failed on them), a sample past the end is never stored, and the
+  // loads for the block after the last one are simply not used.  kl is an
+  // opaque copy of this lane's feature offset, taken per block, so that the
+  // per-step row offsets are recomputed rather than all kept live.
+  auto load = [&](long long m, int s, int kl) -> double {
+    int f = 4 * s + kl;
+    if (f > N - 1) f = N - 1;
+    return (double)X[(size_t)f * (size_t)ldx + (size_t)m];
+  };
+  auto clampm = [&](long long m) { return m < m_end ? m : m_end - 1; };
+  // nxt[s] holds step s of the wave's current column block; it is replaced by
+  // the same step of the next block as soon as it is used, so every load has
+  // a whole block of MFMA work to arrive
+  double nxt[NK];
+  long long m0 = m_item + 16 * wave;
+  if (m0 < m_end) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i_base + tr + 16 * a;
-    if (i >= N) continue;
+    for (int s = 0; s < NK; ++s) nxt[s] = load(clampm(m0 + li), s, lk);
+  }
+  for (; m0 < m_end; m0 += 64) {
+    int kl = lk;
+    asm volatile("" : "+v"(kl));
+    const long long mn = clampm(m0 + 64 + li);
+    f64x4 acc[NRB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long long m = m_base + tc + 16 * b;
-      if (m >= T) continue;
-      const size_t o = (size_t)i * (size_t)T + (size_t)m;
-      if (j.o32) j.o32[o] = (float)acc[a][b];
-      if (j.obf) j.obf[o] = bf16_rne(acc[a][b]);
-      if (j.o32b) j.o32b[o] = (float)acc[a][b];
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // A operands (Wh) one feature step ahead; fences keep the scheduler from
+    // hoisting every step's LDS reads at once, and an opaque zero offset keeps
+    // the compiler from lifting all of them (NRB x NK registers) out of the
+    // sample loop as loop-invariant
+    int wofs = 0;
+    asm volatile("" : "+v"(wofs));
+    const double *wl = whs + wofs;
+    double a[2][NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) a[0][rb] = wl[(rb * 16 + li) * LD + lk];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      if (s + 1 < NK) {
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+          a[(s + 1) % 2][rb] = wl[(rb * 16 + li) * LD + 4 * (s + 1) + lk];
+      }
+      const double b = nxt[s] - mus[4 * s + lk];
+      nxt[s] = load(mn, s, kl);
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s % 2][rb], b, acc[rb], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const long long m = m0 + li;
+    if (m < m_end) {
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rb * 16 + lk + 4 * r;
+          if (i >= N) continue;
+          const size_t o = (size_t)i * (size_t)T + (size_t)m;
+          const double v = acc[rb][r];
+          if (o32) o32[o] = (float)v;
+          if (obf) obf[o] = bf16_rne(v);
+          if (o32b) o32b[o] = (float)v;
+        }
+      }
     }
   }
 }
 
+// BIG: the kernel for N > 64 (5 to 8 row blocks); the other takes N <= 64,
+// so each has the register budget of its own row-block counts.
+template <bool BIG, typename TIN>
+__device__ __forceinline__ void apply_dispatch(const WJob &j, int item, double *lds) {
+  const int nrb = (j.N + 15) / 16;
+  if constexpr (BIG) {
+    switch (nrb) {
+      case 5: apply_body<5, TIN>(j, item, lds); break;
+      case 6: apply_body<6, TIN>(j, item, lds); break;
+      case 7: apply_body<7, TIN>(j, item, lds); break;
+      default: apply_body<8, TIN>(j, item, lds); break;
+    }
+  } else {
+    switch (nrb) {
+      case 1: apply_body<1, TIN>(j, item, lds); break;
+      case 2: apply_body<2, TIN>(j, item, lds); break;
+      case 3: apply_body<3, TIN>(j, item, lds); break;
+      default: apply_body<4, TIN>(j, item, lds); break;
+    }
+  }
+}
+
+template <bool BIG>
 __global__ __launch_bounds__(256) void k_apply(const WJob *__restrict__ jobs, WJob one,
                                                const int *__restrict__ start, int D) {
-  __shared__ double ws[AP_T][AP_K + 1];
-  __shared__ double xs[AP_K][AP_T + 1];
+  extern __shared__ double ap_lds[];
   int t = blockIdx.x;
   const int d = start ? job_of(start, D, t) : 0;
   if (start) t -= start[d];
   const WJob j = start ? jobs[d] : one;
-  if (j.f64) apply_body<double>(j, t, ws, xs);
-  else apply_body<float>(j, t, ws, xs);
+  if (j.f64) apply_dispatch<BIG, double>(j, t, ap_lds);
+  else apply_dispatch<BIG, float>(j, t, ap_lds);
+}
+static_assert(AP_MAX_RB == 8, "apply dispatch covers N up to 128");
+
+// Dynamic LDS of k_apply<BIG> for problems up to n_max features.
+template <bool BIG>
+static size_t apply_prepare(int n_max) {
+  const size_t lds = apply_lds_bytes(n_max);
+  (void)hipFuncSetAttribute((const void *)k_apply<BIG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  (void)hipGetLastError();
+  return lds;
 }
 
 // Per-problem buffers that live from the statistics to the apply phase.
@@ -686,7 +779,8 @@ static void job_starts(const WJob *jj, int D, int *st) {
   for (int d = 0; d < D; ++d) {
     const WJob &j = jj[d];
     const int cnt[W_KINDS] = {j.ch, j.N, j.N <= 64 ? j.cch : 0, j.N <= 64 ? 0 : j.cch, j.N * j.N,
-                              apply_tiles(j.N, j.T)};
+                              j.N <= 64 ? apply_tiles(j.N, j.T) : 0,
+                              j.N <= 64 ? 0 : apply_tiles(j.N, j.T)};
     for (int k = 0; k < W_KINDS; ++k) st[k * (D + 1) + d + 1] = st[k * (D + 1) + d] + cnt[k];
   }
 }
@@ -746,7 +840,12 @@ hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_d
   hipError_t e = launch_jacobi(st, 1, nullptr, job, N);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, nullptr, j);
-  hipLaunchKernelGGL(k_apply, dim3(apply_tiles(N, T)), dim3(256), 0, st, nullptr, j, nullptr, 1);
+  if (N <= 64)
+    hipLaunchKernelGGL(k_apply<false>, dim3(apply_tiles(N, T)), dim3(256), apply_prepare<false>(N),
+                       st, nullptr, j, nullptr, 1);
+  else
+    hipLaunchKernelGGL(k_apply<true>, dim3(apply_tiles(N, T)), dim3(256), apply_prepare<true>(N), st,
+                       nullptr, j, nullptr, 1);
   return hipGetLastError();
 }
 
@@ -838,8 +937,13 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
   e = launch_jacobi(st, D, jac_dev, jj[0], n_max);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_canon, dim3(D), dim3(NMAX), 0, st, wj_dev, wj[0]);
-  hipLaunchKernelGGL(k_apply, dim3(starts[W_APPLY * (D + 1) + D]), dim3(256), 0, st, wj_dev, wj[0],
-                     starts_dev + W_APPLY * (D + 1), D);
+  const int n_ap4 = starts[W_APPLY4 * (D + 1) + D], n_ap8 = starts[W_APPLY8 * (D + 1) + D];
+  if (n_ap4 > 0)
+    hipLaunchKernelGGL(k_apply<false>, dim3(n_ap4), dim3(256), apply_prepare<false>(std::min(n_max, 64)),
+                       st, wj_dev, wj[0], starts_dev + W_APPLY4 * (D + 1), D);
+  if (n_ap8 > 0)
+    hipLaunchKernelGGL(k_apply<true>, dim3(n_ap8), dim3(256), apply_prepare<true>(n_max), st, wj_dev,
+                       wj[0], starts_dev + W_APPLY8 * (D + 1), D);
   return hipGetLastError();
 }
 
