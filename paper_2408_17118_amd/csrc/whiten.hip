@@ -10,7 +10,8 @@
 //   k_canon                      descending order, sign rule, rank check,
 //                                Wh = D^(-1/2) E^T
 //   k_apply<BIG>                 Xw = Wh (X - mu)       (FP64 MFMA; FP32 / BF16 out)
-// Every pass is HBM-bound except the Jacobi solve, which is O(N^3) on N <= 128.
+// The mean is HBM-bound; the covariance and apply passes are FP64 contractions over
+// the samples (N^2 T multiply-adds each); the Jacobi solve is O(N^3) on N <= 128.
 // Every kernel takes a table of problems, so many datasets share each launch
 // (a single problem is passed by value); a problem's arithmetic does not
 // depend on the others.
@@ -253,6 +254,14 @@ size_t jacobi_log_entries(int N) {
 
 __device__ inline int jac_sym(int i, int j, int LD) { return i <= j ? i * LD + j : j * LD + i; }
 
+// Row stride of A in LDS: the smallest LD >= N + 1 with LD = 2 (mod 4).  In a
+// round, neighbouring lanes' elements often differ by one row and one column
+// in opposite directions (LD - 1 doubles) or the same one (LD + 1); both are
+// odd, so those lanes fall in distinct banks, and a pure row step (LD) costs
+// at most a 2-way conflict.  (With LD = N + 1 = 129, LD - 1 = 128 doubles put
+// whole half-waves on one bank.)  Non-decreasing in N.
+__host__ __device__ constexpr int jac_ld(int N) { return N + 1 + ((2 - (N + 1) % 4) + 4) % 4; }
+
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__restrict__ jobs,
                                                                JacJob one) {
   extern __shared__ double jac_smem[];
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
   __shared__ double dscale;
   const JacJob jb = jobs ? jobs[blockIdx.x] : one;
   const int N = jb.N;
-  const int LD = N + 1;
+  const int LD = jac_ld(N);
   double *a = jac_smem;
   const int tid = threadIdx.x;
   const double thr = JAC_EPS * (double)N;
@@ -441,7 +450,7 @@ __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__r
   }
 }
 
-static size_t jacobi_lds_bytes(int N) { return (size_t)N * (N + 1) * sizeof(double); }
+static size_t jacobi_lds_bytes(int N) { return (size_t)N * jac_ld(N) * sizeof(double); }
 
 hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
                          int n_max) {
