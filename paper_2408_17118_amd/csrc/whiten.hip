@@ -3,7 +3,7 @@
 // identity sample covariance, the covariance normalised by the sample count).
 //
 //   k_mean_part / k_mean_final   mu = X 1 / T          (two-level, fixed order)
-//   k_cov_part  / k_cov_final    C = Xc Xc^T / T       (split over T, fixed order)
+//   k_cov_part  / k_cov_final    C = Xc Xc^T / T       (FP64 MFMA, split over T, fixed order)
 //   k_jacobi_values / _vectors   C = E D E^T            (cyclic Jacobi: eigenvalues in one
 //                                                        work-group with A in LDS, then E
 //                                                        from the logged rotations)
@@ -131,71 +131,244 @@ __global__ void k_mean_final(const WJob *__restrict__ jobs, WJob one, const int 
   if (lane == 0) j.mean[n] = s / (double)j.T;
 }
 
-// Partial centred second moments over a chunk.  256 threads = 16 x 16, each
-// owning an RB x RB block of the (padded 16 RB)^2 matrix (RB = 4 for N <= 64,
-// 8 for N <= 128); blocks below the diagonal are skipped (the final pass reads
-// the upper triangle only).
-template <typename TIN, int RB>
-__device__ void cov_part_body(const WJob &j, int c, double *xs_flat) {
-  constexpr int NP = 16 * RB;
-  double(*xs)[NP + 2] = reinterpret_cast<double(*)[NP + 2]>(xs_flat);
-  const TIN *X = (const TIN *)j.X;
+// Partial centred second moments over a chunk, on FP64 MFMA
+// (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// result register r holds D[l / 16 + 4 r][l % 16]).  At one step the operand
+// of row block b is the same register on the A and the B side (lane l: row
+// 16 b + l % 16 of X - mean at sample s + l / 16), so block (bi, bj) of the
+// chunk's X_c X_c^T accumulates mfma(v[bi], v[bj]); only blocks bi <= bj are
+// formed (the final pass reads the upper triangle).  Wave w takes the 16-sample
+// groups w, w + 4, ... of the chunk (step k of a group: samples g + 4 k + l / 16),
+// its loads issued one group ahead, and the four waves' sums are added in
+// LDS in wave order, so a chunk still yields one partial, in a fixed order.
+// Rows past N are read as row N - 1: they only reach entries that are not
+// stored.  Samples past the chunk are zero.
+typedef double cov_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int WAVES_WH = 4;  // waves of a 256-thread work-group
+constexpr int COV_MAX_PAIRS = (NMAX / 16) * (NMAX / 16 + 1) / 2;
+static size_t cov_lds_bytes(int N) {  // the sample-split form's exchange (N <= 64)
+  const int nrb = (N + 15) / 16;
+  return nrb > 4 ? 0 : (size_t)(nrb * (nrb + 1) / 2) * 4 * 64 * sizeof(double);
+}
+template <int NRB, typename TIN>
+__device__ __forceinline__ void cov_part_body(const WJob &j, int c, double *lds) {
+  typedef __attribute__((address_space(1))) const TIN gin;
+  constexpr int NPAIR = NRB * (NRB + 1) / 2;
   const int N = j.N;
   const long long T = j.T;
   const long long t0 = (long long)c * T / j.cch, t1 = (long long)(c + 1) * T / j.cch;
-  const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;
-  const bool active = (RB * ti < N) && (RB * tj < N) && ti <= tj;
-  double acc[RB][RB];
+  gin *X = (gin *)j.X;
+  const long long ldx = j.ld;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int rr = lane % 16, q = lane / 16;
+  double mu[NRB];
+  int row[NRB];
 #pragma unroll
-  for (int a = 0; a < RB; ++a)
+  for (int b = 0; b < NRB; ++b) {
+    row[b] = b * 16 + rr < N ? b * 16 + rr : N - 1;
+    mu[b] = j.mean[row[b]];
+  }
+  auto load = [&](long long m, int b) -> double {
+    return (double)X[(size_t)row[b] * (size_t)ldx + (size_t)(m < t1 ? m : t1 - 1)];
+  };
+  cov_f64x4 acc[NPAIR];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) acc[a][b] = 0.0;
-  for (long long m0 = t0; m0 < t1; m0 += COV_TS) {
-    __syncthreads();
-    for (int e = tid; e < COV_TS * NP; e += 256) {
-      const int n = e / COV_TS, s = e % COV_TS;
-      const long long m = m0 + s;
-      double v = 0.0;
-      if (n < N && m < t1) v = ld(X, (size_t)n * (size_t)j.ld + (size_t)m) - j.mean[n];
-      xs[s][n] = v;
-    }
-    __syncthreads();
-    if (active) {
-      for (int s = 0; s < COV_TS; ++s) {
-        double a[RB], b[RB];
+  for (int p = 0; p < NPAIR; ++p) acc[p] = cov_f64x4{0.0, 0.0, 0.0, 0.0};
+  // nxt[b][k]: step k of the wave's current group, replaced by the same step
+  // of its next group as soon as it is used
+  double nxt[NRB][4];
+  long long g = t0 + 16 * wave;
+  if (g < t1) {
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-          a[q] = xs[s][RB * ti + q];
-          b[q] = xs[s][RB * tj + q];
-        }
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int p = 0; p < RB; ++p)
+      for (int b = 0; b < NRB; ++b) nxt[b][k] = load(g + 4 * k + q, b);
+  }
+  for (; g < t1; g += 64) {
 #pragma unroll
-          for (int q = 0; q < RB; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+    for (int k = 0; k < 4; ++k) {
+      const long long m = g + 4 * k + q;
+      double v[NRB];
+#pragma unroll
+      for (int b = 0; b < NRB; ++b) {
+        v[b] = m < t1 ? nxt[b][k] - mu[b] : 0.0;
+        nxt[b][k] = load(m + 64, b);
       }
+      int p = 0;
+#pragma unroll
+      for (int bi = 0; bi < NRB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NRB; ++bj, ++p)
+          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[p], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (active) {
-    for (int p = 0; p < RB; ++p)
-      for (int q = 0; q < RB; ++q) {
-        const int i = RB * ti + p, jj = RB * tj + q;
-        if (i < N && jj < N) j.cpart[((size_t)c * N + i) * N + jj] = acc[p][q];
-      }
+  // waves 1..3 hand their sums to wave 0 in turn
+#pragma unroll 1
+  for (int w = 1; w < WAVES_WH; ++w) {
+    __syncthreads();
+    if (wave == w) {
+#pragma unroll
+      for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lds[(p * 4 + r) * 64 + lane] = acc[p][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[p][r] += lds[(p * 4 + r) * 64 + lane];
+    }
+  }
+  if (wave == 0) {
+    int p = 0;
+#pragma unroll
+    for (int bi = 0; bi < NRB; ++bi)
+#pragma unroll
+      for (int bj = bi; bj < NRB; ++bj, ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = bi * 16 + q + 4 * r, jj = bj * 16 + rr;
+          if (i < N && jj < N) j.cpart[((size_t)c * N + i) * N + jj] = acc[p][r];
+        }
   }
 }
 
-// RB = 4 for problems with N <= 64, 8 otherwise (one launch per class).
+// N > 64 (5 to 8 row blocks, up to 36 block pairs): the four waves split the
+// block pairs instead of the samples (wave w forms the pairs p = w mod 4 of
+// the bi <= bj enumeration over every sample of the chunk, at most 9
+// accumulators) and each writes its own entries.  Operands are read six steps
+// ahead; the waves read the same X rows, mostly from L1.
+template <int NRB, int PH, typename TIN>
+__device__ __forceinline__ void cov_pairs_body(const WJob &j, int c) {
+  typedef __attribute__((address_space(1))) const TIN gin;
+  constexpr int NPAIR = NRB * (NRB + 1) / 2;
+  constexpr int NMINE = (NPAIR - PH + 3) / 4;
+  const int N = j.N;
+  const long long T = j.T;
+  const long long t0 = (long long)c * T / j.cch, t1 = (long long)(c + 1) * T / j.cch;
+  gin *X = (gin *)j.X;
+  const long long ldx = j.ld;
+  const int lane = threadIdx.x % 64;
+  const int rr = lane % 16, q = lane / 16;
+  double mu[NRB];
+  gin *xr[NRB];
+#pragma unroll
+  for (int b = 0; b < NRB; ++b) {
+    const int r = b * 16 + rr < N ? b * 16 + rr : N - 1;
+    mu[b] = j.mean[r];
+    xr[b] = X + (size_t)r * (size_t)ldx;
+  }
+  // step s of the chunk covers samples t0 + 4 s + (0..3); lane takes t0 + 4 s + q
+  const long long nsteps = (t1 - t0 + 3) / 4;
+  auto load = [&](long long st, int b) -> double {
+    long long m = t0 + 4 * st + q;
+    if (m > t1 - 1) m = t1 - 1;
+    return (double)xr[b][m];
+  };
+  cov_f64x4 acc[NMINE];
+#pragma unroll
+  for (int p = 0; p < NMINE; ++p) acc[p] = cov_f64x4{0.0, 0.0, 0.0, 0.0};
+  // operands PD steps ahead: a step is at most 9 MFMAs, and at one wave per
+  // SIMD the first touch of a sample comes from HBM
+  constexpr int PD = 6;
+  double buf[PD][NRB];
+#pragma unroll
+  for (int h = 0; h < PD; ++h)
+#pragma unroll
+    for (int b = 0; b < NRB; ++b) buf[h][b] = load(h, b);
+  for (long long st = 0; st < nsteps; st += PD) {
+#pragma unroll
+    for (int h = 0; h < PD; ++h) {
+      const long long m = t0 + 4 * (st + h) + q;
+      double v[NRB];
+#pragma unroll
+      for (int b = 0; b < NRB; ++b) {
+        v[b] = m < t1 ? buf[h][b] - mu[b] : 0.0;
+        buf[h][b] = load(st + h + PD, b);
+      }
+      int p = 0, mine = 0;
+#pragma unroll
+      for (int bi = 0; bi < NRB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NRB; ++bj, ++p)
+          if (p % 4 == PH) {
+            acc[mine] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[mine], 0, 0, 0);
+            ++mine;
+          }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  int p = 0, mine = 0;
+#pragma unroll
+  for (int bi = 0; bi < NRB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NRB; ++bj, ++p)
+      if (p % 4 == PH) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = bi * 16 + q + 4 * r, jj = bj * 16 + rr;
+          if (i < N && jj < N) j.cpart[((size_t)c * N + i) * N + jj] = acc[mine][r];
+        }
+        ++mine;
+      }
+}
+
+template <int NRB, typename TIN>
+__device__ __forceinline__ void cov_pairs(const WJob &j, int c) {
+  switch (threadIdx.x / 64) {
+    case 0: cov_pairs_body<NRB, 0, TIN>(j, c); break;
+    case 1: cov_pairs_body<NRB, 1, TIN>(j, c); break;
+    case 2: cov_pairs_body<NRB, 2, TIN>(j, c); break;
+    default: cov_pairs_body<NRB, 3, TIN>(j, c); break;
+  }
+}
+
+// RB = 4: problems with N <= 64 (1 to 4 row blocks, the waves split the
+// samples); RB = 8: N > 64 (5 to 8, the waves split the block pairs); one
+// launch per class, each kernel with the registers of its own sizes.
+template <int RB, typename TIN>
+__device__ __forceinline__ void cov_dispatch(const WJob &j, int c, double *lds) {
+  const int nrb = (j.N + 15) / 16;
+  if constexpr (RB == 8) {
+    (void)lds;
+    switch (nrb) {
+      case 5: cov_pairs<5, TIN>(j, c); break;
+      case 6: cov_pairs<6, TIN>(j, c); break;
+      case 7: cov_pairs<7, TIN>(j, c); break;
+      default: cov_pairs<8, TIN>(j, c); break;
+    }
+  } else {
+    switch (nrb) {
+      case 1: cov_part_body<1, TIN>(j, c, lds); break;
+      case 2: cov_part_body<2, TIN>(j, c, lds); break;
+      case 3: cov_part_body<3, TIN>(j, c, lds); break;
+      default: cov_part_body<4, TIN>(j, c, lds); break;
+    }
+  }
+}
+
 template <int RB>
 __global__ __launch_bounds__(256) void k_cov_part(const WJob *__restrict__ jobs, WJob one,
                                                   const int *__restrict__ start, int D) {
-  __shared__ double xs[COV_TS * (16 * RB + 2)];
+  extern __shared__ double cov_lds[];
   int c = blockIdx.x;
   const int d = start ? job_of(start, D, c) : 0;
   if (start) c -= start[d];
   const WJob j = start ? jobs[d] : one;
-  if (j.f64) cov_part_body<double, RB>(j, c, xs);
-  else cov_part_body<float, RB>(j, c, xs);
+  if (j.f64) cov_dispatch<RB, double>(j, c, cov_lds);
+  else cov_dispatch<RB, float>(j, c, cov_lds);
+}
+
+// Dynamic LDS of k_cov_part<RB> for problems up to n_max features.
+template <int RB>
+static size_t cov_prepare(int n_max) {
+  const size_t lds = cov_lds_bytes(n_max);
+  (void)hipFuncSetAttribute((const void *)k_cov_part<RB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  return lds;
 }
 
 // One wave per (problem, matrix element) (lanes over chunks, fixed shuffle
@@ -840,9 +1013,11 @@ hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_d
   hipLaunchKernelGGL(k_mean_part, dim3(j.ch), dim3(256), 0, st, nullptr, j, nullptr, 1);
   hipLaunchKernelGGL(k_mean_final, dim3((N + 3) / 4), dim3(256), 0, st, nullptr, j, nullptr, 1, N);
   if (N <= 64)
-    hipLaunchKernelGGL(k_cov_part<4>, dim3(j.cch), dim3(256), 0, st, nullptr, j, nullptr, 1);
+    hipLaunchKernelGGL(k_cov_part<4>, dim3(j.cch), dim3(256), cov_prepare<4>(N), st, nullptr, j,
+                       nullptr, 1);
   else
-    hipLaunchKernelGGL(k_cov_part<8>, dim3(j.cch), dim3(256), 0, st, nullptr, j, nullptr, 1);
+    hipLaunchKernelGGL(k_cov_part<8>, dim3(j.cch), dim3(256), cov_prepare<8>(N), st, nullptr, j,
+                       nullptr, 1);
   hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, nullptr, j, nullptr, 1,
                      N * N);
   const JacJob job{N, b.C, b.E, b.rot, b.pq, b.sweeps};
@@ -935,11 +1110,11 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
     hipLaunchKernelGGL(k_mean_final, dim3((tot(W_MEANF) + 3) / 4), dim3(256), 0, st, wj_dev + d0,
                        j0, rng(W_MEANF), n, tot(W_MEANF));
     if (tot(W_COV4) > 0)
-      hipLaunchKernelGGL(k_cov_part<4>, dim3(tot(W_COV4)), dim3(256), 0, st, wj_dev + d0, j0,
-                         rng(W_COV4), n);
+      hipLaunchKernelGGL(k_cov_part<4>, dim3(tot(W_COV4)), dim3(256), cov_prepare<4>(64), st,
+                         wj_dev + d0, j0, rng(W_COV4), n);
     if (tot(W_COV8) > 0)
-      hipLaunchKernelGGL(k_cov_part<8>, dim3(tot(W_COV8)), dim3(256), 0, st, wj_dev + d0, j0,
-                         rng(W_COV8), n);
+      hipLaunchKernelGGL(k_cov_part<8>, dim3(tot(W_COV8)), dim3(256), cov_prepare<8>(NMAX), st,
+                         wj_dev + d0, j0, rng(W_COV8), n);
     hipLaunchKernelGGL(k_cov_final, dim3((tot(W_COVF) + 3) / 4), dim3(256), 0, st, wj_dev + d0, j0,
                        rng(W_COVF), n, tot(W_COVF));
   }
