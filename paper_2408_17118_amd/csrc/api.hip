@@ -249,6 +249,15 @@ int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
 
 // Run passes on data X (F32) from the rows currently in B with active list
 // act[0] (count already in ctl->kact[0]); returns the number of passes launched.
+// Rows on the list a finish phase starts from (its counter's pass-0 count);
+// synchronises.  Negative: an OICA_E_* code.
+static int finish_rows(oica_ctx *ctx, const FpControl *ctl) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return ((const FpControl *)ctx->small_host)->kact[0];
+}
+
 int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const void *X, bool bf16,
                int K, float *B, int *act0, int *act1, float *gpart, float *s4part, double *red,
                FpControl *ctl,
@@ -489,10 +498,14 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         FpControl *ctl3 = (FpControl *)((char *)ctl2 + 256);  // kurtosis list counter
         HIP_TRY(ctx, launch_group_lists(ctx->stream, K, cluster, reps, ctx->small_dev + 1, status,
                                         kurt, act2, ctl2, left_list, left_rows, kurt_list, ctl3));
-        if (fp32_passes > 0) {
-          rc = run_passes(ctx, plan32, N, T, X32p, false, K, W_out, act2, act0, gpart, s4part, red,
-                          ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr, 0,
-                          false, &l2, &ms2);
+        // the representatives' count bounds the FP32 passes' active rows, so
+        // few of them take the thin items from the first pass on
+        const int rows0 = finish_rows(ctx, ctl2);
+        if (rows0 < 0) return rows0;
+        if (fp32_passes > 0 && rows0 > 0) {
+          rc = run_passes(ctx, plan32, N, T, X32p, false, rows0, W_out, act2, act0, gpart, s4part,
+                          red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
+                          0, false, &l2, &ms2);
           if (rc) return rc;
         }
         HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, X32p, K, W_out, s4part64, kurt,
@@ -502,8 +515,10 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
       } else {
         // FP32 passes for every row that converged on BF16 data or is still moving
         HIP_TRY(ctx, launch_refine_select(ctx->stream, K, status, act2, ctl2, left_list, left_rows));
-        if (fp32_passes > 0) {
-          rc = run_passes(ctx, plan32, N, T, X32p, false, K, W_out, act2, act0, gpart, s4part,
+        const int rows0 = finish_rows(ctx, ctl2);
+        if (rows0 < 0) return rows0;
+        if (fp32_passes > 0 && rows0 > 0) {
+          rc = run_passes(ctx, plan32, N, T, X32p, false, rows0, W_out, act2, act0, gpart, s4part,
                           red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
                           0, false, &l2, &ms2);
           if (rc) return rc;
