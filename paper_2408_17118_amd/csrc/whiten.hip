@@ -25,7 +25,6 @@
 namespace oica {
 
 constexpr int NMAX = OICA_MAX_N;
-constexpr int COV_TS = 32;        // samples per LDS tile in the covariance pass
 constexpr int MIN_CHUNK = 256;    // fewest samples per work-group in the reduction passes
 constexpr int MAX_CHUNKS = 1024;  // mean pass
 constexpr int MAX_COV_CHUNKS = 512;
@@ -145,7 +144,6 @@ __global__ void k_mean_final(const WJob *__restrict__ jobs, WJob one, const int 
 // stored.  Samples past the chunk are zero.
 typedef double cov_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int WAVES_WH = 4;  // waves of a 256-thread work-group
-constexpr int COV_MAX_PAIRS = (NMAX / 16) * (NMAX / 16 + 1) / 2;
 static size_t cov_lds_bytes(int N) {  // the sample-split form's exchange (N <= 64)
   const int nrb = (N + 15) / 16;
   return nrb > 4 ? 0 : (size_t)(nrb * (nrb + 1) / 2) * 4 * 64 * sizeof(double);
@@ -866,7 +864,7 @@ __global__ __launch_bounds__(256) void k_apply(const WJob *__restrict__ jobs, WJ
   if (j.f64) apply_dispatch<BIG, double>(j, t, ap_lds);
   else apply_dispatch<BIG, float>(j, t, ap_lds);
 }
-static_assert(AP_MAX_RB == 8, "apply dispatch covers N up to 128");
+static_assert(AP_MAX_RB == 8, "the apply and covariance dispatches cover N up to 128");
 
 // Dynamic LDS of k_apply<BIG> for problems up to n_max features.
 template <bool BIG>
