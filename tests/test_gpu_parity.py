@@ -104,6 +104,26 @@ def test_whiten_matches_oracle(ctx, N, T):
     assert np.max(np.abs(C - np.eye(N))) < 1e-5
 
 
+@pytest.mark.parametrize("N,T,f32", [(16, 2000, False), (17, 1023, True), (64, 257, False),
+                                      (65, 1023, False), (80, 3001, True), (96, 1025, False),
+                                      (113, 2500, False), (128, 3000, True)])
+def test_whiten_kernel_class_edges(ctx, N, T, f32):
+    """Row-block and kernel-class edges of the covariance and apply passes (one
+    kernel for N <= 64, another above; 16-row blocks), short and ragged sample
+    counts (one chunk, a partial last work item), raw FP32 and FP64 input,
+    against the oracle."""
+    X = _mixture(N, T, 1, seed=900 + N).X + 0.25
+    Xd = dev(X.astype(np.float32)) if f32 else dev(X)
+    Xw, X32, V, mu, lam = ctx.whiten(Xd)
+    Xwr, Vr, mur, lamr = ica.whiten(host(Xd).astype(np.float64))
+    assert np.allclose(host(mu), mur, rtol=1e-12, atol=1e-12)
+    # the reference eigensolver fixes small eigenvalues to eps x the largest
+    assert np.allclose(host(lam), lamr, rtol=1e-9, atol=1e-13 * lamr.max())
+    assert np.allclose(host(V), Vr, rtol=1e-7, atol=1e-7 * np.abs(Vr).max())
+    Xg = host(Xw).astype(np.float64)
+    assert np.max(np.abs(Xg - Xwr)) <= 1e-5 * max(1.0, np.abs(Xwr).max())
+
+
 def test_whiten_bf16_output(ctx):
     p = _mixture(16, 4096, 1, seed=5)
     Xw16, X32, V, mu, lam = ctx.whiten(dev(p.X), out_dtype=torch.bfloat16)
