@@ -571,6 +571,10 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
           a[4] = hi[0]; a[5] = hi[1]; a[6] = hi[2]; a[7] = hi[3];
           return a;
         };
+        // GEMM1 at raised wave priority: while one wave of a SIMD runs its
+        // dependent MFMA chain, the other's cube and staging instructions do
+        // not take its issue slots
+        __builtin_amdgcn_s_setprio(1);
         f32x16 zacc[WK];
 #pragma unroll
         for (int w = 0; w < WK; ++w) zacc[w] = f32x16{0.f};
@@ -595,6 +599,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
           else if (s + AH - S1 < S2) abuf[s % AH] = gb(s + AH - S1);
           __builtin_amdgcn_sched_barrier(0);
         }
+        __builtin_amdgcn_s_setprio(0);
         bf16x8 p3[WK][2];
 #pragma unroll
         for (int w = 0; w < WK; ++w) {
