@@ -2,6 +2,7 @@
 fixture.  Calls only the seeded generator and ``oracle/``.
 
 Usage: python tests/golden/make_reference.py eeg_shaped_n64
+       python tests/golden/make_reference.py precision_n128   (about an hour)
 """
 import json
 import os
@@ -17,6 +18,7 @@ from paper_2408_17118_amd import synth  # noqa: E402
 
 WORKLOADS = {
     "eeg_shaped_n64": lambda: synth.eeg_shaped(),
+    "precision_n128": lambda: synth.precision_workload(),
 }
 
 

@@ -324,26 +324,41 @@ def test_fixed_point_trajectory(ctx):
     p = synth.small_mixture()
     Xw, *_ = ica.whiten(p.X)
     X32 = Xw.astype(np.float32)
-    res = ctx.fixed_point(dev(X32), dev(p.W0.astype(np.float32)), tol=1e-6, max_iter=1000,
+    tol = 1e-6
+    res = ctx.fixed_point(dev(X32), dev(p.W0.astype(np.float32)), tol=tol, max_iter=1000,
                           traj_iters=8)
-    _, _, _, trr, _ = ica.fixed_point(X32.astype(np.float64), p.W0, tol=1e-6, max_iter=1000,
-                                      traj_iters=8)
+    Br, itr, _, trr, _ = ica.fixed_point(X32.astype(np.float64), p.W0, tol=tol, max_iter=1000,
+                                         traj_iters=8)
     tr = host(res["traj"]).astype(np.float64)
-    # per row: recorded passes agree (the FP32 and FP64 trajectories may part
-    # ways for the <= 1 % of rows whose basin differs, checked elsewhere)
-    ok_rows = 0
-    for l in range(tr.shape[0]):
-        both = np.isfinite(tr[l, :, 0]) & np.isfinite(trr[l, :, 0])
-        a, ar = tr[l, both, 0], trr[l, both, 0]
-        d, dr = tr[l, both, 1], trr[l, both, 1]
-        # the trajectory kurtosis is a by-product of the update pass: sum z^4 / T
-        # (= alpha + 3) accumulated in FP32, so its error scales with |alpha| + 3;
-        # step sizes carry the ~1e-7 absolute noise of FP32 iterates
-        good = (np.array_equal(np.isfinite(tr[l, :, 0]), np.isfinite(trr[l, :, 0]))
-                and np.all(np.abs(a - ar) <= 1e-5 * (np.abs(ar) + 3.0))
-                and np.all(np.abs(d - dr) <= 1e-4 * dr + 2e-6))
-        ok_rows += good
-    assert ok_rows >= 0.99 * tr.shape[0], ok_rows
+    W, it = host(res["W"]).astype(np.float64), host(res["iters"])
+    # Tolerances (reading of the recorded trajectory): the kurtosis entry is
+    # sum z^4 / T - 3 with the fourth-power sum accumulated in FP32 per split,
+    # so its error scales with alpha + 3 (the quantity summed), not with alpha;
+    # the step carries the ~1e-7 absolute noise of FP32 iterates.
+    def close_a(a, ar):
+        return np.abs(a - ar) <= 1e-5 * (np.abs(ar) + 3.0)
+
+    def close_d(d, dr):
+        return np.abs(d - dr) <= 1e-4 * dr + 2e-6
+    # every row starts from the same vector: the first recorded kurtosis agrees
+    assert np.all(close_a(tr[:, 0, 0], trr[:, 0, 0]))
+    same = _rowwise_abs_cos(W, Br) >= 1 - 1e-6
+    assert same.mean() >= 0.99
+    for l in np.flatnonzero(same):
+        # a row that ends in the oracle's basin has the oracle's trajectory
+        fin, finr = np.isfinite(tr[l, :, 0]), np.isfinite(trr[l, :, 0])
+        both = fin & finr
+        assert np.all(close_a(tr[l, both, 0], trr[l, both, 0])), l
+        assert np.all(close_d(tr[l, both, 1], trr[l, both, 1])), l
+        if it[l] == itr[l]:
+            assert np.array_equal(fin, finr), l
+        else:
+            # one side stopped a pass earlier: only at a step within the FP32
+            # noise of the threshold
+            assert abs(int(it[l]) - int(itr[l])) == 1, l
+            last = min(int(it[l]), int(itr[l])) - 1
+            if last < tr.shape[1]:
+                assert abs(trr[l, last, 1] - tol) <= 2e-6, l
 
 
 def test_fixed_point_is_deterministic(ctx):

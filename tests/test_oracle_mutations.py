@@ -111,3 +111,44 @@ def _greedy_signed(B, alpha, status, tau):
     return {"U": np.array([ica.canonical_sign(B[r]) for r in reps]), "alpha": alpha[reps],
             "upsilon": ups[reps], "rep": np.array(reps), "size": np.array(sizes),
             "n_accepted": len(reps)}
+
+
+def test_s4_from_updated_rows_caught(monkeypatch):
+    # the kurtosis by-product taken from the normalised new rows instead of the
+    # rows the pass started from
+    def upd(Xw, P):
+        G, _ = _update(Xw, P)
+        Bn = G / np.linalg.norm(G, axis=1, keepdims=True)
+        _, s4n = _update(Xw, Bn)
+        return G, s4n
+    monkeypatch.setattr(ica, "update", upd)
+    with pytest.raises(AssertionError):
+        pins.test_update_s4_matches_scipy(_small())
+
+
+_fixed_point = ica.fixed_point
+
+
+@pytest.mark.parametrize("kind", ["shift_one_pass", "alpha_after_update"])
+def test_trajectory_mutations_caught(monkeypatch, kind):
+    def fp(Xw, W0, tol, max_iter, traj_iters=0):
+        B, iters, status, traj, ti = _fixed_point(Xw, W0, tol, max_iter, traj_iters)
+        traj = traj.copy()
+        if kind == "shift_one_pass":        # record of pass t stored at t + 1
+            traj[:, 1:] = traj[:, :-1].copy()
+        else:                               # kurtosis of the row after the pass
+            traj[:, :-1, 0] = traj[:, 1:, 0].copy()
+        return B, iters, status, traj, ti
+    monkeypatch.setattr(ica, "fixed_point", fp)
+    with pytest.raises(AssertionError):
+        pins.test_fixed_point_trajectory_matches_library(_small())
+
+
+def test_degenerate_counted_as_update_caught(monkeypatch):
+    def fp(Xw, W0, tol, max_iter, traj_iters=0):
+        B, iters, status, traj, ti = _fixed_point(Xw, W0, tol, max_iter, traj_iters)
+        iters = iters + (status == ica.DEGENERATE)
+        return B, iters, status, traj, ti
+    monkeypatch.setattr(ica, "fixed_point", fp)
+    with pytest.raises(AssertionError):
+        pins.test_fixed_point_degenerate_rows(_small())

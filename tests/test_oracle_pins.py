@@ -163,6 +163,93 @@ def test_update_matches_library_fastica(small):
         assert np.max(np.abs(B[0] - ref)) < 1e-12
 
 
+# ---- update's second output: sum z^4 / T (eq. 2 plus 3) ---------------------
+
+def test_update_s4_matches_scipy(small):
+    # scipy's non-excess kurtosis m4 / m2^2 uses central moments; for unit rows
+    # on white, centred data m2 = 1 and the mean is 0, so it equals sum z^4 / T
+    scipy_stats = pytest.importorskip("scipy.stats")
+    p, Xw, *_ = small
+    P = ica.normalise_rows(p.W0[:32])
+    _, s4 = ica.update(Xw, P)
+    ref = scipy_stats.kurtosis(P @ Xw, axis=1, fisher=False, bias=True)
+    assert np.allclose(s4, ref, rtol=1e-10, atol=0.0)
+
+
+# ---- the recorded trajectory against library FastICA iterates ---------------
+
+def _library_iterates(Xw, w_first, others, n):
+    """Iterates w_0 .. w_n of component 0 of scikit-learn's FastICA (deflation,
+    cube, no whitening, tol 0) started from w_first: w_t is the fit with
+    max_iter = t (w_0 is the normalised start)."""
+    import warnings
+
+    sk = pytest.importorskip("sklearn.decomposition")
+    w_init = np.vstack([w_first, others])
+    out = [w_first / np.linalg.norm(w_first)]
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        for t in range(1, n + 1):
+            out.append(sk.FastICA(n_components=w_init.shape[0], algorithm="deflation",
+                                  whiten=False, fun="cube", w_init=w_init, max_iter=t,
+                                  tol=0.0).fit(Xw.T).components_[0])
+    return out
+
+
+def test_fixed_point_trajectory_matches_library(small):
+    # traj[l, t] = (excess kurtosis of the row before pass t+1, step of pass t+1):
+    # the kurtosis from scipy on the library's iterate w_t, the step
+    # min(||w_{t+1} - w_t||, ||w_{t+1} + w_t||) from the library's iterates
+    scipy_stats = pytest.importorskip("scipy.stats")
+    p, Xw, *_ = small
+    N = p.N
+    rows = [0, 5, 17, 100, 201]
+    R = 20
+    B, iters, status, traj, _ = ica.fixed_point(Xw, p.W0[rows], tol=1e-10, max_iter=1000,
+                                                traj_iters=R)
+    stopped_early = 0
+    for i, l in enumerate(rows):
+        others = np.delete(p.W0[:N], 0, axis=0)
+        ws = _library_iterates(Xw, p.W0[l], others[: N - 1], min(R, int(iters[i])))
+        for t in range(R):
+            if t >= iters[i]:
+                # passes after the row stopped are not recorded
+                assert np.isnan(traj[i, t, 0]) and np.isnan(traj[i, t, 1])
+                stopped_early += 1
+                continue
+            a_ref = scipy_stats.kurtosis(ws[t] @ Xw, fisher=True, bias=True)
+            d_ref = min(np.linalg.norm(ws[t + 1] - ws[t]), np.linalg.norm(ws[t + 1] + ws[t]))
+            assert abs(traj[i, t, 0] - a_ref) < 1e-10, (l, t)
+            assert abs(traj[i, t, 1] - d_ref) < 1e-11, (l, t)
+    assert stopped_early > 0      # the NaN tail is exercised
+
+
+# ---- R17: degenerate rows -----------------------------------------------------
+
+def test_fixed_point_degenerate_rows(small):
+    # a zero or non-finite start row has no direction: it is DEGENERATE with
+    # no update applied; every other row evolves exactly as it would alone
+    p, Xw, *_ = small
+    W0 = p.W0[:16].copy()
+    W0[3] = 0.0
+    W0[9, 2] = np.nan
+    with np.errstate(invalid="ignore", divide="ignore"):
+        B, iters, status, traj, ti = ica.fixed_point(Xw, W0, tol=1e-10, max_iter=1000,
+                                                     traj_iters=4)
+    for l in (3, 9):
+        assert status[l] == ica.DEGENERATE and iters[l] == 0
+        assert np.all(np.isnan(traj[l, :, 1]))
+    good = [l for l in range(16) if l not in (3, 9)]
+    B2, iters2, status2, *_ = ica.fixed_point(Xw, W0[good], tol=1e-10, max_iter=1000)
+    assert np.array_equal(iters[good], iters2) and np.array_equal(status[good], status2)
+    assert np.max(np.abs(B[good] - B2)) < 1e-12
+    assert np.all(status2 == ica.CONV)
+    # the single-candidate form agrees on the surviving rows
+    for i, l in enumerate(good[:4]):
+        w, t, conv = ica.fastica_single(Xw, W0[l], tol=1e-10, max_iter=1000)
+        assert conv and t == iters2[i] and np.max(np.abs(w - B2[i])) < 1e-12
+
+
 # ---- P5: brute force over all directions at N = 2 ---------------------------
 
 def _alpha_on_circle(Xw, theta):
