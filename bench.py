@@ -3,25 +3,25 @@
 
 One step = the whole path on one batch of device-resident synthetic input:
 whitening (FP64) -> batched kurtosis fixed point with removal of converged rows
-(FP32 MFMA) -> FP64 kurtosis -> clustering up to sign, ordering and the
-Gaussianity test.  Workload: the EEG-shaped mixture N=64, T=200,000, K=4,096
-random starts (24 Laplace, 16 Student-t nu=5, 12 uniform, 8 sines, 4 Gaussian).
+-> FP64 kurtosis -> clustering up to sign, ordering and the Gaussianity test.
+
+Default workload: the precision form at N=128, T=1e6, K=16,384 random starts
+(48 Laplace, 32 Student-t nu=5, 24 uniform, 16 sines, 8 Gaussian sources):
+BF16 data and BF16 MFMA with FP32 sums, then FP32 passes until the FP32
+threshold; its roofline entry is the BF16 fused kernel against the BF16 MFMA
+peak.  The same workload then runs in the plain FP32 form (time to the same
+unique components), and the timed run's unique set is compared with the stored
+FP64 oracle run of this workload when it is present.
 
 Prints one JSON line.  ``value`` is thread-iterations per second over the whole
 step (a thread-iteration is one update of one start vector: 2 N T MACs);
 ``ms_per_step`` is the time from raw data in HBM to the unique list on the host.
 
-After the timed region the same workload runs in the mixed-precision form
-(BF16 data, BF16 MFMA, FP32 finish of one row per group of identical BF16
-fixed points) and the line reports its time to unique components, the speedup
-over the plain FP32 step and whether the accepted components are the same.
-
-``--workload precision_n128`` times the precision form instead (N=128, T=1e6,
-K=16384): BF16 data and BF16 MFMA with FP32 sums, then FP32 passes until the
-FP32 threshold; its roofline entry is the BF16 fused kernel against the BF16
-MFMA peak.  ``--workload pruner_n64`` times the learned-pruner workload (N=64,
-T=2e5, K=65536, held-out seed 5300): BF16 with the shipped pruner, reported
-against the plain FP32 and the unpruned BF16 runs.
+``--workload eeg_shaped_n64`` times the plain FP32 form on the EEG-shaped
+mixture (N=64, T=2e5, K=4096) and compares the mixed-precision form;
+``--workload pruner_n64`` times the learned-pruner workload (N=64, T=2e5,
+K=65536, held-out seed 5300) against the plain FP32 and unpruned BF16 runs;
+``--workload batched_n16_128`` times 64 datasets in one batched call.
 """
 from __future__ import annotations
 
@@ -40,10 +40,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-HBM_PROFILE = os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_counters.txt")
+HBM_PROFILES = {
+    "eeg_shaped_n64": os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_counters.txt"),
+    "precision_n128": os.path.join(ROOT, "profiles", "fused_update_bf16_precision_n128_hbm_counters.txt"),
+}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "{}_oracle.json")
 
 
-def counted_traffic():
+def counted_traffic(workload):
     """HBM bytes per launch of the fused update from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when the kernel's sources (the
     listed files, hashed in order as one byte string) have changed since those
@@ -51,7 +55,7 @@ def counted_traffic():
     import hashlib
     try:
         fields = {}
-        for line in open(HBM_PROFILE):
+        for line in open(HBM_PROFILES[workload]):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
@@ -68,14 +72,15 @@ def counted_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="eeg_shaped_n64",
+    ap.add_argument("--workload", default="precision_n128",
                     choices=["eeg_shaped_n64", "precision_n128", "pruner_n64", "batched_n16_128"])
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=4096,
-                    help="start rows in the CPU-oracle sample")
-    ap.add_argument("--cpu-passes", type=int, default=5)
+    ap.add_argument("--cpu-rows", type=int, default=None,
+                    help="start rows in the CPU-oracle sample (default 256 at N=128, else 4096)")
+    ap.add_argument("--cpu-passes", type=int, default=None,
+                    help="passes in the CPU-oracle sample (default 4 at N=128, else 5)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison runs of the other precision forms (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -120,6 +125,31 @@ def cpu_baseline(prob, rows: int, passes: int):
         "whiten_s": t1 - t0,
         "fixed_point_s": t2 - t1,
     }
+
+
+def vs_oracle(workload, res):
+    """Errors of a timed run's unique set against the stored FP64 oracle run of
+    the same workload (tests/golden), in raw-data space; None if not stored."""
+    path = GOLDEN.format(workload)
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    n = ref["n_accepted"]
+    V = res["V"].cpu().numpy()
+    na = res["n_accepted"]
+    U = res["U"].cpu().numpy()[:na] @ V
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    Ur = np.array(ref["U_raw"])[:n]
+    cos = np.abs(U @ Ur.T) if na and n else np.zeros((na, n))
+    best = cos.max(axis=1) if n else np.zeros(na)
+    match = cos.argmax(axis=1) if n else np.zeros(na, int)
+    ar = np.array(ref["alpha"])
+    a = res["alpha"].cpu().numpy()[:na]
+    rel = np.abs(a - ar[match]) / np.maximum(np.abs(ar[match]), 0.1) if na and n else np.zeros(0)
+    return {"oracle": os.path.relpath(path, ROOT), "same_n_unique": res["n_unique"] == ref["n_unique"],
+            "same_n_accepted": na == n, "one_to_one": len(set(match.tolist())) == na,
+            "max_1_minus_abs_cos": float(np.max(1 - best)) if na else None,
+            "max_kurtosis_rel_err": float(rel.max()) if rel.size else None}
 
 
 def main():
@@ -226,7 +256,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": (achieved_tflops / peak) if achieved_tflops else None,
-            "traffic": None if bf16 else counted_traffic(),
+            "traffic": counted_traffic(args.workload),
             "traffic_unit": "bytes/launch (HBM FETCH+WRITE, calibrated)",
             "avg_launch_ms": upd_ms / launches if launches else None,
             "avg_rows_per_launch": ti / launches if launches else None,
@@ -257,6 +287,10 @@ def main():
                 "pruned": r["fp"].get("pruned", 0)}
     if args.no_compare:
         pass
+    elif args.workload == "precision_n128":
+        pf = compare("plain fp32", precision="f32")
+        out["plain_fp32"] = pf
+        out["speedup_vs_plain_fp32"] = pf["time_to_unique_ms"] / ms_per_step
     elif args.workload == "eeg_shaped_n64":
         mp = compare("bf16 + fp32 finish (mixed precision)", precision="bf16", tol_bf16=1e-5)
         mp["speedup_vs_plain_fp32"] = ms_per_step / mp["time_to_unique_ms"]
@@ -268,8 +302,13 @@ def main():
         out["bf16_unpruned"] = ub
         out["speedup_vs_plain_fp32"] = pf["time_to_unique_ms"] / ms_per_step
         out["pruner_thread_iter_saving"] = 1.0 - (ti / args.steps) / ub["thread_iters"]
-    if not args.no_cpu_baseline and not bf16:
-        cb = cpu_baseline(prob, args.cpu_rows, args.cpu_passes)
+    vo = vs_oracle(args.workload, last)
+    if vo is not None:
+        out["vs_oracle"] = vo
+    if not args.no_cpu_baseline:
+        rows = args.cpu_rows or (256 if N == 128 else 4096)
+        passes = args.cpu_passes or (4 if N == 128 else 5)
+        cb = cpu_baseline(prob, rows, passes)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     ctx.close()
     print(json.dumps(out))

@@ -273,11 +273,12 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
   *kernel_ms = 0.0;
   // few rows active: the thin items (FP32, up to THIN_PLAN_ROWS rows), or one
   // 32-row block per wave (BF16, at most one such row block; same splits)
-  const FusedPlan narrow = bf16 ? narrow_plan(plan) : thin_plan(plan);
+  const int np = fused_np(N);
+  const FusedPlan narrow = bf16 ? narrow_plan(plan, np) : thin_plan(plan);
   for (int pass = 0; pass < max_iter; ++pass) {
     int *cur = (pass & 1) ? act1 : act0;
     int *nxt = (pass & 1) ? act0 : act1;
-    const bool few = bf16 ? (kmax <= WAVES_PER_WG * 32 && plan.kwg > WAVES_PER_WG * 32)
+    const bool few = bf16 ? (kmax <= bf16_waves(np) * 32 && plan.kwg > bf16_waves(np) * 32)
                           : kmax <= THIN_PLAN_ROWS;
     const FusedPlan &pp = few ? narrow : plan;
     if (profile) {

@@ -30,12 +30,12 @@ static int rows_per_wave(int kmax) {
   return r < 1 ? 1 : (r > EPI_ROWS ? EPI_ROWS : r);
 }
 
-// The same plan with one 32-row block per wave: for passes with at most
-// WAVES * 32 active rows (one row block either way, so the same sample splits
+// The BF16 plan with one 32-row block per wave: for passes with at most
+// bf16_waves(np) * 32 active rows (one row block either way, so the same sample splits
 // and the same arithmetic per row, with half the padded rows).
-FusedPlan narrow_plan(const FusedPlan &p) {
+FusedPlan narrow_plan(const FusedPlan &p, int np) {
   FusedPlan q = p;
-  q.kwg = WAVES * 32;
+  q.kwg = bf16_waves(np) * 32;
   return q;
 }
 
@@ -50,11 +50,10 @@ FusedPlan thin_plan(const FusedPlan &p) {
 
 FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
   (void)kmax;
-  (void)bf16;
   FusedPlan p;
   int np = fused_np(N);
   p.grid = GRID;
-  p.kwg = WAVES * wk_for_np(np) * 32;
+  p.kwg = (bf16 ? bf16_waves(np) : WAVES) * wk_for_np(np) * 32;
   int64_t n_sub = (T + 31) / 32;
   p.n_sub = (int)n_sub;
   int64_t ms = n_sub / MIN_SUB;
@@ -188,11 +187,12 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32_thin(
 }
 
 template <int NP, int WK>
-__global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
+__global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
     const __bf16 *__restrict__ X, int N, long long T, FusedPlan plan, const float *__restrict__ Bm,
     const int *__restrict__ act, const int *__restrict__ kact_dev, int kact_host,
     float *__restrict__ gpart, float *__restrict__ s4part, FpControl *ctl, int pass) {
-  constexpr int KWG = WAVES * WK * 32;
+  constexpr int NW = bf16_waves(NP);
+  constexpr int KWG = NW * WK * 32;
   constexpr int XTS = BfStride<NP>::v;
   __shared__ __attribute__((aligned(16))) __bf16 xs[2 * BfTile<NP>::xs_elems];
   __shared__ __attribute__((aligned(16))) __bf16 xt[2 * BfTile<NP>::xt_elems];
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_bf16(
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
     if (s4part)
-      item_bf16<NP, WK, true>(c, w_item % n_kb, w_item / n_kb, xs, xt);
+      item_bf16<NP, WK, true, NW>(c, w_item % n_kb, w_item / n_kb, xs, xt);
     else
-      item_bf16<NP, WK, false>(c, w_item % n_kb, w_item / n_kb, xs, xt);
+      item_bf16<NP, WK, false, NW>(c, w_item % n_kb, w_item / n_kb, xs, xt);
   }
 }
 
@@ -494,21 +494,23 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
                                int kact_host, float *gpart, float *s4part, FpControl *ctl,
                                int pass) {
   const int np = fused_np(N);
-  const bool wk1 = p.kwg == WAVES * 32;  // one 32-row block per wave (narrow plan)
   if (bf16) {
+    const bool wk1 = p.kwg == bf16_waves(np) * 32;  // one 32-row block per wave (narrow plan)
+#define OICA_BF16_LAUNCH(WKV)                                                              \
+  hipLaunchKernelGGL((k_fused_bf16<NP_, WKV>), dim3(p.grid), dim3(bf16_waves(NP_) * 64), 0, st, \
+                     (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,        \
+                     gpart, s4part, ctl, pass)
     OICA_NP_SWITCH(np, {
       constexpr int WK2 = NP_ <= 64 ? 2 : 1;  // the wide variant
       if (!wk1)
-        hipLaunchKernelGGL((k_fused_bf16<NP_, WK2>), dim3(p.grid), dim3(WAVES * 64), 0, st,
-                           (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,
-                           gpart, s4part, ctl, pass);
+        OICA_BF16_LAUNCH(WK2);
       else
-        hipLaunchKernelGGL((k_fused_bf16<NP_, 1>), dim3(p.grid), dim3(WAVES * 64), 0, st,
-                           (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,
-                           gpart, s4part, ctl, pass);
+        OICA_BF16_LAUNCH(1);
     });
+#undef OICA_BF16_LAUNCH
     return hipGetLastError();
   }
+  const bool wk1 = p.kwg == WAVES * 32;  // one 32-row block per wave (narrow plan)
   if (p.thin) {
     OICA_NP_SWITCH(np, {
       hipLaunchKernelGGL((k_fused_f32_thin<NP_>), dim3(p.grid), dim3(WAVES * 64), 0, st,

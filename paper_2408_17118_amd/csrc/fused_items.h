@@ -420,10 +420,12 @@ template <int NP> struct BfTile {
 // S4: also form the per-row sums of z^4 (the kurtosis of the rows before the
 // update, recorded only in the passes whose trajectory is kept); without it
 // the sums are skipped and a non-null s4part receives zeros.
-template <int NP, int WK, bool S4 = true>
+// NW: waves of the work-group (all stage the shared X tile; each holds its own
+// WK x 32 rows).
+template <int NP, int WK, bool S4 = true, int NW = WAVES>
 __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs_base,
                                           __bf16 *xt_base) {
-  constexpr int KWG = WAVES * WK * 32;
+  constexpr int KWG = NW * WK * 32;
   constexpr int XTS = BfStride<NP>::v;
   g_cbf16 *__restrict__ X = (g_cbf16 *)c.X;
   const int N = c.N;
@@ -485,12 +487,12 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
     // store per sample holding the pair.
     constexpr int PAIRS = NP / 2;
     constexpr int UNITS = PAIRS * (BT / 8);
-    constexpr int F8 = (UNITS + WAVES * 64 - 1) / (WAVES * 64);
+    constexpr int F8 = (UNITS + NW * 64 - 1) / (NW * 64);
     bf16x8 pre0[F8], pre1[F8];
     auto fetch = [&](long long mt) {
 #pragma unroll
       for (int q = 0; q < F8; ++q) {
-        const int u = tid + q * WAVES * 64;
+        const int u = tid + q * NW * 64;
         const int pp = u % PAIRS, c = u / PAIRS;
         const long long gm = mt + c * 8;
         const int n0 = 2 * pp;
@@ -514,7 +516,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
       __bf16 *xt = xt_base + b * BfTile<NP>::xt_elems;
 #pragma unroll
       for (int q = 0; q < F8; ++q) {
-        const int u = tid + q * WAVES * 64;
+        const int u = tid + q * NW * 64;
         if (u < UNITS) {
           const int pp = u % PAIRS, c = u / PAIRS;
           bf16x4 *r0 = reinterpret_cast<bf16x4 *>(&xs[(2 * pp) * BSX + c * 8]);

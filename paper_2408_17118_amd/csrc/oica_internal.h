@@ -13,6 +13,11 @@
 namespace oica {
 
 constexpr int WAVES_PER_WG = 4;      // waves per work-group of the fused kernels
+// Waves per work-group of the single-problem BF16 pass kernel at padded
+// dimension np: for the widest tiles eight waves share one staged X tile,
+// which halves the staging work per row; below that (two 32-row blocks per
+// wave already) four waves measured faster.
+__host__ __device__ constexpr int bf16_waves(int np) { return np >= 96 ? 8 : 4; }
 constexpr int SPLIT_GROUP_HOST = 16; // splits per first-stage reduction item
 
 // Device-side bookkeeping of one fixed-point run.  Written by single lanes of
@@ -168,7 +173,7 @@ size_t whiten_workspace_bytes(int N, int64_t T);
 
 // fixed_point.hip
 int fused_np(int N);  // padded feature count used by the kernels for N
-FusedPlan narrow_plan(const FusedPlan &p);
+FusedPlan narrow_plan(const FusedPlan &p, int np);
 FusedPlan thin_plan(const FusedPlan &p);
 // Most active rows for the thin FP32 plan (rows padded to 32 instead of the
 // plan's 128 or 256).

@@ -321,44 +321,75 @@ def test_fixed_point_edge_cases(ctx):
 
 
 def test_fixed_point_trajectory(ctx):
+    """traj[l, t] = (kurtosis of the row before pass t+1, step of pass t+1).
+
+    Checked two ways.  Step by step, on every row and every recorded pass: the
+    GPU's iterates after t passes (runs capped at t passes) give the oracle's
+    kurtosis of the row the pass started from and the step to the next iterate,
+    and the next iterate is the oracle's normalised update of the previous one.
+    Whole trajectories, on every row: the oracle's own run, within what the
+    measured distance between the two sides' iterates allows (a wandering
+    start amplifies FP32 and FP64 rounding from pass to pass).
+    """
     p = synth.small_mixture()
     Xw, *_ = ica.whiten(p.X)
     X32 = Xw.astype(np.float32)
-    tol = 1e-6
-    res = ctx.fixed_point(dev(X32), dev(p.W0.astype(np.float32)), tol=tol, max_iter=1000,
-                          traj_iters=8)
-    Br, itr, _, trr, _ = ica.fixed_point(X32.astype(np.float64), p.W0, tol=tol, max_iter=1000,
-                                         traj_iters=8)
+    X64 = X32.astype(np.float64)
+    tol, R = 1e-6, 8
+    W0d = dev(p.W0.astype(np.float32))
+    res = ctx.fixed_point(dev(X32), W0d, tol=tol, max_iter=1000, traj_iters=R)
     tr = host(res["traj"]).astype(np.float64)
-    W, it = host(res["W"]).astype(np.float64), host(res["iters"])
+    it = host(res["iters"])
+    _, itr, _, trr, _ = ica.fixed_point(X64, p.W0, tol=tol, max_iter=1000, traj_iters=R)
+    B0 = ica.normalise_rows(p.W0.astype(np.float32).astype(np.float64))
+    Wg = [B0] + [host(ctx.fixed_point(dev(X32), W0d, tol=tol, max_iter=t)["W"]).astype(np.float64)
+                 for t in range(1, R + 1)]
+    Wo = [B0] + [ica.fixed_point(X64, p.W0, tol=tol, max_iter=t)[0] for t in range(1, R + 1)]
+    K = tr.shape[0]
     # Tolerances (reading of the recorded trajectory): the kurtosis entry is
     # sum z^4 / T - 3 with the fourth-power sum accumulated in FP32 per split,
-    # so its error scales with alpha + 3 (the quantity summed), not with alpha;
-    # the step carries the ~1e-7 absolute noise of FP32 iterates.
-    def close_a(a, ar):
-        return np.abs(a - ar) <= 1e-5 * (np.abs(ar) + 3.0)
-
-    def close_d(d, dr):
-        return np.abs(d - dr) <= 1e-4 * dr + 2e-6
+    # so its error scales with alpha + 3 (the quantity summed); the step is
+    # formed in FP64 from the FP32 row and the new row before it is rounded.
+    for t in range(R):
+        live = it > t                                   # rows updated in pass t+1
+        assert np.array_equal(np.isfinite(tr[:, t, 0]), live), t
+        a_ref = ica.kurtosis(X64, Wg[t][live])
+        assert np.all(np.abs(tr[live, t, 0] - a_ref) <= 1e-5 * (np.abs(a_ref) + 3.0)), t
+        d_ref = np.minimum(np.linalg.norm(Wg[t + 1][live] - Wg[t][live], axis=1),
+                           np.linalg.norm(Wg[t + 1][live] + Wg[t][live], axis=1))
+        assert np.all(np.abs(tr[live, t, 1] - d_ref) <= 1e-6), t
+        G, _ = ica.update(X64, Wg[t][live])
+        Bn = G / np.linalg.norm(G, axis=1, keepdims=True)
+        assert np.all(_rowwise_abs_cos(Wg[t + 1][live], Bn) >= 1 - 1e-10), t
     # every row starts from the same vector: the first recorded kurtosis agrees
-    assert np.all(close_a(tr[:, 0, 0], trr[:, 0, 0]))
-    same = _rowwise_abs_cos(W, Br) >= 1 - 1e-6
-    assert same.mean() >= 0.99
-    for l in np.flatnonzero(same):
-        # a row that ends in the oracle's basin has the oracle's trajectory
-        fin, finr = np.isfinite(tr[l, :, 0]), np.isfinite(trr[l, :, 0])
-        both = fin & finr
-        assert np.all(close_a(tr[l, both, 0], trr[l, both, 0])), l
-        assert np.all(close_d(tr[l, both, 1], trr[l, both, 1])), l
-        if it[l] == itr[l]:
-            assert np.array_equal(fin, finr), l
-        else:
-            # one side stopped a pass earlier: only at a step within the FP32
-            # noise of the threshold
-            assert abs(int(it[l]) - int(itr[l])) == 1, l
-            last = min(int(it[l]), int(itr[l])) - 1
-            if last < tr.shape[1]:
-                assert abs(trr[l, last, 1] - tol) <= 2e-6, l
+    assert np.all(np.abs(tr[:, 0, 0] - trr[:, 0, 0]) <= 1e-5 * (np.abs(trr[:, 0, 0]) + 3.0))
+    # Whole trajectories against the oracle's own run, every row: the entries
+    # may differ by what the measured distance e_t between the GPU's and the
+    # oracle's iterates allows -- steps by e_t + e_{t+1} (triangle inequality),
+    # kurtosis by 4 ||E[y^3 x]|| e_t (its gradient) -- plus the FP32 terms
+    # above.  Rows whose iterates stay together are held to the FP32 terms;
+    # a wandering start amplifies rounding from pass to pass and is held to
+    # the distance its iterates actually drift apart by.
+    e = [np.minimum(np.linalg.norm(Wg[t] - Wo[t], axis=1), np.linalg.norm(Wg[t] + Wo[t], axis=1))
+         for t in range(R + 1)]
+    close = 0
+    for t in range(R):
+        both = np.isfinite(tr[:, t, 0]) & np.isfinite(trr[:, t, 0])
+        G, _ = ica.update(X64, Wo[t][both])
+        lip = 4.0 * np.linalg.norm(G + 3.0 * Wo[t][both], axis=1)
+        a, ar = tr[both, t, 0], trr[both, t, 0]
+        assert np.all(np.abs(a - ar) <= 1.1 * lip * e[t][both] + 1e-5 * (np.abs(ar) + 3.0)), t
+        d, dr = tr[both, t, 1], trr[both, t, 1]
+        assert np.all(np.abs(d - dr) <= e[t][both] + e[t + 1][both] + 1e-6), t
+        close += int(np.sum(e[t + 1][both] <= 1e-6))
+    assert close >= 0.9 * int(np.sum(np.isfinite(trr[:, :, 0])))
+    # where the two sides stop a pass apart, the oracle's step at the earlier
+    # stop lies within the FP32 noise of the threshold
+    for l in np.flatnonzero(it != itr):
+        assert abs(int(it[l]) - int(itr[l])) == 1, l
+        last = min(int(it[l]), int(itr[l])) - 1
+        if last < R:
+            assert abs(trr[l, last, 1] - tol) <= 2e-6 + e[last][l] + e[last + 1][l], l
 
 
 def test_fixed_point_is_deterministic(ctx):
