@@ -238,6 +238,22 @@ int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t
 int oica_kurtosis(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
                   const float *W, double *kurt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kurtosis as oica_kurtosis (same kernels, bitwise the same result), with its
+ * per-split partial sums in a fixed library-owned device array of
+ * OICA_NOALLOC_SCRATCH_BYTES per device (held from library load until the
+ * process ends) instead of the context's workspace.  Allocates nothing and
+ * does not synchronise.  Every call on a device shares that device's array
+ * and overwrites it; calls that overlap on one device (other streams, other
+ * contexts, other host threads) race and must be serialised by the caller.
+ * Nothing needs clearing between calls.  Errors: as oica_kurtosis, plus
+ * OICA_E_UNSUPPORTED when K needs more partial sums than the array holds
+ * (above about two million rows). */
+#define OICA_NOALLOC_SCRATCH_BYTES (16 * 1024 * 1024)
+int oica_kurtosis_noalloc(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
+                          const float *W, double *kurt);
+
 /* ---------------------------------------------------------------------------
  * Learned pruner (an extension beyond the paper, built on its trajectories):
  * a 16 -> 64 -> 64 -> 1 network (ReLU, sigmoid) reads, for the first eight

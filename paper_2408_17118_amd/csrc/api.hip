@@ -9,12 +9,42 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "oica_internal.h"
 
 using namespace oica;
+
+// Fixed device array behind oica_kurtosis_noalloc (per-split partial sums of
+// z^4), for callers that cannot allocate.  Every device the library runs on
+// holds its own copy from module load until the process ends.  Host code
+// never passes the array's name to a kernel: it uses the device address taken
+// once per device below.
+constexpr size_t NOALLOC_DOUBLES = (size_t)OICA_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, which must be current; taken on the
+// first call for that device.
+hipError_t scratch_address(int device, void **out) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
 
 struct oica_ctx {
   int device = 0;
@@ -25,6 +55,7 @@ struct oica_ctx {
   int *small_host = nullptr;   // 64 ints of pinned host memory
   std::vector<hipEvent_t> events;  // start/stop pairs for kernel timing
   std::map<std::string, std::vector<int>> tune;  // batched tile choices: {wk32, wk64, grid}
+  void *scratch = nullptr;     // device address of the fixed noalloc array on `device`
   std::string err;
 };
 
@@ -121,7 +152,8 @@ int oica_create(oica_ctx **out, int device, void *hip_stream) {
   oica_ctx *ctx = new oica_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
-  if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->small_dev, 64 * sizeof(int)) != hipSuccess ||
+  if (hipSetDevice(device) != hipSuccess || scratch_address(device, &ctx->scratch) != hipSuccess ||
+      hipMalloc(&ctx->small_dev, 64 * sizeof(int)) != hipSuccess ||
       hipHostMalloc(&ctx->small_host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     if (ctx->small_dev) (void)hipFree(ctx->small_dev);
@@ -755,6 +787,29 @@ int oica_update(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t
   HIP_TRY(ctx, launch_fused_update(ctx->stream, plan, N, T, Xw, bf16, B, nullptr, nullptr, K, gpart,
                                    s4part, nullptr, 0));
   HIP_TRY(ctx, launch_update_out(ctx->stream, plan, N, T, K, B, gpart, s4part, G, s4));
+  return OICA_OK;
+}
+
+int oica_kurtosis_noalloc(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, int K,
+                          const float *W, double *kurt) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, OICA_E_ARG, "K must be >= 1");
+  if (!Xw_f32 || !W || !kurt) return fail(ctx, OICA_E_ARG, "Xw_f32, W and kurt must be non-null");
+  const FusedPlan plan = make_plan(N, T, K, false);
+  const size_t rows_max = fp_workspace_floats(plan, N, K) / fused_np(N);
+  if (rows_max > NOALLOC_DOUBLES)
+    return fail(ctx, OICA_E_UNSUPPORTED,
+                "K=%d needs %zu partial sums; the fixed array holds %zu (%d bytes)", K, rows_max,
+                NOALLOC_DOUBLES, (int)OICA_NOALLOC_SCRATCH_BYTES);
+  if (!ctx->scratch) return fail(ctx, OICA_E_DEVICE, "no device address for the fixed array");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // every partial sum the second kernel reads is written by the first in this
+  // call, so the array needs no clearing
+  HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan, N, T, Xw_f32, K, W, (double *)ctx->scratch,
+                               kurt));
   return OICA_OK;
 }
 

@@ -98,6 +98,7 @@ _SIGS = {
                                    C.POINTER(FpParams), _P, _P, _P, _P, _P, C.POINTER(FpStats)]),
     "oica_update": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, C.c_int, _P, _P, _P]),
     "oica_kurtosis": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, _P]),
+    "oica_kurtosis_noalloc": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, _P]),
     "oica_fixed_point_batched": (C.c_int, [_P, C.c_int, C.POINTER(Problem), C.c_int,
                                            C.POINTER(FpParams), C.POINTER(BatchParams),
                                            C.POINTER(BatchStats)]),
@@ -353,6 +354,18 @@ class Context:
         K = W.shape[0]
         kurt = torch.empty(K, dtype=torch.float64, device=self._tdev())
         rc = self.lib.oica_kurtosis(self.h, N, T, _ptr(Xw_f32), K, _ptr(W), _ptr(kurt))
+        self._check(rc)
+        return kurt
+
+    def kurtosis_noalloc(self, Xw_f32, W, kurt):
+        """oica_kurtosis_noalloc: the library allocates nothing; the caller passes
+        the output ``kurt`` (K float64 on the device)."""
+        _dev(Xw_f32, "Xw_f32", torch.float32, (None, None))
+        N, T = Xw_f32.shape
+        _dev(W, "W", torch.float32, (None, N))
+        K = W.shape[0]
+        _dev(kurt, "kurt", torch.float64, (K,))
+        rc = self.lib.oica_kurtosis_noalloc(self.h, N, T, _ptr(Xw_f32), K, _ptr(W), _ptr(kurt))
         self._check(rc)
         return kurt
 
