@@ -2,7 +2,11 @@
 fixture.  Calls only the seeded generator and ``oracle/``.
 
 Usage: python tests/golden/make_reference.py eeg_shaped_n64
-       python tests/golden/make_reference.py precision_n128   (about an hour)
+       python tests/golden/make_reference.py precision_n128   (about 40 minutes)
+       python tests/golden/make_reference.py batched_n16_128  (two datasets per
+           padded-dimension class 32/64/96/128 of the 64-dataset workload)
+       python tests/golden/make_reference.py batched_basins   (four datasets,
+           one per class, with enough starts that every basin has >= 6)
 """
 import json
 import os
@@ -22,7 +26,62 @@ WORKLOADS = {
 }
 
 
+def _entry(res, prob, dt, extra):
+    out = {
+        "N": prob.N, "T": prob.T, "K": prob.K, "tol": 1e-10, "max_iter": 1000, "tau": 1e-3,
+        "oracle_seconds": dt, "thread_iters": int(res["thread_iters"]),
+        "status_counts": [int((res["status"] == s).sum()) for s in range(4)],
+        "n_unique": int(len(res["U"])), "n_accepted": int(res["n_accepted"]),
+        "alpha": [float(a) for a in res["alpha"]],
+        "upsilon": [float(u) for u in res["upsilon"]],
+        "size": [int(s) for s in res["size"]],
+        "rep": [int(r) for r in res["rep"]],
+        "U_raw": [[float(v) for v in row] for row in res["U_raw"]],
+    }
+    out.update(extra)
+    return out
+
+
+# Datasets of the many-dataset workload checked against the oracle: the two
+# with the smallest N T in each padded-dimension class (N rounded up to 32).
+def batched_selection(shapes):
+    by_class = {}
+    for d, (N, T, _) in enumerate(shapes):
+        by_class.setdefault((N + 31) // 32 * 32, []).append((N * T, d))
+    return sorted(d for c in sorted(by_class) for _, d in sorted(by_class[c])[:2])
+
+
+# One dataset per padded-dimension class with enough starts for every basin to
+# be reached by at least six of them.
+BASIN_SHAPES = [(20, 20_000, 1024, 300), (40, 20_000, 2048, 301), (80, 20_000, 4096, 302),
+                (110, 20_000, 6144, 303)]
+
+
+def main_many(name):
+    entries = []
+    if name == "batched_n16_128":
+        shapes = synth.batched_shapes()
+        todo = [(d, shapes[d]) for d in batched_selection(shapes)]
+        probs = ((d, synth.batched_problem(N, T, rng)) for d, (N, T, rng) in todo)
+    else:
+        probs = ((d, synth.make_problem(synth.eeg_kinds(N), T=T, K=K, seed=seed))
+                 for d, (N, T, K, seed) in enumerate(BASIN_SHAPES))
+    for d, prob in probs:
+        t0 = time.time()
+        res = ica.ordering_ica(prob.X, prob.W0, tol=1e-10, max_iter=1000, tau=1e-3)
+        dt = time.time() - t0
+        entries.append(_entry(res, prob, dt, {"dataset": d}))
+        print(f"dataset {d}: N={prob.N} T={prob.T} K={prob.K}: {len(res['U'])} clusters, "
+              f"{res['n_accepted']} accepted, smallest {min(res['size'])}, {dt:.1f} s", flush=True)
+    path = os.path.join(HERE, f"{name}_oracle.json")
+    with open(path, "w") as f:
+        json.dump({"workload": name, "datasets": entries}, f, indent=0)
+    print(f"wrote {path}")
+
+
 def main(name):
+    if name in ("batched_n16_128", "batched_basins"):
+        return main_many(name)
     prob = WORKLOADS[name]()
     t0 = time.time()
     res = ica.ordering_ica(prob.X, prob.W0, tol=1e-10, max_iter=1000, tau=1e-3)

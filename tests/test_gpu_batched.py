@@ -14,7 +14,8 @@ pass, through oica_fixed_point_batched.
   in either run is in the other run (|cos| >= 1 - 1e-6, kurtosis within
   1e-5 max(|alpha|, 0.1)), and the accepted counts differ by no more than the
   clusters of size <= 2.
-* Full size: 64 datasets, N in {16..128}, T log-uniform in [2e4, 5e5], K = 1024.
+The full 64-dataset workload and one dataset per padded-dimension class are
+checked against stored oracle runs in test_gpu_batched_oracle.py.
 """
 import numpy as np
 import pytest
@@ -144,41 +145,6 @@ def test_bf16_batched_matches_f32_batched(ctx, small_batch, grouped):
     assert s16["refine_thread_iters"] > 0
     for (p, X32), a, b in zip(probs, o32, o16):
         _compare_stable(ctx, a, b, p.T, f"N={p.N} T={p.T}")
-
-
-@pytest.mark.slow
-def test_full_size_many_datasets(ctx):
-    """64 datasets of the batched workload; three smallest checked against the
-    oracle's unique sets, every dataset's BF16 run against its FP32 run."""
-    from paper_2408_17118_amd import oica
-    shapes = synth.batched_shapes()
-    dev_in, dev16, hosts = [], [], []
-    for N, T, rng in shapes:
-        p = synth.batched_problem(N, T, rng)
-        X = torch.from_numpy(p.X).cuda()
-        Xw, X32, V, mu, eig = ctx.whiten(X, out_dtype=torch.bfloat16)
-        del X
-        dev16.append({"Xw": Xw, "Xw_f32": X32, "W0": torch.from_numpy(p.W0.astype(np.float32)).cuda()})
-        dev_in.append({"Xw": X32, "W0": dev16[-1]["W0"]})
-        hosts.append((p, V))
-    o32, s32 = ctx.fixed_point_batched(dev_in, tol=1e-6, autotune=True)
-    o16, s16 = ctx.fixed_point_batched(dev16, tol=1e-6, precision="bf16", autotune=True)
-    print(f"f32 batched: {s32}\nbf16 batched: {s16}")
-    order = np.argsort([p.N * p.T for p, _ in hosts])
-    for d in range(len(shapes)):
-        p, V = hosts[d]
-        _compare_stable(ctx, o32[d], o16[d], p.T, f"dataset {d} N={p.N} T={p.T}")
-    for d in order[:3]:
-        p, V = hosts[d]
-        ref = ica.ordering_ica(p.X, p.W0, tol=1e-10, max_iter=1000)
-        Ua, aa, na = _unique_raw(ctx, o32[d], p.T)
-        assert na == ref["n_accepted"], (d, na, ref["n_accepted"])
-        R = Ua @ V.cpu().numpy()
-        R /= np.linalg.norm(R, axis=1, keepdims=True)
-        cos = np.abs(R @ ref["U_raw"][:na].T)
-        assert np.all(cos.max(axis=1) >= 1 - 1e-6), d
-        j = cos.argmax(axis=1)
-        assert np.all(np.abs(aa - ref["alpha"][j]) <= 1e-5 * np.maximum(np.abs(ref["alpha"][j]), 0.1))
 
 
 def test_ordering_ica_batched_end_to_end(ctx):
