@@ -341,3 +341,98 @@ def fluctuation(W_runs) -> np.ndarray:
                 acc += 1.0 - abs(float(a @ b)) / (np.linalg.norm(a) * np.linalg.norm(b))
         out[i] = acc / (R * (R - 1))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The deflation driver: the outer loop of Algorithm 2 (Sec. 3.3, eqs. 6-8)
+# ---------------------------------------------------------------------------
+
+def reduce_basis(W: np.ndarray, N: int, rank_tol: float = 1e-12) -> np.ndarray:
+    """Orthonormal basis of the complement of the rows of W (Sec. 3.3).
+
+    F = I_N - W^T W (eq. 6); F~ keeps the first N - i + 1 rows of F, i.e.
+    drops the bottom i - 1 rows, where i - 1 = W.shape[0] components are
+    already estimated; G = (F~ F~^T)^(-1/2) F~ (eq. 7), the inverse square root
+    taken from the eigendecomposition of the symmetric F~ F~^T.  With no
+    component yet (i = 1), G = I_N.  Raises RankError when F~ F~^T is singular
+    (smallest eigenvalue <= rank_tol x largest): the first N - i + 1 rows of F
+    then do not span the complement.
+    """
+    W = np.asarray(W, dtype=np.float64).reshape(-1, N)
+    n_prev = W.shape[0]
+    if n_prev == 0:
+        return np.eye(N)
+    F = np.eye(N) - W.T @ W
+    Ft = F[: N - n_prev]
+    lam, E = np.linalg.eigh(Ft @ Ft.T)
+    if not np.all(np.isfinite(lam)) or lam[0] <= rank_tol * lam[-1] or lam[-1] <= 0:
+        raise RankError(f"F~ F~^T is singular (eigenvalues {lam[0]:.3e} .. {lam[-1]:.3e})")
+    return (E / np.sqrt(lam)) @ E.T @ Ft
+
+
+def deflation(Xw: np.ndarray, W0s, tol: float, max_iter: int, rank_tol: float = 1e-12):
+    """Fast ordering ICA, Algorithm 2: components one at a time.
+
+    For step i = 1, 2, ...: G from the components found so far
+    (``reduce_basis``), X~ = G Xw (eq. 8, an (N - i + 1) x T matrix); the batched
+    fixed point with removal of converged rows from the start rows W0s[i-1]
+    (L x (N - i + 1)); the kurtosis of every converged row on X~; p = the
+    converged row of largest upsilon (lowest row index on ties; if no row
+    converged, every non-degenerate row is a candidate, as in ``unique``).  If
+    upsilon_p is below the Gaussianity threshold of eq. 3 for step i the loop
+    ends; otherwise the row b_p G (a unit vector in the whitened space,
+    orthogonal to the earlier ones) is appended to W.
+
+    Returns (W, steps): W is n x N with the components in the order found;
+    steps holds one dict per step taken (the last one may be the rejected step)
+    with the dimension, p, alpha_p, upsilon_p, the threshold, whether it was
+    accepted, and the fixed point's row updates.
+    """
+    N, T = Xw.shape
+    W = np.zeros((0, N))
+    steps = []
+    for i in range(1, N + 1):
+        G = reduce_basis(W, N, rank_tol)
+        Xt = G @ Xw
+        B, iters, status, _, ti = fixed_point(Xt, W0s[i - 1], tol, max_iter)
+        cand = np.flatnonzero(status == CONV)
+        if cand.size == 0:
+            cand = np.flatnonzero(status != DEGENERATE)
+        alpha = kurtosis(Xt, B[cand])
+        ups = upsilon(alpha)
+        k = int(np.argmax(ups))          # first maximum = lowest row index on ties
+        p = int(cand[k])
+        thr = float(gaussianity_threshold(N, i, T))
+        ok = bool(ups[k] >= thr)
+        steps.append({"i": i, "dim": N - i + 1, "p": p, "alpha": float(alpha[k]),
+                      "upsilon": float(ups[k]), "threshold": thr, "accepted": ok,
+                      "thread_iters": int(ti), "n_conv": int(np.sum(status == CONV))})
+        if not ok:
+            break
+        W = np.vstack([W, B[p] @ G])
+    return W, steps
+
+
+def fastica_projected(Xw: np.ndarray, w0: np.ndarray, E: np.ndarray, tol: float, max_iter: int):
+    """The FastICA function of Algorithm 1 with the projection E = W^T W of the
+    components found so far: w <- w - E w and normalise, then repeatedly
+    y = w^T Xw, w <- Xw y^3 / T - 3 w, w <- w - E w, normalise, until the step
+    test of ``fixed_point`` passes or max_iter passes have run.
+    Returns (w, iters, converged)."""
+    w = np.asarray(w0, dtype=np.float64)
+    w = w - E @ w
+    w = w / math.sqrt(float(w @ w))
+    T = Xw.shape[1]
+    t = 0
+    while True:
+        w_prev = w
+        y = w @ Xw
+        w = (Xw @ (y * y * y)) / T - 3.0 * w
+        w = w - E @ w
+        w = w / math.sqrt(float(w @ w))
+        t += 1
+        step = min(np.linalg.norm(w - w_prev), np.linalg.norm(w + w_prev))
+        if step < tol:
+            return w, t, True
+        if t >= max_iter:
+            return w, t, False

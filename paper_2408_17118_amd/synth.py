@@ -120,6 +120,13 @@ def draw_start(rng: np.random.Generator, K: int, N: int) -> np.ndarray:
     return rng.standard_normal((K, N)).astype(np.float32).astype(np.float64)
 
 
+def draw_deflation_starts(rng: np.random.Generator, L: int, N: int) -> list[np.ndarray]:
+    """Start vectors of the deflation driver: for step i = 1..N an L x (N - i + 1)
+    block of iid N(0,1) values rounded to FP32, drawn step after step from rng
+    (Algorithm 2 draws a fresh random B at every step)."""
+    return [draw_start(rng, L, N - i + 1) for i in range(1, N + 1)]
+
+
 def make_problem(kinds: list[str], T: int, K: int, seed, nu: float = 5.0) -> Problem:
     """Draw A, S and W0 for the given source families from one generator."""
     rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
