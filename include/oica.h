@@ -415,6 +415,48 @@ typedef struct {
 int oica_unique_batched(oica_ctx *ctx, int D, oica_unique_problem *problems,
                         const oica_unique_params *params);
 
+/* ---------------------------------------------------------------------------
+ * The deflation driver: Algorithm 2's outer loop (Sec. 3.3, eqs. 6-8), one
+ * component per step on data reduced to the complement of the components
+ * found so far.
+ *
+ *   for i = 1, 2, ..., N:
+ *     F = I_N - W^T W with its bottom i-1 rows deleted (F~, (N-i+1) x N);
+ *     G = (F~ F~^T)^(-1/2) F~ (at i = 1, G = I);  X~ = G Xw;
+ *     the batched fixed point (as oica_fixed_point, with params) on X~ from
+ *       step i's start rows;  p = the converged row of largest criterion
+ *       (eq. 1; lowest row on ties);
+ *     stop if upsilon_p < 2 (N-i+2)(N-i+1) / T (eq. 3);
+ *     W <- [W; b_p G], the new row normalised in FP64.
+ *
+ * Xw: N x T FP32 whitened data (row stride T).  With params->precision ==
+ * OICA_BF16 every step's X~ is also rounded to BF16 for the BF16 passes.
+ * L: start rows per step.  W0: device FP32, the start rows of every step one
+ * block after the other: step i's block is L x (N - i + 1), row-major, at
+ * element offset L * sum_{k < i} (N - k + 1) (L N (N + 1) / 2 values in all).
+ * tau: the clustering threshold of oica_unique (0 < tau < 1), which picks p.
+ * W_out: device N x N FP64; its first *n_found rows are the components in the
+ * order found (unit rows, orthonormal).  n_found: host.  steps: host array of
+ * N records, nullable; entries past the last step taken are left untouched.
+ * params->pruner must be NULL and traj_iters 0.  Synchronises.
+ * Errors: as oica_fixed_point; OICA_E_RANK when a step's F~ F~^T is singular
+ * (smallest eigenvalue <= 1e-12 x largest). */
+typedef struct {
+  int dim;               /* N - i + 1                                      */
+  int rep;               /* p: the chosen start row of the step            */
+  int accepted;          /* 1: b_p G was appended; 0: eq. 3 ended the loop */
+  int passes;            /* fixed-point passes of the step                 */
+  int64_t thread_iters;  /* row updates of the step (BF16 or FP32)         */
+  int64_t refine_thread_iters; /* FP32 finish row updates (BF16 mode)      */
+  double alpha;          /* kurtosis of row p on X~                        */
+  double upsilon;        /* eq. 1 at alpha                                 */
+  double threshold;      /* eq. 3's right-hand side for step i             */
+} oica_deflation_step;
+
+int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, const float *W0,
+                   const oica_fp_params *params, double tau, double *W_out, int *n_found,
+                   oica_deflation_step *steps);
+
 #ifdef __cplusplus
 }
 #endif

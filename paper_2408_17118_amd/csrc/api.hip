@@ -56,6 +56,8 @@ struct oica_ctx {
   std::vector<hipEvent_t> events;  // start/stop pairs for kernel timing
   std::map<std::string, std::vector<int>> tune;  // batched tile choices: {wk32, wk64, grid}
   void *scratch = nullptr;     // device address of the fixed noalloc array on `device`
+  void *ws2 = nullptr;         // deflation driver's buffers (the calls it makes use ws)
+  size_t ws2_bytes = 0;
   std::string err;
 };
 
@@ -81,24 +83,25 @@ int fail(oica_ctx *ctx, int code, const char *fmt, ...) {
       return fail(ctx, OICA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-int ensure_ws(oica_ctx *ctx, size_t bytes) {
-  if (bytes <= ctx->ws_bytes) return OICA_OK;
+int ensure_buf(oica_ctx *ctx, void **buf, size_t *have, size_t bytes) {
+  if (bytes <= *have) return OICA_OK;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if (ctx->ws) {
+  if (*buf) {
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(ctx, hipFree(ctx->ws));
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
+    HIP_TRY(ctx, hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
   }
   size_t want = bytes + bytes / 4 + (1u << 20);
-  if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+  if (hipMalloc(buf, want) != hipSuccess) {
     (void)hipGetLastError();
-    ctx->ws = nullptr;
+    *buf = nullptr;
     return fail(ctx, OICA_E_NOMEM, "workspace allocation of %zu bytes failed", want);
   }
-  ctx->ws_bytes = want;
+  *have = want;
   return OICA_OK;
 }
+int ensure_ws(oica_ctx *ctx, size_t bytes) { return ensure_buf(ctx, &ctx->ws, &ctx->ws_bytes, bytes); }
 
 struct Carve {
   char *p;
@@ -169,6 +172,7 @@ void oica_destroy(oica_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->ws2) (void)hipFree(ctx->ws2);
   if (ctx->small_dev) (void)hipFree(ctx->small_dev);
   if (ctx->small_host) (void)hipHostFree(ctx->small_host);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -1372,6 +1376,114 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
   *n_accepted = ctx->small_host[3];
   if (cap < *n_unique)
     return fail(ctx, OICA_E_SHAPE, "cap=%d is smaller than the %d clusters found", cap, *n_unique);
+  return OICA_OK;
+}
+
+int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, const float *W0,
+                   const oica_fp_params *params, double tau, double *W_out, int *n_found,
+                   oica_deflation_step *steps) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (L < 1 || L > (1 << 24)) return fail(ctx, OICA_E_ARG, "L must be in [1, 2^24] (got %d)", L);
+  rc = check_fp_params(ctx, params);
+  if (rc) return rc;
+  if (params->pruner) return fail(ctx, OICA_E_ARG, "the deflation driver runs without the pruner");
+  if (params->traj_iters != 0) return fail(ctx, OICA_E_ARG, "traj_iters must be 0");
+  if (!(tau > 0.0 && tau < 1.0)) return fail(ctx, OICA_E_ARG, "tau must be in (0, 1)");
+  if (!Xw || !W0 || !W_out || !n_found) return fail(ctx, OICA_E_ARG, "Xw, W0, W_out and n_found must be non-null");
+  const bool bf16 = params->precision == OICA_BF16;
+  *n_found = 0;
+  // buffers of the driver itself (the calls below use the context workspace)
+  const size_t nn = (size_t)N * N;
+  size_t need = 0;
+  need += (size_t)N * T * 4 + 256;                       // X~ FP32
+  if (bf16) need += (size_t)N * T * 2 + 256;             // X~ BF16
+  need += 5 * (nn * 8 + 256) + (size_t)N * 8 * 2 + 512;  // Ft, C, E (+eigenvalues), G, Wh, mean 0
+  need += jacobi_log_entries(N) * (sizeof(double2) + sizeof(int)) + 512 + 256;
+  need += (size_t)L * N * 4 + 256;                       // fixed-point rows
+  need += (size_t)L * (8 + 4 + 1) + 3 * 256;             // kurt, iters, status
+  need += (size_t)L * (N * 8 + 8 + 8 + 4 + 4) + 5 * 256; // unique outputs (cap L)
+  rc = ensure_buf(ctx, &ctx->ws2, &ctx->ws2_bytes, need);
+  if (rc) return rc;
+  Carve cv{(char *)ctx->ws2};
+  float *xt32 = cv.take<float>((size_t)N * T);
+  uint16_t *xt16 = bf16 ? cv.take<uint16_t>((size_t)N * T) : nullptr;
+  double *Ft = cv.take<double>(nn);
+  double *C = cv.take<double>(nn);
+  double *E = cv.take<double>(nn + N);
+  double *G = cv.take<double>(nn);
+  double *Wh = cv.take<double>(nn);
+  double *zero = cv.take<double>(N);
+  double2 *rot = cv.take<double2>(jacobi_log_entries(N));
+  int *pq = cv.take<int>(jacobi_log_entries(N));
+  int *sweeps = cv.take<int>(64);
+  int *flag = cv.take<int>(64);
+  float *B = cv.take<float>((size_t)L * N);
+  double *kurt = cv.take<double>(L);
+  int32_t *iters = cv.take<int32_t>(L);
+  uint8_t *status = cv.take<uint8_t>(L);
+  double *U = cv.take<double>((size_t)L * N);
+  double *ku = cv.take<double>(L);
+  double *uu = cv.take<double>(L);
+  int32_t *rep = cv.take<int32_t>(L);
+  int32_t *csz = cv.take<int32_t>(L);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemsetAsync(zero, 0, (size_t)N * 8, ctx->stream));
+  size_t w0_off = 0;  // step i's start rows: L x (N - i + 1) after those of steps 1 .. i-1
+  for (int i = 1; i <= N; ++i) {
+    const int n_prev = i - 1, n = N - n_prev;
+    // eqs. 6-8: F = I - W^T W without its bottom i-1 rows, G = (F~ F~^T)^(-1/2) F~,
+    // X~ = G Xw (at i = 1: G = I)
+    HIP_TRY(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+    HIP_TRY(ctx, launch_defl_gram(ctx->stream, N, n_prev, W_out, Ft, C));
+    HIP_TRY(ctx, launch_jacobi(ctx->stream, 1, nullptr, JacJob{n, C, E, rot, pq, sweeps}, n));
+    HIP_TRY(ctx, launch_defl_basis(ctx->stream, N, n_prev, Ft, E, 1e-12, G, Wh, flag));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 8, flag, sizeof(int), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->small_host[8])
+      return fail(ctx, OICA_E_RANK, "step %d: F~ F~^T is singular (the first %d rows of "
+                  "I - W^T W do not span the complement)", i, n);
+    HIP_TRY(ctx, launch_apply_rows(ctx->stream, N, n, T, Xw, T, Wh, zero, xt32, xt16));
+    oica_fp_stats st{};
+    rc = oica_fixed_point(ctx, n, T, bf16 ? (const void *)xt16 : (const void *)xt32,
+                          bf16 ? OICA_BF16 : OICA_F32, xt32, L, W0 + w0_off, params, B, kurt,
+                          iters, status, nullptr, &st);
+    if (rc) return rc;
+    w0_off += (size_t)L * n;
+    // p = argmax of the criterion over the converged rows (lowest row on
+    // ties) with eq. 3's test at step i: the first cluster of oica_unique on
+    // the n-dimensional rows, whose rank-1 threshold is 2(n+1)n/T
+    const oica_unique_params up{tau, 1, 1};
+    int nu = 0, na = 0;
+    rc = oica_unique(ctx, n, T, L, B, kurt, status, &up, L, U, ku, uu, rep, csz, nullptr, &nu, &na);
+    if (rc) return rc;
+    int32_t p = -1;
+    double a = NAN, u = NAN;
+    if (nu > 0) {
+      HIP_TRY(ctx, hipMemcpy(&p, rep, sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpy(&a, ku, sizeof(double), hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpy(&u, uu, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (steps) {
+      oica_deflation_step &s = steps[i - 1];
+      s.dim = n;
+      s.rep = p;
+      s.accepted = na > 0;
+      s.passes = st.passes;
+      s.thread_iters = st.thread_iters;
+      s.refine_thread_iters = st.refine_thread_iters;
+      s.alpha = a;
+      s.upsilon = u;
+      s.threshold = 2.0 * (double)(n + 1) * (double)n / (double)T;
+    }
+    if (na == 0) break;
+    HIP_TRY(ctx, launch_defl_append(ctx->stream, N, n_prev, G, B, rep, W_out));
+    *n_found = i;
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return OICA_OK;
 }
 

@@ -165,6 +165,23 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
                                  int *flags_dev);
 hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
                          int n_max);
+hipError_t launch_apply_rows(hipStream_t st, int N, int n_out, int64_t T, const float *X,
+                             int64_t ld, const double *Wh, const double *mean, float *o32,
+                             uint16_t *obf);
+
+// deflation.hip
+// Reduced basis of the deflation driver for n_prev found components W
+// (n_prev x N FP64): Ft = first N - n_prev rows of I - W^T W and C = Ft Ft^T.
+hipError_t launch_defl_gram(hipStream_t st, int N, int n_prev, const double *W, double *Ft,
+                            double *C);
+// From the eigenpairs E of C (n x n, then n eigenvalues): G = E D^(-1/2) E^T Ft
+// (n x N) and Wh = G padded to N x N with zero rows; flag |= 1 when the
+// smallest eigenvalue is <= rank_tol x the largest.
+hipError_t launch_defl_basis(hipStream_t st, int N, int n_prev, const double *Ft, const double *E,
+                             double rank_tol, double *G, double *Wh, int *flag);
+// W[n_prev] = normalised B[rep[0]] G (B: rows of n = N - n_prev FP32 entries).
+hipError_t launch_defl_append(hipStream_t st, int N, int n_prev, const double *G, const float *B,
+                              const int32_t *rep, double *W);
 hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t, int64_t ld,
                          void *Xw, oica_dtype out_t, float *Xw_f32, double *V_out,
                          double *mean_out, double *eig_out, void *ws, size_t ws_bytes,

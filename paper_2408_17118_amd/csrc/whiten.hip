@@ -64,6 +64,7 @@ struct WJob {
   int *flags;
   float *o32, *o32b;    // FP32 outputs (either may be null)
   uint16_t *obf;        // BF16 output (may be null)
+  int n_out;            // apply: output rows (the first n_out rows of Wh); 0 = N
 };
 
 // Launch-wide ranges: problem d owns work-groups (or waves) [start[d],
@@ -745,6 +746,7 @@ __device__ __forceinline__ void apply_body(const WJob &j, int item, double *lds)
   gf32 *o32 = (gf32 *)j.o32, *o32b = (gf32 *)j.o32b;
   gu16 *obf = (gu16 *)j.obf;
   const int N = j.N;
+  const int n_out = j.n_out > 0 ? j.n_out : N;
   const long long T = j.T;
   const long long ldx = j.ld;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -819,7 +821,7 @@ __device__ __forceinline__ void apply_body(const WJob &j, int item, double *lds)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = rb * 16 + lk + 4 * r;
-          if (i >= N) continue;
+          if (i >= n_out) continue;
           const size_t o = (size_t)i * (size_t)T + (size_t)m;
           const double v = acc[rb][r];
           if (o32) o32[o] = (float)v;
@@ -1022,6 +1024,33 @@ hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_d
   hipError_t e = launch_jacobi(st, 1, nullptr, job, N);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, nullptr, j);
+  if (N <= 64)
+    hipLaunchKernelGGL(k_apply<false>, dim3(apply_tiles(N, T)), dim3(256), apply_prepare<false>(N),
+                       st, nullptr, j, nullptr, 1);
+  else
+    hipLaunchKernelGGL(k_apply<true>, dim3(apply_tiles(N, T)), dim3(256), apply_prepare<true>(N), st,
+                       nullptr, j, nullptr, 1);
+  return hipGetLastError();
+}
+
+// Rows 0 .. n_out-1 of Wh (X - mean) for an N x N FP64 matrix Wh, FP32 data X
+// (row stride ld) and FP64 means (zeros for data already centred): the apply
+// kernel of the whitening with fewer output rows.  Outputs of T samples per
+// row (row stride T): o32 FP32 and/or obf BF16 (either may be null).
+hipError_t launch_apply_rows(hipStream_t st, int N, int n_out, int64_t T, const float *X,
+                             int64_t ld, const double *Wh, const double *mean, float *o32,
+                             uint16_t *obf) {
+  WJob j{};
+  j.X = X;
+  j.f64 = 0;
+  j.N = N;
+  j.T = T;
+  j.ld = ld;
+  j.mean = (double *)mean;
+  j.Wh = (double *)Wh;
+  j.o32 = o32;
+  j.obf = obf;
+  j.n_out = n_out;
   if (N <= 64)
     hipLaunchKernelGGL(k_apply<false>, dim3(apply_tiles(N, T)), dim3(256), apply_prepare<false>(N),
                        st, nullptr, j, nullptr, 1);

@@ -83,6 +83,12 @@ class UniqueParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("gaussianity_test", C.c_int), ("n_top", C.c_int)]
 
 
+class DeflationStep(C.Structure):
+    _fields_ = [("dim", C.c_int), ("rep", C.c_int), ("accepted", C.c_int), ("passes", C.c_int),
+                ("thread_iters", C.c_int64), ("refine_thread_iters", C.c_int64),
+                ("alpha", C.c_double), ("upsilon", C.c_double), ("threshold", C.c_double)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "oica_version": (C.c_int, []),
@@ -116,6 +122,8 @@ _SIGS = {
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
                               C.c_int, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int),
                               C.POINTER(C.c_int)]),
+    "oica_deflation": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.POINTER(FpParams),
+                                 C.c_double, _P, C.POINTER(C.c_int), C.POINTER(DeflationStep)]),
     "oica_unique_batched": (C.c_int, [_P, C.c_int, C.POINTER(UniqueProblem),
                                       C.POINTER(UniqueParams)]),
 }
@@ -369,6 +377,45 @@ class Context:
         self._check(rc)
         return kurt
 
+    # ---- deflation driver (Algorithm 2's outer loop) ------------------------------
+    def deflation(self, Xw, W0_blocks, max_iter=1000, tol=1e-6, precision="f32", tol_bf16=1e-5,
+                  refine_iters=5, tau=1e-3, check_every=4):
+        """Xw: N x T float32 whitened data; W0_blocks: the start rows of every
+        step, step i's block L x (N - i + 1) float32 (a list of N tensors, or
+        one flat device tensor holding them one after the other).  Returns
+        (W: n_found x N float64 device tensor, list of per-step dicts)."""
+        _dev(Xw, "Xw", torch.float32, (None, None))
+        N, T = Xw.shape
+        if isinstance(W0_blocks, (list, tuple)):
+            if len(W0_blocks) != N:
+                raise ValueError(f"W0_blocks must hold {N} blocks, not {len(W0_blocks)}")
+            L = W0_blocks[0].shape[0]
+            for i, b in enumerate(W0_blocks):
+                _dev(b, f"W0_blocks[{i}]", torch.float32, (L, N - i))
+            flat = torch.cat([b.reshape(-1) for b in W0_blocks])
+        else:
+            flat = _dev(W0_blocks, "W0_blocks", torch.float32, (None,))
+            L = flat.numel() // (N * (N + 1) // 2)
+            if L * (N * (N + 1) // 2) != flat.numel() or L < 1:
+                raise ValueError("flat W0_blocks must hold L N (N + 1) / 2 values")
+        W = torch.zeros((N, N), dtype=torch.float64, device=self._tdev())
+        p = FpParams(max_iter, tol, OICA_BF16 if precision == "bf16" else OICA_F32, tol_bf16,
+                     refine_iters, 0, check_every, 0, 1, None, 0, 0, 0)
+        steps = (DeflationStep * N)()
+        n_found = C.c_int(0)
+        rc = self.lib.oica_deflation(self.h, N, T, _ptr(Xw), L, _ptr(flat), C.byref(p), float(tau),
+                                     _ptr(W), C.byref(n_found), steps)
+        self._check(rc)
+        taken = []
+        for i in range(N):
+            st = steps[i]
+            if st.dim == 0:
+                break
+            taken.append({k: getattr(st, k) for k, _ in DeflationStep._fields_})
+            if not st.accepted:
+                break
+        return W[: n_found.value], taken
+
     # ---- a12-a13 ----------------------------------------------------------------
     def unique(self, W, kurt, status, T, tau=1e-3, gaussianity_test=True, n_top=0, cap=None,
                row_cluster=False):
@@ -529,6 +576,20 @@ def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_
                      gaussianity_test=gaussianity_test)
     res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)
     return res
+
+
+def ordering_ica_deflation(ctx: Context, X: torch.Tensor, W0_blocks, tol=1e-6, max_iter=1000,
+                           tau=1e-3, precision="f32", tol_bf16=1e-5, refine_iters=5):
+    """The paper's full method on device-resident raw data: whiten, then the
+    deflation driver (one component per step).  Returns a dict with the
+    components in whitened space (W), in raw-data space (W V, unit rows), the
+    per-step records and the whitening outputs."""
+    Xw, Xw32, V, mean, eig = ctx.whiten(X, out_dtype=torch.float32)
+    W, steps = ctx.deflation(Xw32, W0_blocks, max_iter=max_iter, tol=tol, precision=precision,
+                             tol_bf16=tol_bf16, refine_iters=refine_iters, tau=tau)
+    Wr = W @ V
+    Wr = Wr / torch.linalg.norm(Wr, dim=1, keepdim=True)
+    return {"W": W, "W_raw": Wr, "steps": steps, "V": V, "mean": mean, "eig": eig, "Xw": Xw32}
 
 
 def ordering_ica_batched(ctx: Context, Xs, W0s, tol=1e-6, max_iter=1000, tau=1e-3,

@@ -6,7 +6,9 @@ Usage: python tests/golden/make_reference.py eeg_shaped_n64
        python tests/golden/make_reference.py batched_n16_128  (two datasets per
            padded-dimension class 32/64/96/128 of the 64-dataset workload)
        python tests/golden/make_reference.py batched_basins   (four datasets,
-           one per class, with enough starts that every basin has >= 6)
+           one per padded-dimension class)
+       python tests/golden/make_reference.py deflation_n24 | deflation_eeg_shaped_n64
+           (the deflation driver, Algorithm 2's outer loop)
 """
 import json
 import os
@@ -79,9 +81,38 @@ def main_many(name):
     print(f"wrote {path}")
 
 
+# Deflation driver runs: (data, start-row seed, L).  Both sides get the
+# oracle's whitened data rounded to FP32 and the same start rows of every step.
+DEFLATION = {
+    "deflation_n24": (lambda: synth.make_problem(synth.eeg_kinds(24), T=50_000, K=8, seed=41), 42, 1024),
+    "deflation_eeg_shaped_n64": (lambda: synth.eeg_shaped(), 43, 1024),
+}
+
+
+def main_deflation(name):
+    import numpy as np
+    make, seed, L = DEFLATION[name]
+    prob = make()
+    Xw, *_ = ica.whiten(prob.X)
+    X32 = Xw.astype(np.float32).astype(np.float64)
+    W0s = synth.draw_deflation_starts(np.random.default_rng(seed), L, prob.N)
+    t0 = time.time()
+    W, steps = ica.deflation(X32, W0s, 1e-10, 1000)
+    dt = time.time() - t0
+    out = {"workload": name, "N": prob.N, "T": prob.T, "L": L, "start_seed": seed,
+           "tol": 1e-10, "max_iter": 1000, "oracle_seconds": dt, "n_found": int(W.shape[0]),
+           "steps": steps, "W": [[float(v) for v in row] for row in W]}
+    path = os.path.join(HERE, f"{name}_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+    print(f"wrote {path}: {W.shape[0]} components in {len(steps)} steps, {dt:.1f} s")
+
+
 def main(name):
     if name in ("batched_n16_128", "batched_basins"):
         return main_many(name)
+    if name in DEFLATION:
+        return main_deflation(name)
     prob = WORKLOADS[name]()
     t0 = time.time()
     res = ica.ordering_ica(prob.X, prob.W0, tol=1e-10, max_iter=1000, tau=1e-3)
