@@ -49,7 +49,10 @@ enum {
   OICA_E_NONFINITE = -4,   /* NaN or Inf in the input                        */
   OICA_E_DEVICE = -5,      /* HIP runtime error                              */
   OICA_E_NOMEM = -6,       /* workspace allocation failed                    */
-  OICA_E_UNSUPPORTED = -7  /* size or dtype outside what the kernels handle  */
+  OICA_E_UNSUPPORTED = -7, /* size or dtype outside what the kernels handle  */
+  OICA_E_NOCONV = -8       /* an eigensolver did not converge within its
+                              sweep limit (the Jacobi solves of oica_whiten
+                              and oica_deflation)                          */
 };
 
 /* Per-row outcome of the fixed point (status array). */
@@ -83,6 +86,23 @@ const char *oica_last_error(const oica_ctx *ctx);
 /* Change the stream later calls enqueue on. */
 int oica_set_stream(oica_ctx *ctx, void *hip_stream);
 
+/* Process-wide switches for tests of failure handling (every kernel still
+ * ends normally), and a counter:
+ *   OICA_OPT_COOP_GIVE_UP: value 1 makes every later all-rounds clustering
+ *     launch start with its give-up flag set, so it ends at its first
+ *     exchange and the round-by-round form redoes the clustering from the
+ *     start (the path taken when the work-groups are not all resident and the
+ *     bounded wait gives up).  0 restores normal launches.
+ *   OICA_OPT_JACOBI_MAX_SWEEPS: cap on the Jacobi sweeps of later solves,
+ *     1..30 (0 = 30); a solve still rotating at the cap fails with
+ *     OICA_E_NOCONV.
+ *   OICA_OPT_COOP_FALLBACKS (read only): how many all-rounds clustering
+ *     launches ended in the give-up flag and were redone round by round.
+ * Errors: OICA_E_ARG (unknown option or value out of range). */
+enum { OICA_OPT_COOP_GIVE_UP = 1, OICA_OPT_JACOBI_MAX_SWEEPS = 2, OICA_OPT_COOP_FALLBACKS = 3 };
+int oica_set_option(int option, int value);
+int oica_get_option(int option, int *value);
+
 /* ---------------------------------------------------------------------------
  * Whitening (Sec. 2.2: the observations are whitened before the method runs,
  * so that every unit row w gives a component with zero mean and unit variance,
@@ -102,8 +122,9 @@ int oica_set_stream(oica_ctx *ctx, void *hip_stream);
  * V (N x N), mean (N), eigval (N): FP64 outputs; any may be NULL.
  * Synchronises.  Errors: OICA_E_ARG, OICA_E_SHAPE (ld_raw < T),
  * OICA_E_UNSUPPORTED (N > OICA_MAX_N), OICA_E_NONFINITE (NaN/Inf in X_raw),
- * OICA_E_RANK (smallest eigenvalue <= 1e-12 x largest), OICA_E_NOMEM,
- * OICA_E_DEVICE.
+ * OICA_E_RANK (smallest eigenvalue <= 1e-12 x largest), OICA_E_NOCONV (the
+ * Jacobi solve of the covariance still rotating at its sweep limit),
+ * OICA_E_NOMEM, OICA_E_DEVICE.
  * ------------------------------------------------------------------------- */
 int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype raw_t,
                 int64_t ld_raw, void *Xw, oica_dtype out_t, float *Xw_f32,

@@ -137,6 +137,7 @@ const char *oica_status_string(int status) {
     case OICA_E_DEVICE: return "OICA_E_DEVICE";
     case OICA_E_NOMEM: return "OICA_E_NOMEM";
     case OICA_E_UNSUPPORTED: return "OICA_E_UNSUPPORTED";
+    case OICA_E_NOCONV: return "OICA_E_NOCONV";
     default: return "OICA_E_UNKNOWN";
   }
 }
@@ -212,8 +213,33 @@ int oica_whiten(oica_ctx *ctx, int N, int64_t T, const void *X_raw, oica_dtype r
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   const int flags = ctx->small_host[0];
   if (flags & 1) return fail(ctx, OICA_E_NONFINITE, "X_raw contains NaN or Inf");
+  if (flags & 4) return fail(ctx, OICA_E_NOCONV, "the Jacobi solve of the covariance did not converge");
   if (flags & 2) return fail(ctx, OICA_E_RANK, "covariance is rank deficient (eigenvalue ratio <= 1e-12)");
   return OICA_OK;
+}
+
+int oica_set_option(int option, int value) {
+  switch (option) {
+    case OICA_OPT_COOP_GIVE_UP:
+      if (value != 0 && value != 1) return OICA_E_ARG;
+      set_coop_give_up(value == 1);
+      return OICA_OK;
+    case OICA_OPT_JACOBI_MAX_SWEEPS:
+      if (value < 0 || value > 30) return OICA_E_ARG;
+      set_jacobi_max_sweeps(value == 0 ? 30 : value);
+      return OICA_OK;
+    default:
+      return OICA_E_ARG;
+  }
+}
+
+int oica_get_option(int option, int *value) {
+  if (!value) return OICA_E_ARG;
+  switch (option) {
+    case OICA_OPT_JACOBI_MAX_SWEEPS: *value = jacobi_max_sweeps(); return OICA_OK;
+    case OICA_OPT_COOP_FALLBACKS: *value = coop_fallbacks(); return OICA_OK;
+    default: return OICA_E_ARG;
+  }
 }
 
 int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oica_dtype out_t) {
@@ -254,12 +280,16 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   int first = OICA_OK;
   for (int d = 0; d < D; ++d) {
-    const int st = (hf[d] & 1) ? OICA_E_NONFINITE : (hf[d] & 2) ? OICA_E_RANK : OICA_OK;
+    const int st = (hf[d] & 1)   ? OICA_E_NONFINITE
+                   : (hf[d] & 4) ? OICA_E_NOCONV
+                   : (hf[d] & 2) ? OICA_E_RANK
+                                 : OICA_OK;
     problems[d].status = st;
     if (st != OICA_OK && first == OICA_OK) {
       first = st;
       fail(ctx, st, "problem %d: %s", d,
            st == OICA_E_NONFINITE ? "X_raw contains NaN or Inf"
+           : st == OICA_E_NOCONV  ? "the Jacobi solve of the covariance did not converge"
                                   : "covariance is rank deficient (eigenvalue ratio <= 1e-12)");
     }
   }
@@ -1438,11 +1468,14 @@ int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, cons
     // X~ = G Xw (at i = 1: G = I)
     HIP_TRY(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
     HIP_TRY(ctx, launch_defl_gram(ctx->stream, N, n_prev, W_out, Ft, C));
-    HIP_TRY(ctx, launch_jacobi(ctx->stream, 1, nullptr, JacJob{n, C, E, rot, pq, sweeps}, n));
+    HIP_TRY(ctx, launch_jacobi(ctx->stream, 1, nullptr,
+                               JacJob{n, C, E, rot, pq, sweeps, flag, jacobi_max_sweeps()}, n));
     HIP_TRY(ctx, launch_defl_basis(ctx->stream, N, n_prev, Ft, E, 1e-12, G, Wh, flag));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 8, flag, sizeof(int), hipMemcpyDeviceToHost,
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->small_host[8] & 4)
+      return fail(ctx, OICA_E_NOCONV, "step %d: the Jacobi solve of F~ F~^T did not converge", i);
     if (ctx->small_host[8])
       return fail(ctx, OICA_E_RANK, "step %d: F~ F~^T is singular (the first %d rows of "
                   "I - W^T W do not span the complement)", i, n);

@@ -147,7 +147,14 @@ struct JacJob {        // one symmetric eigenproblem of the Jacobi solver
   double2 *rot;        // rotation log (c, s), jacobi_log_entries(N)
   int *pq;             // rotation log p | q << 16 (q = 0xFFFF: padding index)
   int *sweeps;         // out: sweeps that rotated
+  int *flags;          // nullable: |= 4 when the solve is still rotating at its sweep limit
+  int max_sweeps;      // sweep limit (<= 30)
 };
+// Process-wide test switches (oica_set_option).
+int jacobi_max_sweeps();
+void set_jacobi_max_sweeps(int s);
+void set_coop_give_up(bool on);
+int coop_fallbacks();
 size_t jacobi_log_entries(int N);
 struct WhitenJob {     // one problem of the batched whitening
   int N;

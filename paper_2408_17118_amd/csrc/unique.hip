@@ -9,6 +9,8 @@
 // representatives ranked above it and joins the first that matches, so this
 // is the same partition as the sequential greedy pass.  Each round is one
 // wide kernel (dot products and per-block arg-max) plus a one-block pick.
+#include <atomic>
+
 #include "oica_internal.h"
 
 #include <math.h>
@@ -390,8 +392,9 @@ hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
 // exchange of the per-group arg-maxes through `slots` (two sets, by round
 // parity) behind an arrival counter.  Every work-group reduces the same slots
 // in the same way, so all agree on the next representative.  A wait that
-// exceeds its bound (about half a second) sets done[1] and ends the kernel,
-// reported as a device error.  The dot products are
+// exceeds its bound (about half a second) sets done[1]; every work-group then
+// ends at its next exchange and puts its rows back in their state on entry,
+// and the host redoes the clustering round by round.  The dot products are
 // k_assign's, in the same order, so the partition is identical.
 constexpr int CO_BLOCK = 256;
 constexpr int CO_SPIN_LIMIT = 1 << 24;
@@ -411,7 +414,8 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int l = blockIdx.x * CO_BLOCK + tid;
   const bool have = l < K;
-  int cl = have ? cluster[l] : -2;
+  const int cl0 = have ? cluster[l] : -2;
+  int cl = cl0;
   const double kv = cl == -1 ? key[l] : -INFINITY;
   float row[NP];
 #pragma unroll
@@ -512,12 +516,20 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
     for (int n = tid; n < N; n += CO_BLOCK) lw[n] = (double)W[(size_t)leader * N + n];
     __syncthreads();
   }
-  if (have) cluster[l] = cl;
-  if (blockIdx.x == 0 && tid == 0) {
+  // given up: the rows go back to their state on entry for the round-by-round
+  // form (every work-group has seen done[1] by the time it leaves the loop)
+  const bool gave_up = __hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  if (have) cluster[l] = gave_up ? cl0 : cl;
+  if (blockIdx.x == 0 && tid == 0 && !gave_up) {
     ctl[1] = r + 1;
     ctl[2] = 1;
   }
 }
+
+static std::atomic<int> g_coop_give_up{0};
+static std::atomic<int> g_coop_fallbacks{0};
+void set_coop_give_up(bool on) { g_coop_give_up.store(on ? 1 : 0); }
+int coop_fallbacks() { return g_coop_fallbacks.load(); }
 
 // Launch of k_cluster_coop when every work-group fits on the device at once
 // (the stream is in order, so the device is otherwise free for it);
@@ -544,11 +556,19 @@ static hipError_t launch_cluster_coop(hipStream_t st, int N, int K, const float 
   int *cluster = cw.cluster, *reps = cw.reps;
   CoopSlot *slots = cw.slots;
   unsigned int *done = cw.done;
+  if (g_coop_give_up.load()) {  // test switch: start with the give-up flag set
+    e = hipMemsetAsync(done + 1, 0xFF, sizeof(unsigned int), st);
+    if (e != hipSuccess) return e;
+  }
   void *args[] = {(void *)&K, (void *)&N, (void *)&W, (void *)&key, (void *)&cluster, (void *)&reps,
                   (void *)&tau, (void *)&slots, (void *)&done, (void *)&ctl_dev};
-  e = hipLaunchKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st);
-  if (e == hipSuccess) *launched = true;
-  return e;
+  e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st);
+  if (e != hipSuccess) {  // refused (not all co-resident): the round-by-round form
+    (void)hipGetLastError();
+    return hipSuccess;
+  }
+  *launched = true;
+  return hipSuccess;
 }
 
 // Greedy leader clustering of the candidates (cluster[l] == -1 on entry) in
@@ -582,7 +602,14 @@ hipError_t launch_cluster(hipStream_t st, int N, int K, const float *W, const Cl
       if (e != hipSuccess) return e;
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return e;
-      return flags[1] ? hipErrorLaunchTimeOut : hipSuccess;
+      if (!flags[1]) return hipSuccess;
+      // the bounded wait gave up: redo the clustering round by round from the
+      // rows' state on entry (restored by the kernel)
+      g_coop_fallbacks.fetch_add(1);
+      e = hipMemsetAsync(ctl_dev + 1, 0, 3 * sizeof(int), st);
+      if (e != hipSuccess) return e;
+      e = hipMemsetAsync(cw.done, 0, 2 * sizeof(unsigned int), st);
+      if (e != hipSuccess) return e;
     }
   }
   // round -1: arg-max only; then rounds 0, 1, ... until no candidate is left.

@@ -414,6 +414,9 @@ constexpr int JAC_THREADS = 1024;
 // 2 x 2 blocks per thread and round, at most: npair (npair / 2 + 1) blocks
 constexpr int JAC_UNITS = ((NMAX / 2) * (NMAX / 4 + 1) + JAC_THREADS - 1) / JAC_THREADS;
 constexpr int JAC_MAX_SWEEPS = 30;
+static int g_jacobi_sweeps = JAC_MAX_SWEEPS;
+int jacobi_max_sweeps() { return g_jacobi_sweeps; }
+void set_jacobi_max_sweeps(int s) { g_jacobi_sweeps = s; }
 constexpr double JAC_EPS = 2.220446049250313e-16;
 constexpr int JV_ROWS = 8;       // rows of E per work-group
 constexpr int JV_THREADS = 256;
@@ -462,7 +465,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
   const int H = npair / 2;
   const int units = npair * (H + 1);
   int sweep = 0;
-  for (; sweep < JAC_MAX_SWEEPS && ne > 1; ++sweep) {
+  bool still = false;  // the last sweep run rotated
+  const int limit = jb.max_sweeps;
+  for (; sweep < limit && ne > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < ne - 1; ++r) {
@@ -560,11 +565,15 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
       __syncthreads();
     }
     if (rotated == 0) break;
+    still = sweep + 1 == limit;
     __syncthreads();
   }
   // eigenvalues: the diagonal, stored after E
   for (int i = tid; i < N; i += JAC_THREADS) jb.E[N * N + i] = a[i * LD + i];
-  if (tid == 0) jb.sweeps[0] = sweep;  // sweeps that rotated (all logged)
+  if (tid == 0) {
+    jb.sweeps[0] = sweep;  // sweeps that rotated (all logged)
+    if (still && jb.flags) atomicOr(jb.flags, 4);
+  }
 }
 
 __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__restrict__ jobs,
@@ -1020,7 +1029,7 @@ hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_d
                        nullptr, 1);
   hipLaunchKernelGGL(k_cov_final, dim3((N * N + 3) / 4), dim3(256), 0, st, nullptr, j, nullptr, 1,
                      N * N);
-  const JacJob job{N, b.C, b.E, b.rot, b.pq, b.sweeps};
+  const JacJob job{N, b.C, b.E, b.rot, b.pq, b.sweeps, j.flags, jacobi_max_sweeps()};
   hipError_t e = launch_jacobi(st, 1, nullptr, job, N);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(NMAX), 0, st, nullptr, j);
@@ -1090,7 +1099,8 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
     off = 0;
     for (int d = groups[g]; d < groups[g + 1]; ++d) {
       bufs[d] = carve_bufs(p, jobs[d].N, jobs[d].V, jobs[d].mean, jobs[d].eig);
-      jj[d] = JacJob{jobs[d].N, bufs[d].C, bufs[d].E, bufs[d].rot, bufs[d].pq, bufs[d].sweeps};
+      jj[d] = JacJob{jobs[d].N, bufs[d].C, bufs[d].E, bufs[d].rot, bufs[d].pq, bufs[d].sweeps,
+                     flags_dev + d, jacobi_max_sweeps()};
       double *mp = (double *)(scratch + off);
       double *cp = (double *)(scratch + off + mean_part_bytes(jobs[d].N, jobs[d].T));
       off += stats_scratch_bytes(jobs[d].N, jobs[d].T);

@@ -22,7 +22,9 @@ MAX_N = 128
 ERRORS = {
     0: "OICA_OK", -1: "OICA_E_ARG", -2: "OICA_E_SHAPE", -3: "OICA_E_RANK",
     -4: "OICA_E_NONFINITE", -5: "OICA_E_DEVICE", -6: "OICA_E_NOMEM", -7: "OICA_E_UNSUPPORTED",
+    -8: "OICA_E_NOCONV",
 }
+OPT_COOP_GIVE_UP, OPT_JACOBI_MAX_SWEEPS, OPT_COOP_FALLBACKS = 1, 2, 3
 
 
 class OicaError(RuntimeError):
@@ -122,6 +124,8 @@ _SIGS = {
     "oica_unique": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int, _P, _P, _P, C.POINTER(UniqueParams),
                               C.c_int, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_int),
                               C.POINTER(C.c_int)]),
+    "oica_set_option": (C.c_int, [C.c_int, C.c_int]),
+    "oica_get_option": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
     "oica_deflation": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.POINTER(FpParams),
                                  C.c_double, _P, C.POINTER(C.c_int), C.POINTER(DeflationStep)]),
     "oica_unique_batched": (C.c_int, [_P, C.c_int, C.POINTER(UniqueProblem),
@@ -267,7 +271,7 @@ class Context:
                                    _ptr(V), _ptr(mean), _ptr(eig), 0)
             outs.append((Xw, (Xw if out_dtype == torch.float32 else Xw32), V, mean, eig))
         rc = self.lib.oica_whiten_batched(self.h, D, arr, _DT[out_dtype])
-        if return_status and rc in (-3, -4):
+        if return_status and rc in (-3, -4, -8):
             return outs, [arr[d].status for d in range(D)]
         self._check(rc)
         return (outs, [arr[d].status for d in range(D)]) if return_status else outs
@@ -561,6 +565,21 @@ class Pruner:
                                                        float(lr), int(seed) & (2**64 - 1),
                                                        out.ctypes.data))
         return [float(x) for x in out]
+
+
+def set_option(option: int, value: int) -> None:
+    """oica_set_option: process-wide switches for tests of failure handling."""
+    rc = load().oica_set_option(int(option), int(value))
+    if rc:
+        raise OicaError(rc, f"option {option} = {value}")
+
+
+def get_option(option: int) -> int:
+    v = C.c_int(0)
+    rc = load().oica_get_option(int(option), C.byref(v))
+    if rc:
+        raise OicaError(rc, f"option {option}")
+    return v.value
 
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
