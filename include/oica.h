@@ -71,7 +71,12 @@ int oica_version(void);
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the legacy default stream).  *out (host) receives the
- * handle.  Errors: OICA_E_ARG (out == NULL, device out of range), OICA_E_DEVICE. */
+ * handle.  device == OICA_NO_DEVICE makes a context without a device, which
+ * makes no HIP call: every call on it returns its argument errors as on a
+ * device and OICA_E_DEVICE where device work would begin (input validation on
+ * a host without a GPU).  Errors: OICA_E_ARG (out == NULL, device out of
+ * range), OICA_E_DEVICE. */
+#define OICA_NO_DEVICE (-1)
 int oica_create(oica_ctx **out, int device, void *hip_stream);
 
 /* Destroy a context and free its workspace (synchronises its stream). NULL is a no-op. */

@@ -39,29 +39,41 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [hipcc(), *FLAGS, "-I", INCLUDE, "-c", src, "-o", obj]
+# Host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (device code is built as usual): a separate library for CPU tests of the
+# host-side paths, loaded with the ASan runtime preloaded.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+SAN_OUT = os.path.join(BUILD, "san", "liboica_san.so")
+
+
+def _compile(src: str, san: bool = False) -> str:
+    out_dir = os.path.join(BUILD, "san") if san else BUILD
+    obj = os.path.join(out_dir, os.path.basename(src)[:-4] + ".o")
+    cmd = [hipcc(), *FLAGS, *(SAN_FLAGS if san else []), "-I", INCLUDE, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, san: bool = False) -> str:
+    """Compile every source and link the library; san=True builds the
+    sanitizer-instrumented copy (SAN_OUT) instead."""
+    out_path = SAN_OUT if san else OUT
+    os.makedirs(os.path.dirname(out_path) if san else BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, san), srcs))
+    tmp = out_path + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out_path)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out_path}")
+    return out_path
 
 
 if __name__ == "__main__":

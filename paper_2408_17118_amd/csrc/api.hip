@@ -83,7 +83,14 @@ int fail(oica_ctx *ctx, int code, const char *fmt, ...) {
       return fail(ctx, OICA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Calls on a context without a device stop where device work would begin.
+int device_ready(oica_ctx *ctx) {
+  return ctx->device < 0 ? fail(ctx, OICA_E_DEVICE, "context has no device (argument checks only)")
+                         : OICA_OK;
+}
+
 int ensure_buf(oica_ctx *ctx, void **buf, size_t *have, size_t bytes) {
+  if (int rc = device_ready(ctx)) return rc;
   if (bytes <= *have) return OICA_OK;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (*buf) {
@@ -147,6 +154,12 @@ const char *oica_last_error(const oica_ctx *ctx) { return ctx ? ctx->err.c_str()
 int oica_create(oica_ctx **out, int device, void *hip_stream) {
   if (!out) return OICA_E_ARG;
   *out = nullptr;
+  if (device == OICA_NO_DEVICE) {  // argument checks only: no HIP call at all
+    oica_ctx *ctx = new oica_ctx();
+    ctx->device = OICA_NO_DEVICE;
+    *out = ctx;
+    return OICA_OK;
+  }
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) {
     (void)hipGetLastError();
@@ -170,6 +183,10 @@ int oica_create(oica_ctx **out, int device, void *hip_stream) {
 
 void oica_destroy(oica_ctx *ctx) {
   if (!ctx) return;
+  if (ctx->device < 0) {
+    delete ctx;
+    return;
+  }
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
@@ -653,6 +670,7 @@ int oica_pruner_create(oica_ctx *ctx, const float *init_w, const float *feat_mea
   for (int i = 0; i < 16; ++i)
     if (!(feat_std[i] > 0.f) || !isfinite(feat_std[i]) || !isfinite(feat_mean[i]))
       return fail(ctx, OICA_E_ARG, "feature statistics must be finite with std > 0");
+  if (int rc = device_ready(ctx)) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   oica_pruner *p = new oica_pruner();
   p->device = ctx->device;
@@ -676,6 +694,7 @@ void oica_pruner_destroy(oica_pruner *p) {
 
 int oica_pruner_get_weights(oica_ctx *ctx, const oica_pruner *p, float *host_w) {
   if (!ctx || !p || !host_w) return OICA_E_ARG;
+  if (int rc = device_ready(ctx)) return rc;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   HIP_TRY(ctx, hipMemcpy(host_w, p->st.w32, OICA_PRUNER_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
   return OICA_OK;
@@ -692,6 +711,7 @@ int oica_pruner_predict(oica_ctx *ctx, const oica_pruner *p, const float *traj, 
   if (!ctx || !p) return OICA_E_ARG;
   ctx->err.clear();
   if (!traj || !prob || R < 1) return fail(ctx, OICA_E_ARG, "traj, prob must be non-null and R >= 1");
+  if (int rc = device_ready(ctx)) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, launch_pruner_predict(ctx->stream, &p->st, traj, R, nullptr, nullptr, prob));
   return OICA_OK;
@@ -729,6 +749,8 @@ int oica_pruner_train_step(oica_ctx *ctx, oica_pruner *p, const float *traj, con
   if (!ctx || !p) return OICA_E_ARG;
   ctx->err.clear();
   if (!(lr > 0.f)) return fail(ctx, OICA_E_ARG, "lr must be > 0");
+  if (!traj || !labels || R < 1 || !(w_pos > 0.f))
+    return fail(ctx, OICA_E_ARG, "traj, labels non-null, R >= 1, w_pos > 0 required");
   // gradient goes to the first bytes of the small device buffer region of the
   // workspace tail; keep it separate from the partials
   int rc = ensure_ws(ctx, pruner_grad_workspace_bytes(R) + OICA_PRUNER_PARAMS * 4 + 1024);
@@ -838,6 +860,7 @@ int oica_kurtosis_noalloc(oica_ctx *ctx, int N, int64_t T, const float *Xw_f32, 
     return fail(ctx, OICA_E_UNSUPPORTED,
                 "K=%d needs %zu partial sums; the fixed array holds %zu (%d bytes)", K, rows_max,
                 NOALLOC_DOUBLES, (int)OICA_NOALLOC_SCRATCH_BYTES);
+  if (int rc2 = device_ready(ctx)) return rc2;
   if (!ctx->scratch) return fail(ctx, OICA_E_DEVICE, "no device address for the fixed array");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   // every partial sum the second kernel reads is written by the first in this
