@@ -212,13 +212,16 @@ typedef struct {
                             probability of ending in a top-ranked component
                             is below the pruner's threshold become PRUNED
                             (row and counts kept); after the run, if one of
-                            the top components (the first guard_top
-                            accepted ones and those whose criterion is
-                            within a relative 1e-3 of the guard_top-th) has
-                            fewer than guard_min rows, every pruned row is
-                            resumed from its saved state and finished.     */
+                            the checked components has fewer than guard_min
+                            rows, every pruned row is resumed from its saved
+                            state and finished.  Checked: with guard_top 0,
+                            every accepted component and the cluster where
+                            the eq. 3 walk stopped; with guard_top > 0, the
+                            first guard_top accepted ones and those whose
+                            criterion is within a relative 1e-3 of the
+                            guard_top-th.                                  */
   int prune_pass;        /* pass after which to prune (8..16; 0 = 8)       */
-  int guard_top;         /* components checked by the guard (0 = 20)       */
+  int guard_top;         /* see pruner (0 = every accepted component)      */
   int guard_min;         /* rows each of them must keep (0 = 4)            */
 } oica_fp_params;
 

@@ -438,7 +438,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   if (!bf16 && xw_t != OICA_F32) return fail(ctx, OICA_E_ARG, "F32 precision needs xw_t == OICA_F32");
   const PrunerState *pruner = params->pruner ? &params->pruner->st : nullptr;
   const int prune_pass = params->prune_pass > 0 ? params->prune_pass : 8;
-  const int guard_top = params->guard_top > 0 ? params->guard_top : 20;
+  const int guard_top = params->guard_top;  // 0: every accepted component
   const int guard_min = params->guard_min > 0 ? params->guard_min : 4;
   if (pruner) {
     if (params->pruner->device != ctx->device)
@@ -468,7 +468,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   const size_t gfl = fp_workspace_floats(plan, N, K);
   const int np = fused_np(N);
   const size_t rows_max = gfl / np;
-  const int gcap = guard_top + 64;  // room for components tied with the guard_top-th
+  const int gcap = guard_top > 0 ? guard_top + 64 : K;  // room for the ties / every cluster
   size_t need = 0;
   need += gfl * sizeof(float) + 256;            // gpart
   need += rows_max * sizeof(float) + 256;       // s4part
@@ -617,13 +617,15 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
       HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan_f32(), N, T, X32p, K, W_out,
                                    s4part64, kurt));
     if (!(prune_now && pruned > 0)) break;
-    // guard: every one of the first guard_top accepted components must keep
-    // guard_min rows in the pruned run, else the pruned rows are resumed
+    // guard: every checked component must keep guard_min rows in the pruned
+    // run, else the pruned rows are resumed
     HIP_TRY(ctx, hipMemsetAsync(ctx->small_dev, 0, 64 * sizeof(int), ctx->stream));
     HIP_TRY(ctx, launch_unique(ctx->stream, N, T, K, W_out, kurt, status, 1e-3, 1, 0, gcap, gU, gk,
                                gu, grep, gsize, gwork, ctx->small_host, ctx->small_dev));
     const int n_acc = ctx->small_host[3];
-    const int n_got = n_acc < gcap ? n_acc : gcap;
+    const int n_uni = ctx->small_host[1];
+    const int n_need = guard_top > 0 ? n_acc : std::min(n_uni, n_acc + 1);
+    const int n_got = n_need < gcap ? n_need : gcap;
     std::vector<int32_t> sizes(gcap);
     std::vector<double> ups(gcap);
     if (n_got > 0) {
@@ -631,13 +633,19 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
                              hipMemcpyDeviceToHost));
       HIP_TRY(ctx, hipMemcpy(ups.data(), gu, (size_t)n_got * sizeof(double), hipMemcpyDeviceToHost));
     }
-    // the top components: the first guard_top accepted ones and every accepted
-    // one whose criterion is within a relative 1e-3 of the guard_top-th (ties)
+    // guard_top > 0: the top components, the first guard_top accepted ones and
+    // every accepted one whose criterion is within a relative 1e-3 of the
+    // guard_top-th (ties).  guard_top == 0: every accepted component and the
+    // cluster where the eq. 3 walk stopped.
     bool ok = true;
     if (n_got > 0) {
-      const double cut = ups[(guard_top < n_got ? guard_top : n_got) - 1];
-      for (int r = 0; r < n_got; ++r)
-        if (r < guard_top || ups[r] >= cut - 1e-3 * fabs(cut)) ok &= sizes[r] >= guard_min;
+      if (guard_top > 0) {
+        const double cut = ups[(guard_top < n_got ? guard_top : n_got) - 1];
+        for (int r = 0; r < n_got; ++r)
+          if (r < guard_top || ups[r] >= cut - 1e-3 * fabs(cut)) ok &= sizes[r] >= guard_min;
+      } else {
+        for (int r = 0; r < n_got; ++r) ok &= sizes[r] >= guard_min;
+      }
     }
     if (ok) break;
     tripped = 1;

@@ -279,7 +279,7 @@ class Context:
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
                     tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
-                    refine_groups=True, pruner=None, prune_pass=8, guard_top=20, guard_min=4):
+                    refine_groups=True, pruner=None, prune_pass=8, guard_top=0, guard_min=4):
         _dev(Xw, "Xw", torch.bfloat16 if precision == "bf16" else torch.float32, (None, None))
         N, T = Xw.shape
         _dev(W0, "W0", torch.float32, (None, N))

@@ -5,11 +5,16 @@ training nor for calibration).
 For each dataset three GPU runs from the same data and start vectors:
   plain FP32, BF16 + FP32 finish without the pruner, BF16 + FP32 finish with
   the pruner (model shipped in paper_2408_17118_amd/pruner_model.json).
-Required: the top components (the first 20 accepted ones and those tied with
-the 20th) of the pruned run are those of the plain FP32 run (|cos| >= 1 - 1e-6,
-kurtosis within 1e-5 max(|alpha|, 0.1)); the pruner removes rows and the pruned
-run needs fewer thread-iterations than the unpruned BF16 run (unless the guard
-resumed the pruned rows).  Timings and counts are printed (pytest -s).
+Required: the pruned run's whole unique set is the unpruned BF16 run's (the
+same counts, every cluster at |cos| >= 1 - 1e-6, kurtosis within 1e-5
+max(|alpha|, 0.1), the same order up to near-equal criterion values), and its
+top components (the first 20 accepted ones and those tied with the 20th) are
+those of the plain FP32 run; the pruner removes rows and, unless the guard
+resumed them, saves at least 1 % of the unpruned run's thread-iterations.
+Pruning after pass 8 can save at most the row updates of passes 9 on (8-10 %
+of them here); timings are printed (pytest -s), not asserted: the guard's
+clustering costs about what the saved row updates would, so the pruned run is
+not faster at this size.
 """
 import json
 import os
@@ -78,6 +83,23 @@ def test_pruned_run_keeps_top_components_and_saves_work(seed):
     assert np.all(np.abs(aa - ab[j]) <= 1e-5 * np.maximum(np.abs(aa), 0.1))
     assert fp["pruned"] > 0
     if not fp["guard_tripped"]:
-        assert fp["thread_iters"] < b16["fp"]["thread_iters"]
+        assert fp["thread_iters"] <= 0.99 * b16["fp"]["thread_iters"]
+    # the whole unique set equals the unpruned BF16 run's
+    nb, nq = b16["n_unique"], prn["n_unique"]
+    assert nb == nq and b16["n_accepted"] == prn["n_accepted"]
+    Rb = b16["U"].cpu().numpy()[:nb] @ b16["V"].cpu().numpy()
+    Rq = prn["U"].cpu().numpy()[:nq] @ prn["V"].cpu().numpy()
+    Rb /= np.linalg.norm(Rb, axis=1, keepdims=True)
+    Rq /= np.linalg.norm(Rq, axis=1, keepdims=True)
+    c2 = np.abs(Rb @ Rq.T)
+    assert np.all(c2.max(axis=1) >= 1 - 1e-6)
+    m2 = c2.argmax(axis=1)
+    assert len(set(m2.tolist())) == nb
+    ab_, aq_ = b16["alpha"].cpu().numpy()[:nb], prn["alpha"].cpu().numpy()[:nq]
+    assert np.all(np.abs(ab_ - aq_[m2]) <= 1e-5 * np.maximum(np.abs(ab_), 0.1))
+    ub_ = b16["upsilon"].cpu().numpy()[:nb]
+    for k in range(nb):
+        if m2[k] != k:
+            assert abs(ub_[m2[k]] - ub_[k]) <= 1e-5 * max(ub_[k], 1e-3)
     pr.close()
     ctx.close()
