@@ -455,7 +455,8 @@ int oica_unique_batched(oica_ctx *ctx, int D, oica_unique_problem *problems,
  *     the batched fixed point (as oica_fixed_point, with params) on X~ from
  *       step i's start rows;  p = the converged row of largest criterion
  *       (eq. 1; lowest row on ties);
- *     stop if upsilon_p < 2 (N-i+2)(N-i+1) / T (eq. 3);
+ *     stop if upsilon_p < 2 (N-i+2)(N-i+1) / T (eq. 3; only with
+ *       gaussianity_test != 0, else all N steps run);
  *     W <- [W; b_p G], the new row normalised in FP64.
  *
  * Xw: N x T FP32 whitened data (row stride T).  With params->precision ==
@@ -483,8 +484,8 @@ typedef struct {
 } oica_deflation_step;
 
 int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, const float *W0,
-                   const oica_fp_params *params, double tau, double *W_out, int *n_found,
-                   oica_deflation_step *steps);
+                   const oica_fp_params *params, double tau, int gaussianity_test, double *W_out,
+                   int *n_found, oica_deflation_step *steps);
 
 #ifdef __cplusplus
 }

@@ -370,7 +370,8 @@ def reduce_basis(W: np.ndarray, N: int, rank_tol: float = 1e-12) -> np.ndarray:
     return (E / np.sqrt(lam)) @ E.T @ Ft
 
 
-def deflation(Xw: np.ndarray, W0s, tol: float, max_iter: int, rank_tol: float = 1e-12):
+def deflation(Xw: np.ndarray, W0s, tol: float, max_iter: int, rank_tol: float = 1e-12,
+              gaussianity_test: bool = True):
     """Fast ordering ICA, Algorithm 2: components one at a time.
 
     For step i = 1, 2, ...: G from the components found so far
@@ -380,8 +381,10 @@ def deflation(Xw: np.ndarray, W0s, tol: float, max_iter: int, rank_tol: float = 
     converged row of largest upsilon (lowest row index on ties; if no row
     converged, every non-degenerate row is a candidate, as in ``unique``).  If
     upsilon_p is below the Gaussianity threshold of eq. 3 for step i the loop
-    ends; otherwise the row b_p G (a unit vector in the whitened space,
-    orthogonal to the earlier ones) is appended to W.
+    ends (without the test, as in the EEG experiment of Sec. 4.3, all N steps
+    run); otherwise the row b_p G (a unit vector in the whitened space,
+    orthogonal to the earlier ones), re-orthogonalised against them to undo
+    the rounding of eqs. 6-7, is appended to W.
 
     Returns (W, steps): W is n x N with the components in the order found;
     steps holds one dict per step taken (the last one may be the rejected step)
@@ -403,13 +406,21 @@ def deflation(Xw: np.ndarray, W0s, tol: float, max_iter: int, rank_tol: float = 
         k = int(np.argmax(ups))          # first maximum = lowest row index on ties
         p = int(cand[k])
         thr = float(gaussianity_threshold(N, i, T))
-        ok = bool(ups[k] >= thr)
+        ok = bool(ups[k] >= thr) or not gaussianity_test
         steps.append({"i": i, "dim": N - i + 1, "p": p, "alpha": float(alpha[k]),
                       "upsilon": float(ups[k]), "threshold": thr, "accepted": ok,
                       "thread_iters": int(ti), "n_conv": int(np.sum(status == CONV))})
         if not ok:
             break
-        W = np.vstack([W, B[p] @ G])
+        # b_p G is orthogonal to the rows of W in exact arithmetic; evaluated
+        # as printed, the rounding of F~ and of the inverse square root
+        # compounds from step to step (the rows of X~ must stay orthonormal to
+        # the estimated components), so the row is orthogonalised against W
+        # twice (classical Gram-Schmidt) before it is normalised
+        w = B[p] @ G
+        for _ in range(2):
+            w = w - W.T @ (W @ w)
+        W = np.vstack([W, w / np.linalg.norm(w)])
     return W, steps
 
 

@@ -1441,8 +1441,8 @@ int oica_unique(oica_ctx *ctx, int N, int64_t T, int K, const float *W, const do
 }
 
 int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, const float *W0,
-                   const oica_fp_params *params, double tau, double *W_out, int *n_found,
-                   oica_deflation_step *steps) {
+                   const oica_fp_params *params, double tau, int gaussianity_test, double *W_out,
+                   int *n_found, oica_deflation_step *steps) {
   if (!ctx) return OICA_E_ARG;
   ctx->err.clear();
   int rc = check_dims(ctx, N, T);
@@ -1520,7 +1520,7 @@ int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, cons
     // p = argmax of the criterion over the converged rows (lowest row on
     // ties) with eq. 3's test at step i: the first cluster of oica_unique on
     // the n-dimensional rows, whose rank-1 threshold is 2(n+1)n/T
-    const oica_unique_params up{tau, 1, 1};
+    const oica_unique_params up{tau, gaussianity_test ? 1 : 0, 1};
     int nu = 0, na = 0;
     rc = oica_unique(ctx, n, T, L, B, kurt, status, &up, L, U, ku, uu, rep, csz, nullptr, &nu, &na);
     if (rc) return rc;

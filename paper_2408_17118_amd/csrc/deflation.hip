@@ -86,8 +86,10 @@ __global__ __launch_bounds__(DT) void k_defl_basis(int N, int n_prev, const doub
   }
 }
 
-// w = B[p] G in FP64 (b_p held in FP32), normalised so the rows of W stay
-// orthonormal to FP64 rounding; one wave.
+// w = B[p] G in FP64 (b_p held in FP32), orthogonalised against the earlier
+// rows twice (classical Gram-Schmidt) and normalised: b_p G is orthogonal to
+// them in exact arithmetic, but the rounding of F~ and of the inverse square
+// root would otherwise compound from step to step.  One wave.
 __global__ __launch_bounds__(64) void k_defl_append(int N, int n_prev, const double *__restrict__ G,
                                                     const float *__restrict__ B,
                                                     const int32_t *__restrict__ rep,
@@ -101,6 +103,27 @@ __global__ __launch_bounds__(64) void k_defl_append(int N, int n_prev, const dou
     const double b = (double)B[(size_t)p * n + a];
     if (j0 < N) w0 = fma(b, G[a * N + j0], w0);
     if (j1 < N) w1 = fma(b, G[a * N + j1], w1);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    // coefficients against every earlier row, then one subtraction
+    double c0 = 0.0, c1 = 0.0;  // lanes hold rows k = lane and lane + 64
+    for (int k = 0; k < n_prev; ++k) {
+      double d = 0.0;
+      if (j0 < N) d = fma(W[(size_t)k * N + j0], w0, d);
+      if (j1 < N) d = fma(W[(size_t)k * N + j1], w1, d);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
+      if (k == lane) c0 = d;
+      if (k == lane + 64) c1 = d;
+    }
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < n_prev; ++k) {
+      const double ck = k < 64 ? __shfl(c0, k) : __shfl(c1, k - 64);
+      if (j0 < N) s0 = fma(ck, W[(size_t)k * N + j0], s0);
+      if (j1 < N) s1 = fma(ck, W[(size_t)k * N + j1], s1);
+    }
+    w0 -= s0;
+    w1 -= s1;
   }
   double ss = w0 * w0 + w1 * w1;
 #pragma unroll

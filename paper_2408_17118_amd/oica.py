@@ -127,7 +127,8 @@ _SIGS = {
     "oica_set_option": (C.c_int, [C.c_int, C.c_int]),
     "oica_get_option": (C.c_int, [C.c_int, C.POINTER(C.c_int)]),
     "oica_deflation": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.POINTER(FpParams),
-                                 C.c_double, _P, C.POINTER(C.c_int), C.POINTER(DeflationStep)]),
+                                 C.c_double, C.c_int, _P, C.POINTER(C.c_int),
+                                 C.POINTER(DeflationStep)]),
     "oica_unique_batched": (C.c_int, [_P, C.c_int, C.POINTER(UniqueProblem),
                                       C.POINTER(UniqueParams)]),
 }
@@ -383,7 +384,7 @@ class Context:
 
     # ---- deflation driver (Algorithm 2's outer loop) ------------------------------
     def deflation(self, Xw, W0_blocks, max_iter=1000, tol=1e-6, precision="f32", tol_bf16=1e-5,
-                  refine_iters=5, tau=1e-3, check_every=4):
+                  refine_iters=5, tau=1e-3, check_every=4, gaussianity_test=True):
         """Xw: N x T float32 whitened data; W0_blocks: the start rows of every
         step, step i's block L x (N - i + 1) float32 (a list of N tensors, or
         one flat device tensor holding them one after the other).  Returns
@@ -408,7 +409,7 @@ class Context:
         steps = (DeflationStep * N)()
         n_found = C.c_int(0)
         rc = self.lib.oica_deflation(self.h, N, T, _ptr(Xw), L, _ptr(flat), C.byref(p), float(tau),
-                                     _ptr(W), C.byref(n_found), steps)
+                                     1 if gaussianity_test else 0, _ptr(W), C.byref(n_found), steps)
         self._check(rc)
         taken = []
         for i in range(N):

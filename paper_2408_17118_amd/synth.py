@@ -120,6 +120,47 @@ def draw_start(rng: np.random.Generator, K: int, N: int) -> np.ndarray:
     return rng.standard_normal((K, N)).astype(np.float32).astype(np.float64)
 
 
+# ---------------------------------------------------------------------------
+# Generalised Gaussian sources (the paper's artificial datasets, Sec. 4.2).
+# ---------------------------------------------------------------------------
+
+def gg_rhos(n_pos: int = 10, n_neg: int = 10) -> list[float]:
+    """Shape parameters rho = 2 * 2^(i/4): i = -n_pos .. -1 (rho < 2, positive
+    kurtosis) then i = 1 .. n_neg (rho > 2, negative kurtosis)."""
+    return [2.0 * 2.0 ** (i / 4.0) for i in list(range(-n_pos, 0)) + list(range(1, n_neg + 1))]
+
+
+def draw_gg(rng: np.random.Generator, rho: float, T: int) -> np.ndarray:
+    """T samples of the generalised Gaussian with density proportional to
+    exp(-(|u| / beta)^rho), beta chosen for unit variance: |u| / beta is
+    G^(1/rho) with G ~ Gamma(1/rho, 1), with a random sign; the variance of
+    G^(1/rho) is Gamma(3/rho) / Gamma(1/rho)."""
+    g = rng.gamma(1.0 / rho, 1.0, T)
+    sign = np.where(rng.random(T) < 0.5, -1.0, 1.0)
+    scale = math.sqrt(math.gamma(1.0 / rho) / math.gamma(3.0 / rho))
+    return sign * g ** (1.0 / rho) * scale
+
+
+def artificial_gg(seed, n_gauss: int = 0, T: int = 10_000, K: int = 1) -> Problem:
+    """The paper's artificial datasets: the 20 generalised Gaussian sources of
+    ``gg_rhos`` (in that order) plus n_gauss N(0, 1) sources (0 for the first
+    experiment, N = 20; 10 for the second, N = 30); A iid N(0, 1).  Draw order:
+    A, the sources in order, W0 (K x N)."""
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    rhos = gg_rhos()
+    N = len(rhos) + n_gauss
+    A = rng.standard_normal((N, N))
+    S = np.empty((N, T))
+    for i, rho in enumerate(rhos):
+        S[i] = draw_gg(rng, rho, T)
+    for i in range(len(rhos), N):
+        S[i] = rng.standard_normal(T)
+    W0 = draw_start(rng, K, N)
+    return Problem(X=A @ S, A=A, S=S, W0=W0,
+                   kinds=[f"gg{r:.4f}" for r in rhos] + ["gaussian"] * n_gauss, seed=seed,
+                   meta={"rhos": rhos, "T": T, "K": K})
+
+
 def draw_deflation_starts(rng: np.random.Generator, L: int, N: int) -> list[np.ndarray]:
     """Start vectors of the deflation driver: for step i = 1..N an L x (N - i + 1)
     block of iid N(0,1) values rounded to FP32, drawn step after step from rng

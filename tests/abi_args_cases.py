@@ -176,7 +176,7 @@ def run(lib):
 
     def dfl(N=8, L=16, tau=1e-3, p=None, W0=P, Wout=P):
         prm = p if p is not None else fp()
-        return lib.oica_deflation(ctx, N, 100, P, L, W0, C.byref(prm), tau, Wout, C.byref(nf), steps)
+        return lib.oica_deflation(ctx, N, 100, P, L, W0, C.byref(prm), tau, 1, Wout, C.byref(nf), steps)
     expect("deflation L", dfl(L=0), E_ARG)
     expect("deflation tau", dfl(tau=1.5), E_ARG)
     expect("deflation traj", dfl(p=fp(traj_iters=2)), E_ARG)

@@ -54,6 +54,22 @@ def test_components_orthonormal(small):
     assert np.max(np.abs(W @ W.T - np.eye(W.shape[0]))) < 1e-12
 
 
+def test_orthonormal_over_many_steps():
+    # sixteen steps on the EEG-shaped family mix: the components stay
+    # orthonormal to FP64 rounding (the appended rows are re-orthogonalised),
+    # and every step's basis is orthonormal and orthogonal to them
+    p = synth.make_problem(synth.eeg_kinds(16), T=20_000, K=4, seed=12)
+    Xw, *_ = ica.whiten(p.X)
+    W0s = synth.draw_deflation_starts(np.random.default_rng(13), 128, p.N)
+    W, steps = ica.deflation(Xw, W0s, 1e-10, 1000, gaussianity_test=False)
+    assert W.shape == (16, 16) and len(steps) == 16
+    assert np.max(np.abs(W @ W.T - np.eye(16))) < 1e-13
+    for k in range(1, 16):
+        G = ica.reduce_basis(W[:k], 16)
+        assert np.max(np.abs(W[:k] @ G.T)) < 1e-11
+        assert np.max(np.abs(G @ G.T - np.eye(16 - k))) < 1e-8
+
+
 def test_step_equals_projected_fastica(small):
     # step 3: the reduced fixed point mapped back equals Algorithm 1's
     # projected FastICA from the same start, row by row

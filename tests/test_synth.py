@@ -69,3 +69,30 @@ def test_batched_shapes():
     assert all(20_000 <= t <= 500_000 for t in Ts)
     again = synth.batched_shapes()
     assert [(n, t) for n, t, _ in again] == list(zip(Ns, Ts))
+
+
+@pytest.mark.parametrize("rho", [2 * 2 ** (-10 / 4), 2 * 2 ** (-3 / 4), 2 * 2 ** (1 / 4), 2 * 2 ** (10 / 4)])
+def test_generalized_gaussian_moments(rho):
+    # kurtosis of the generalised Gaussian: G(5/rho) G(1/rho) / G(3/rho)^2 - 3
+    # (rho = 1: Laplace, 3; rho = 2: Gaussian, 0; rho -> inf: uniform, -1.2),
+    # checked within 5 standard errors, and unit variance
+    g = math.gamma
+    kap = g(5 / rho) * g(1 / rho) / g(3 / rho) ** 2 - 3
+    rng = np.random.default_rng(17)
+    T = 400_000
+    s = synth.draw_gg(rng, rho, T)
+    assert abs(s.var() - 1.0) < 5 * np.std(s ** 2) / math.sqrt(T)
+    se = np.std(s ** 4) / math.sqrt(T)
+    assert abs(_excess_kurtosis(s) - kap) < 5 * se + 1e-3
+
+
+def test_generalized_gaussian_reference_points():
+    g = math.gamma
+    kap = lambda r: g(5 / r) * g(1 / r) / g(3 / r) ** 2 - 3   # noqa: E731
+    assert kap(1.0) == pytest.approx(3.0)                      # Laplace
+    assert kap(2.0) == pytest.approx(0.0, abs=1e-12)           # Gaussian
+    assert kap(8.0) == pytest.approx(-1.0766, abs=1e-4)
+    rhos = synth.gg_rhos()
+    assert len(rhos) == 20 and sum(r < 2 for r in rhos) == 10 and sum(r > 2 for r in rhos) == 10
+    p = synth.artificial_gg(0, n_gauss=10)
+    assert p.N == 30 and p.T == 10_000 and p.kinds[-10:] == ["gaussian"] * 10
