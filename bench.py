@@ -85,6 +85,9 @@ def parse():
                     help="skip the comparison runs of the other precision forms (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--plain-coop-launch", action="store_true",
+                    help="launch the all-rounds clustering without the cooperative-launch API "
+                         "(profiling runs: the same kernel, a launch the profiler follows)")
     return ap.parse_args()
 
 
@@ -165,6 +168,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.plain_coop_launch:
+        oica.set_option(oica.OPT_COOP_LAUNCH_API, 0)
     if args.workload == "batched_n16_128":
         return bench_batched(args)
     dev = torch.device("cuda", 0)

@@ -103,8 +103,14 @@ int oica_set_stream(oica_ctx *ctx, void *hip_stream);
  *     OICA_E_NOCONV.
  *   OICA_OPT_COOP_FALLBACKS (read only): how many all-rounds clustering
  *     launches ended in the give-up flag and were redone round by round.
+ *   OICA_OPT_COOP_LAUNCH_API: 1 (default) launches the all-rounds clustering
+ *     with hipLaunchCooperativeKernel (refused when its work-groups cannot
+ *     all be resident: the round-by-round form runs instead); 0 uses a plain
+ *     launch after the same occupancy check (for tools that do not follow
+ *     cooperative launches; the bounded wait still covers residency).
  * Errors: OICA_E_ARG (unknown option or value out of range). */
-enum { OICA_OPT_COOP_GIVE_UP = 1, OICA_OPT_JACOBI_MAX_SWEEPS = 2, OICA_OPT_COOP_FALLBACKS = 3 };
+enum { OICA_OPT_COOP_GIVE_UP = 1, OICA_OPT_JACOBI_MAX_SWEEPS = 2, OICA_OPT_COOP_FALLBACKS = 3,
+       OICA_OPT_COOP_LAUNCH_API = 4 };
 int oica_set_option(int option, int value);
 int oica_get_option(int option, int *value);
 

@@ -245,6 +245,10 @@ int oica_set_option(int option, int value) {
       if (value < 0 || value > 30) return OICA_E_ARG;
       set_jacobi_max_sweeps(value == 0 ? 30 : value);
       return OICA_OK;
+    case OICA_OPT_COOP_LAUNCH_API:
+      if (value != 0 && value != 1) return OICA_E_ARG;
+      set_coop_launch_api(value == 1);
+      return OICA_OK;
     default:
       return OICA_E_ARG;
   }
@@ -255,6 +259,7 @@ int oica_get_option(int option, int *value) {
   switch (option) {
     case OICA_OPT_JACOBI_MAX_SWEEPS: *value = jacobi_max_sweeps(); return OICA_OK;
     case OICA_OPT_COOP_FALLBACKS: *value = coop_fallbacks(); return OICA_OK;
+    case OICA_OPT_COOP_LAUNCH_API: *value = coop_launch_api(); return OICA_OK;
     default: return OICA_E_ARG;
   }
 }

@@ -154,6 +154,8 @@ struct JacJob {        // one symmetric eigenproblem of the Jacobi solver
 int jacobi_max_sweeps();
 void set_jacobi_max_sweeps(int s);
 void set_coop_give_up(bool on);
+void set_coop_launch_api(bool on);
+int coop_launch_api();
 int coop_fallbacks();
 size_t jacobi_log_entries(int N);
 struct WhitenJob {     // one problem of the batched whitening

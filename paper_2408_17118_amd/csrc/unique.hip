@@ -528,7 +528,10 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
 
 static std::atomic<int> g_coop_give_up{0};
 static std::atomic<int> g_coop_fallbacks{0};
+static std::atomic<int> g_coop_api{1};
 void set_coop_give_up(bool on) { g_coop_give_up.store(on ? 1 : 0); }
+void set_coop_launch_api(bool on) { g_coop_api.store(on ? 1 : 0); }
+int coop_launch_api() { return g_coop_api.load(); }
 int coop_fallbacks() { return g_coop_fallbacks.load(); }
 
 // Launch of k_cluster_coop when every work-group fits on the device at once
@@ -562,7 +565,8 @@ static hipError_t launch_cluster_coop(hipStream_t st, int N, int K, const float 
   }
   void *args[] = {(void *)&K, (void *)&N, (void *)&W, (void *)&key, (void *)&cluster, (void *)&reps,
                   (void *)&tau, (void *)&slots, (void *)&done, (void *)&ctl_dev};
-  e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st);
+  e = g_coop_api.load() ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st)
+                        : hipLaunchKernel(fn, dim3(grid), dim3(CO_BLOCK), args, 0, st);
   if (e != hipSuccess) {  // refused (not all co-resident): the round-by-round form
     (void)hipGetLastError();
     return hipSuccess;

@@ -24,7 +24,7 @@ ERRORS = {
     -4: "OICA_E_NONFINITE", -5: "OICA_E_DEVICE", -6: "OICA_E_NOMEM", -7: "OICA_E_UNSUPPORTED",
     -8: "OICA_E_NOCONV",
 }
-OPT_COOP_GIVE_UP, OPT_JACOBI_MAX_SWEEPS, OPT_COOP_FALLBACKS = 1, 2, 3
+OPT_COOP_GIVE_UP, OPT_JACOBI_MAX_SWEEPS, OPT_COOP_FALLBACKS, OPT_COOP_LAUNCH_API = 1, 2, 3, 4
 
 
 class OicaError(RuntimeError):
