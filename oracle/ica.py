@@ -447,3 +447,35 @@ def fastica_projected(Xw: np.ndarray, w0: np.ndarray, E: np.ndarray, tol: float,
             return w, t, True
         if t >= max_iter:
             return w, t, False
+
+
+def ordering_original(Xw: np.ndarray, W0s, tol: float, max_iter: int,
+                      gaussianity_test: bool = True):
+    """The original ordering ICA, Algorithm 1: for step i = 1, 2, ...,
+    E = W^T W of the components found so far (0 at i = 1); every start row
+    of W0s[i-1] (L x N) runs ``fastica_projected`` with E; the kurtosis of each
+    returned vector; p = the run of largest upsilon over all runs (lowest index
+    on ties; Algorithm 1 keeps every run, converged or not); the loop ends when
+    upsilon_p is below eq. 3's threshold for step i (unless the test is off),
+    else the vector of run p is appended to W.  Returns (W, steps) as
+    ``deflation``."""
+    N, T = Xw.shape
+    W = np.zeros((0, N))
+    steps = []
+    for i in range(1, N + 1):
+        E = W.T @ W if i > 1 else np.zeros((N, N))
+        runs = [fastica_projected(Xw, w0, E, tol, max_iter) for w0 in W0s[i - 1]]
+        V = np.array([r[0] for r in runs])
+        alpha = kurtosis(Xw, V)
+        ups = upsilon(alpha)
+        p = int(np.argmax(ups))
+        thr = float(gaussianity_threshold(N, i, T))
+        ok = bool(ups[p] >= thr) or not gaussianity_test
+        steps.append({"i": i, "dim": N, "p": p, "alpha": float(alpha[p]),
+                      "upsilon": float(ups[p]), "threshold": thr, "accepted": ok,
+                      "thread_iters": int(sum(r[1] for r in runs)),
+                      "n_conv": int(sum(r[2] for r in runs))})
+        if not ok:
+            break
+        W = np.vstack([W, V[p] / np.linalg.norm(V[p])])
+    return W, steps

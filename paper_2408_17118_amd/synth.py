@@ -168,6 +168,12 @@ def draw_deflation_starts(rng: np.random.Generator, L: int, N: int) -> list[np.n
     return [draw_start(rng, L, N - i + 1) for i in range(1, N + 1)]
 
 
+def draw_original_starts(rng: np.random.Generator, L: int, N: int) -> list[np.ndarray]:
+    """Start vectors of Algorithm 1: an L x N block of iid N(0,1) values rounded
+    to FP32 for each of the N steps, drawn step after step from rng."""
+    return [draw_start(rng, L, N) for _ in range(N)]
+
+
 def make_problem(kinds: list[str], T: int, K: int, seed, nu: float = 5.0) -> Problem:
     """Draw A, S and W0 for the given source families from one generator."""
     rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)

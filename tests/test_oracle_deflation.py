@@ -167,3 +167,31 @@ def test_mutation_reduced_row_not_mapped_back_caught(monkeypatch):
     W, _ = defl(Xw, W0s, 1e-10, 1000)
     with pytest.raises(AssertionError):
         assert np.max(np.abs(W @ W.T - np.eye(W.shape[0]))) < 1e-12
+
+
+# ---- Algorithm 1 (the original ordering ICA) ----------------------------------
+
+def test_original_algorithm_first_step_is_plain_fastica(small):
+    p, Xw, V, W0s, W, steps = small
+    starts = synth.draw_original_starts(np.random.default_rng(21), 16, p.N)
+    for l in range(4):
+        w1, t1, c1 = ica.fastica_projected(Xw, starts[0][l], np.zeros((p.N, p.N)), 1e-10, 1000)
+        w2, t2, c2 = ica.fastica_single(Xw, starts[0][l], 1e-10, 1000)
+        assert t1 == t2 and c1 == c2 and np.max(np.abs(w1 - w2)) < 1e-15
+
+
+def test_original_algorithm_recovers_sources(small):
+    # Algorithm 1 on the small mixture: orthonormal components, the known
+    # sources in criterion order, the same components as the fast form
+    p, Xw, V, W0s, W_fast, steps_fast = small
+    starts = synth.draw_original_starts(np.random.default_rng(22), 64, p.N)
+    W, steps = ica.ordering_original(Xw, starts, 1e-10, 1000)
+    assert np.max(np.abs(W @ W.T - np.eye(len(W)))) < 1e-12
+    ng = [j for j, k in enumerate(p.kinds) if k != "gaussian"]
+    C = (W[: len(ng)] @ V) @ p.A
+    assert np.all(np.max(np.abs(C), axis=1) / np.linalg.norm(C, axis=1) >= 0.99)
+    assert sorted(np.argmax(np.abs(C), axis=1)) == ng
+    n = min(len(W), len(W_fast))
+    assert np.all(np.abs(np.einsum("kn,kn->k", W[:n], W_fast[:n])) >= 1 - 1e-6)
+    for s in steps:
+        assert s["accepted"] == (s["upsilon"] >= s["threshold"])
