@@ -493,6 +493,28 @@ int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, cons
                    const oica_fp_params *params, double tau, int gaussianity_test, double *W_out,
                    int *n_found, oica_deflation_step *steps);
 
+/* ---------------------------------------------------------------------------
+ * The original ordering ICA (Algorithm 1, Sec. 2.2) as a batched variant:
+ * the L runs of a step are the rows of one fixed point on the full data, with
+ * Algorithm 1's projection.
+ *
+ *   for i = 1, 2, ..., N:  E = W^T W (E = 0 at i = 1);
+ *     every start row w <- w - E w, normalised; every pass
+ *       w <- Xw (y o y o y)^T / T - 3 w,  w <- w - E w,  normalised,
+ *     with the step test and removal of converged rows of oica_fixed_point;
+ *     p = the run of largest criterion (eq. 1) over every run, converged or
+ *       not (lowest row on ties);
+ *     stop if upsilon_p < 2 (N-i+2)(N-i+1) / T (eq. 3; only with
+ *       gaussianity_test != 0);  W <- [W; w_p] (normalised in FP64).
+ *
+ * Arguments as oica_deflation, except: W0 holds N blocks of L x N start rows
+ * (step i's block at element offset (i - 1) L N); params->precision must be
+ * OICA_F32; the steps' dim is N.  Synchronises.  Errors: as oica_fixed_point. */
+int oica_ordering_original(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L,
+                           const float *W0, const oica_fp_params *params, double tau,
+                           int gaussianity_test, double *W_out, int *n_found,
+                           oica_deflation_step *steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -352,7 +352,8 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
                int max_iter, double tol, int check_every, int32_t *iters, uint8_t *status,
                float *traj, int traj_iters, bool profile, int *launched, double *kernel_ms,
                int exit_below = 0, int stall_polls = 0, const PrunerState *pruner = nullptr,
-               int prune_pass = 0, int *keep = nullptr, int *prune_counts = nullptr) {
+               int prune_pass = 0, int *keep = nullptr, int *prune_counts = nullptr,
+               const double *proj = nullptr, int n_proj = 0) {
   // exit_below > 0: stop once at most exit_below rows are active;
   // stall_polls > 0: stop once the active count has not shrunk over that many polls.
   int kmax = K;  // upper bound on the active count (it never grows)
@@ -384,7 +385,7 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
     if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
     *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, pp, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
-                                 s4p, red, tol, iters, status, traj, traj_iters));
+                                 s4p, red, tol, iters, status, traj, traj_iters, proj, n_proj));
     if (pruner && pass + 1 == prune_pass) {
       // the list of pass prune_pass is nxt, its count kact[prune_pass & 1]
       HIP_TRY(ctx, hipMemsetAsync(prune_counts, 0, sizeof(int), ctx->stream));
@@ -423,10 +424,28 @@ struct oica_pruner {
   PrunerState st;
 };
 
+// The fixed point of oica_fixed_point; proj (n_proj x N FP64 unit rows, device)
+// adds Algorithm 1's projection of every start row and update onto the
+// complement of those rows (n_proj = 0: none).
+static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
+                            const float *Xw_f32, int K, const float *W0,
+                            const oica_fp_params *params, float *W_out, double *kurt,
+                            int32_t *iters, uint8_t *status, float *traj, oica_fp_stats *stats,
+                            const double *proj, int n_proj);
+
 int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
                      const float *Xw_f32, int K, const float *W0, const oica_fp_params *params,
                      float *W_out, double *kurt, int32_t *iters, uint8_t *status, float *traj,
                      oica_fp_stats *stats) {
+  return fixed_point_impl(ctx, N, T, Xw, xw_t, Xw_f32, K, W0, params, W_out, kurt, iters, status,
+                          traj, stats, nullptr, 0);
+}
+
+static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype xw_t,
+                            const float *Xw_f32, int K, const float *W0,
+                            const oica_fp_params *params, float *W_out, double *kurt,
+                            int32_t *iters, uint8_t *status, float *traj, oica_fp_stats *stats,
+                            const double *proj, int n_proj) {
   if (!ctx) return OICA_E_ARG;
   ctx->err.clear();
   int rc = check_dims(ctx, N, T);
@@ -531,7 +550,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
   }
   HIP_TRY(ctx, hipMemsetAsync(ctl, 0, 4 * 256, ctx->stream));
   HIP_TRY(ctx, launch_init_rows(ctx->stream, K, N, W0, W_out, iters, status, act0, ctl, traj_buf,
-                                traj_n));
+                                traj_n, proj, n_proj));
   const int check_every = params->check_every > 0 ? params->check_every : 4;
   const bool profile = params->profile != 0;
   // The BF16 loop ends early once at most K/64 rows are left or the active
@@ -554,7 +573,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
                     params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
                     status, attempt == 0 ? traj_buf : nullptr, attempt == 0 ? traj_n : 0, profile,
                     &launched, &kernel_ms, bf16_exit, bf16_stall, prune_now ? pruner : nullptr,
-                    prune_pass, keep, prune_counts);
+                    prune_pass, keep, prune_counts, proj, n_proj);
     if (rc) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -594,7 +613,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         if (fp32_passes > 0 && rows0 > 0) {
           rc = run_passes(ctx, plan32, N, T, X32p, false, rows0, W_out, act2, act0, gpart, s4part,
                           red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
-                          0, false, &l2, &ms2);
+                          0, false, &l2, &ms2, 0, 0, nullptr, 0, nullptr, nullptr, proj, n_proj);
           if (rc) return rc;
         }
         HIP_TRY(ctx, launch_kurtosis(ctx->stream, plan32, N, T, X32p, K, W_out, s4part64, kurt,
@@ -609,7 +628,7 @@ int oica_fixed_point(oica_ctx *ctx, int N, int64_t T, const void *Xw, oica_dtype
         if (fp32_passes > 0 && rows0 > 0) {
           rc = run_passes(ctx, plan32, N, T, X32p, false, rows0, W_out, act2, act0, gpart, s4part,
                           red, ctl2, fp32_passes, params->tol, check_every, iters, status, nullptr,
-                          0, false, &l2, &ms2);
+                          0, false, &l2, &ms2, 0, 0, nullptr, 0, nullptr, nullptr, proj, n_proj);
           if (rc) return rc;
         }
       }
@@ -1550,6 +1569,85 @@ int oica_deflation(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L, cons
     }
     if (na == 0) break;
     HIP_TRY(ctx, launch_defl_append(ctx->stream, N, n_prev, G, B, rep, W_out));
+    *n_found = i;
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return OICA_OK;
+}
+
+int oica_ordering_original(oica_ctx *ctx, int N, int64_t T, const float *Xw, int L,
+                           const float *W0, const oica_fp_params *params, double tau,
+                           int gaussianity_test, double *W_out, int *n_found,
+                           oica_deflation_step *steps) {
+  if (!ctx) return OICA_E_ARG;
+  ctx->err.clear();
+  int rc = check_dims(ctx, N, T);
+  if (rc) return rc;
+  if (L < 1 || L > (1 << 24)) return fail(ctx, OICA_E_ARG, "L must be in [1, 2^24] (got %d)", L);
+  rc = check_fp_params(ctx, params);
+  if (rc) return rc;
+  if (params->precision != OICA_F32)
+    return fail(ctx, OICA_E_UNSUPPORTED, "the original algorithm runs in FP32 (precision OICA_F32)");
+  if (params->pruner) return fail(ctx, OICA_E_ARG, "the original algorithm runs without the pruner");
+  if (params->traj_iters != 0) return fail(ctx, OICA_E_ARG, "traj_iters must be 0");
+  if (!(tau > 0.0 && tau < 1.0)) return fail(ctx, OICA_E_ARG, "tau must be in (0, 1)");
+  if (!Xw || !W0 || !W_out || !n_found) return fail(ctx, OICA_E_ARG, "Xw, W0, W_out and n_found must be non-null");
+  *n_found = 0;
+  size_t need = (size_t)L * N * 4 + 256;                   // rows of the runs
+  need += (size_t)L * (8 + 4 + 1) + 3 * 256;               // kurt, iters, status
+  need += (size_t)L * (N * 8 + 8 + 8 + 4 + 4) + 5 * 256;   // selection outputs (cap L)
+  rc = ensure_buf(ctx, &ctx->ws2, &ctx->ws2_bytes, need);
+  if (rc) return rc;
+  Carve cv{(char *)ctx->ws2};
+  float *B = cv.take<float>((size_t)L * N);
+  double *kurt = cv.take<double>(L);
+  int32_t *iters = cv.take<int32_t>(L);
+  uint8_t *status = cv.take<uint8_t>(L);
+  double *U = cv.take<double>((size_t)L * N);
+  double *ku = cv.take<double>(L);
+  double *uu = cv.take<double>(L);
+  int32_t *rep = cv.take<int32_t>(L);
+  int32_t *csz = cv.take<int32_t>(L);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  for (int i = 1; i <= N; ++i) {
+    const int n_prev = i - 1;
+    // L runs of Algorithm 1's FastICA from step i's starts, every start row and
+    // update projected with E = W^T W of the n_prev components found so far
+    oica_fp_stats st{};
+    rc = fixed_point_impl(ctx, N, T, Xw, OICA_F32, Xw, L, W0 + (size_t)(i - 1) * L * N, params, B,
+                          kurt, iters, status, nullptr, &st, n_prev ? W_out : nullptr, n_prev);
+    if (rc) return rc;
+    // p = argmax of the criterion over every run (lowest row on ties)
+    HIP_TRY(ctx, launch_mark_runs(ctx->stream, L, status));
+    const oica_unique_params up{tau, 0, 1};
+    int nu = 0, na = 0;
+    rc = oica_unique(ctx, N, T, L, B, kurt, status, &up, L, U, ku, uu, rep, csz, nullptr, &nu, &na);
+    if (rc) return rc;
+    int32_t p = -1;
+    double a = NAN, u = NAN;
+    if (nu > 0) {
+      HIP_TRY(ctx, hipMemcpy(&p, rep, sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpy(&a, ku, sizeof(double), hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpy(&u, uu, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    // eq. 3 at step i (the selection above ran without the test: its
+    // threshold would use the full dimension)
+    const double thr = 2.0 * (double)(N - i + 2) * (double)(N - i + 1) / (double)T;
+    const bool ok = nu > 0 && (!gaussianity_test || u >= thr);
+    if (steps) {
+      oica_deflation_step &s = steps[i - 1];
+      s.dim = N;
+      s.rep = p;
+      s.accepted = ok;
+      s.passes = st.passes;
+      s.thread_iters = st.thread_iters;
+      s.refine_thread_iters = st.refine_thread_iters;
+      s.alpha = a;
+      s.upsilon = u;
+      s.threshold = thr;
+    }
+    if (!ok) break;
+    HIP_TRY(ctx, launch_append_row(ctx->stream, N, n_prev, B, rep, W_out));
     *n_found = i;
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -133,7 +133,42 @@ __global__ __launch_bounds__(64) void k_defl_append(int N, int n_prev, const dou
   if (j1 < N) W[(size_t)n_prev * N + j1] = w1 * inv;
 }
 
+// Algorithm 1 takes the argmax over every run, converged or not: the
+// candidates of the selection are all rows that did not degenerate.
+__global__ __launch_bounds__(DT) void k_mark_runs(int K, uint8_t *__restrict__ status) {
+  const int l = blockIdx.x * DT + threadIdx.x;
+  if (l < K && status[l] == OICA_ROW_NOTCONV) status[l] = OICA_ROW_CONV;
+}
+
+// W[n_prev] = B[rep[0]] (an N-entry FP32 row, already projected and
+// normalised by the fixed point), normalised again in FP64.  One wave.
+__global__ __launch_bounds__(64) void k_append_row(int N, int n_prev, const float *__restrict__ B,
+                                                   const int32_t *__restrict__ rep,
+                                                   double *__restrict__ W) {
+  const int p = rep[0];
+  const int lane = threadIdx.x, j0 = lane, j1 = lane + 64;
+  const double w0 = j0 < N ? (double)B[(size_t)p * N + j0] : 0.0;
+  const double w1 = j1 < N ? (double)B[(size_t)p * N + j1] : 0.0;
+  double ss = w0 * w0 + w1 * w1;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) ss += __shfl_xor(ss, o);
+  const double inv = 1.0 / sqrt(ss);
+  if (j0 < N) W[(size_t)n_prev * N + j0] = w0 * inv;
+  if (j1 < N) W[(size_t)n_prev * N + j1] = w1 * inv;
+}
+
 }  // namespace
+
+hipError_t launch_mark_runs(hipStream_t st, int K, uint8_t *status) {
+  hipLaunchKernelGGL(k_mark_runs, dim3((K + DT - 1) / DT), dim3(DT), 0, st, K, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_append_row(hipStream_t st, int N, int n_prev, const float *B, const int32_t *rep,
+                             double *W) {
+  hipLaunchKernelGGL(k_append_row, dim3(1), dim3(64), 0, st, N, n_prev, B, rep, W);
+  return hipGetLastError();
+}
 
 hipError_t launch_defl_gram(hipStream_t st, int N, int n_prev, const double *W, double *Ft,
                             double *C) {

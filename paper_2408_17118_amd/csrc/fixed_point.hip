@@ -280,12 +280,32 @@ size_t fp_reduce_doubles(const FusedPlan &p, int N, int kmax) {
 // ---------------------------------------------------------------------------
 // Epilogue: one wave per active position.
 // ---------------------------------------------------------------------------
+// Algorithm 1's projection w <- w - E w with E = P^T P for the n_proj unit
+// rows of P (n_proj x N, FP64): the coefficients c_k = P_k . w of the whole
+// vector first, then one subtraction.  A wave holds w in (lane, lane + 64).
+__device__ inline void project_out(double &w0, double &w1, const double *__restrict__ P,
+                                   int n_proj, int N, int lane) {
+  if (n_proj <= 0) return;
+  const int n0 = lane, n1 = lane + 64;
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = 0; k < n_proj; ++k) {
+    const double p0 = n0 < N ? P[(size_t)k * N + n0] : 0.0;
+    const double p1 = n1 < N ? P[(size_t)k * N + n1] : 0.0;
+    const double c = wave_sum(p0 * w0 + p1 * w1);
+    s0 = fma(c, p0, s0);
+    s1 = fma(c, p1, s1);
+  }
+  w0 -= s0;
+  w1 -= s1;
+}
+
 template <int NP>
 __global__ __launch_bounds__(256) void k_epilogue(
     FusedPlan plan, int N, long long T, float *__restrict__ Bm, const int *__restrict__ act_cur,
     int *__restrict__ act_next, FpControl *ctl, int pass, const double *__restrict__ red,
     double tol, int32_t *__restrict__ iters, uint8_t *__restrict__ status,
-    float *__restrict__ traj, int traj_iters, int rows_per_wave) {
+    float *__restrict__ traj, int traj_iters, int rows_per_wave, const double *__restrict__ proj,
+    int n_proj) {
   constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
   const int lane = threadIdx.x % 64;
@@ -329,6 +349,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
     const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
     g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
     g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+    project_out(g0, g1, proj, n_proj, N, lane);  // Algorithm 1 only (n_proj > 0)
     const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
     s4 = __shfl(s4, 0);
     const double alpha = s4 * invT - 3.0;
@@ -365,7 +386,8 @@ __global__ __launch_bounds__(256) void k_epilogue(
 __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *__restrict__ Bm,
                             int32_t *__restrict__ iters, uint8_t *__restrict__ status,
                             int *__restrict__ act0, FpControl *ctl, float *__restrict__ traj,
-                            int traj_iters, int rpw) {
+                            int traj_iters, int rpw, const double *__restrict__ proj,
+                            int n_proj) {
   const int lane = threadIdx.x % 64;
   const int row0 = (blockIdx.x * 4 + threadIdx.x / 64) * rpw;  // rpw rows per wave
   if (row0 >= K) return;  // uniform over the wave
@@ -375,8 +397,9 @@ __global__ void k_init_rows(int K, int N, const float *__restrict__ W0, float *_
     const int row = row0 + r;
     const float *src = W0 + (size_t)row * N;
     const int n0 = lane, n1 = lane + 64;
-    const double w0 = n0 < N ? (double)src[n0] : 0.0;
-    const double w1 = n1 < N ? (double)src[n1] : 0.0;
+    double w0 = n0 < N ? (double)src[n0] : 0.0;
+    double w1 = n1 < N ? (double)src[n1] : 0.0;
+    project_out(w0, w1, proj, n_proj, N, lane);  // Algorithm 1 only (n_proj > 0)
     const double nrm = sqrt(wave_sum(w0 * w0 + w1 * w1));
     const bool ok = nrm > 0.0 && isfinite(nrm);
     float *dst = Bm + (size_t)row * N;
@@ -482,10 +505,10 @@ __global__ void k_kurt_out(FusedPlan plan, long long T, int K, const double *__r
 
 hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
                             int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
-                            float *traj, int traj_iters) {
+                            float *traj, int traj_iters, const double *proj, int n_proj) {
   const int rpw = rows_per_wave(K);
   hipLaunchKernelGGL(k_init_rows, dim3((K + 4 * rpw - 1) / (4 * rpw)), dim3(256), 0, st, K, N, W0,
-                     B, iters, status, act0, ctl, traj, traj_iters, rpw);
+                     B, iters, status, act0, ctl, traj, traj_iters, rpw, proj, n_proj);
   return hipGetLastError();
 }
 
@@ -536,7 +559,8 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
 hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax, float *B,
                            const int *act_cur, int *act_next, FpControl *ctl, int pass,
                            const float *gpart, const float *s4part, double *red, double tol,
-                           int32_t *iters, uint8_t *status, float *traj, int traj_iters) {
+                           int32_t *iters, uint8_t *status, float *traj, int traj_iters,
+                           const double *proj, int n_proj) {
   const int np = fused_np(N);
   OICA_NP_SWITCH(np, {
     hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
@@ -544,7 +568,8 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
     const int rpw = rows_per_wave(kmax);
     hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 4 * rpw - 1) / (4 * rpw)), dim3(256), 0,
                        st, p, N, (long long)T, B, act_cur, act_next, ctl, pass,
-                       (const double *)red, tol, iters, status, traj, traj_iters, rpw);
+                       (const double *)red, tol, iters, status, traj, traj_iters, rpw, proj,
+                       n_proj);
   });
   return hipGetLastError();
 }

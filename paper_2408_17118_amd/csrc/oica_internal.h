@@ -188,6 +188,11 @@ hipError_t launch_defl_gram(hipStream_t st, int N, int n_prev, const double *W, 
 // smallest eigenvalue is <= rank_tol x the largest.
 hipError_t launch_defl_basis(hipStream_t st, int N, int n_prev, const double *Ft, const double *E,
                              double rank_tol, double *G, double *Wh, int *flag);
+// Algorithm 1: every row that did not degenerate becomes a selection candidate;
+// W[n_prev] = B[rep[0]] normalised in FP64 (B: K x N FP32).
+hipError_t launch_mark_runs(hipStream_t st, int K, uint8_t *status);
+hipError_t launch_append_row(hipStream_t st, int N, int n_prev, const float *B, const int32_t *rep,
+                             double *W);
 // W[n_prev] = normalised B[rep[0]] G (B: rows of n = N - n_prev FP32 entries).
 hipError_t launch_defl_append(hipStream_t st, int N, int n_prev, const double *G, const float *B,
                               const int32_t *rep, double *W);
@@ -209,7 +214,8 @@ size_t fp_workspace_floats(const FusedPlan &p, int N, int kmax);
 
 hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float *B,
                             int32_t *iters, uint8_t *status, int *act0, FpControl *ctl,
-                            float *traj, int traj_iters);
+                            float *traj, int traj_iters, const double *proj = nullptr,
+                            int n_proj = 0);
 hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                                const void *X, bool bf16, const float *B, const int *act,
                                const int *kact_dev, int kact_host, float *gpart, float *s4part,
@@ -218,7 +224,8 @@ size_t fp_reduce_doubles(const FusedPlan &p, int N, int kmax);
 hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax,
                            float *B, const int *act_cur, int *act_next, FpControl *ctl, int pass,
                            const float *gpart, const float *s4part, double *red, double tol,
-                           int32_t *iters, uint8_t *status, float *traj, int traj_iters);
+                           int32_t *iters, uint8_t *status, float *traj, int traj_iters,
+                           const double *proj = nullptr, int n_proj = 0);
 hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t T, int K,
                              const float *B, const float *gpart, const float *s4part, double *G,
                              double *s4);

@@ -129,6 +129,9 @@ _SIGS = {
     "oica_deflation": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P, C.POINTER(FpParams),
                                  C.c_double, C.c_int, _P, C.POINTER(C.c_int),
                                  C.POINTER(DeflationStep)]),
+    "oica_ordering_original": (C.c_int, [_P, C.c_int, C.c_int64, _P, C.c_int, _P,
+                                         C.POINTER(FpParams), C.c_double, C.c_int, _P,
+                                         C.POINTER(C.c_int), C.POINTER(DeflationStep)]),
     "oica_unique_batched": (C.c_int, [_P, C.c_int, C.POINTER(UniqueProblem),
                                       C.POINTER(UniqueParams)]),
 }
@@ -410,6 +413,43 @@ class Context:
         n_found = C.c_int(0)
         rc = self.lib.oica_deflation(self.h, N, T, _ptr(Xw), L, _ptr(flat), C.byref(p), float(tau),
                                      1 if gaussianity_test else 0, _ptr(W), C.byref(n_found), steps)
+        self._check(rc)
+        taken = []
+        for i in range(N):
+            st = steps[i]
+            if st.dim == 0:
+                break
+            taken.append({k: getattr(st, k) for k, _ in DeflationStep._fields_})
+            if not st.accepted:
+                break
+        return W[: n_found.value], taken
+
+    def ordering_original(self, Xw, W0_blocks, max_iter=1000, tol=1e-6, tau=1e-3,
+                          check_every=4, gaussianity_test=True):
+        """Algorithm 1 as a batched variant (oica_ordering_original).  Xw: N x T
+        float32; W0_blocks: N blocks of L x N float32 start rows (a list, or one
+        flat tensor).  Returns (W: n_found x N float64, per-step dicts)."""
+        _dev(Xw, "Xw", torch.float32, (None, None))
+        N, T = Xw.shape
+        if isinstance(W0_blocks, (list, tuple)):
+            if len(W0_blocks) != N:
+                raise ValueError(f"W0_blocks must hold {N} blocks, not {len(W0_blocks)}")
+            L = W0_blocks[0].shape[0]
+            for i, b in enumerate(W0_blocks):
+                _dev(b, f"W0_blocks[{i}]", torch.float32, (L, N))
+            flat = torch.cat([b.reshape(-1) for b in W0_blocks])
+        else:
+            flat = _dev(W0_blocks, "W0_blocks", torch.float32, (None,))
+            L = flat.numel() // (N * N)
+            if L * N * N != flat.numel() or L < 1:
+                raise ValueError("flat W0_blocks must hold L N N values")
+        W = torch.zeros((N, N), dtype=torch.float64, device=self._tdev())
+        p = FpParams(max_iter, tol, OICA_F32, 1e-5, 0, 0, check_every, 0, 1, None, 0, 0, 0)
+        steps = (DeflationStep * N)()
+        n_found = C.c_int(0)
+        rc = self.lib.oica_ordering_original(self.h, N, T, _ptr(Xw), L, _ptr(flat), C.byref(p),
+                                             float(tau), 1 if gaussianity_test else 0, _ptr(W),
+                                             C.byref(n_found), steps)
         self._check(rc)
         taken = []
         for i in range(N):

@@ -7,7 +7,8 @@ measures; the evaluation is plain host arithmetic on the returned components.
 * ``artificial``: the generalised-Gaussian datasets of Sec. 4.2 -- 20 sources
   (N = 20, ordering error against the number of start rows L) or 20 sources
   plus 10 Gaussian ones (N = 30, the number of components the Gaussianity
-  test accepts against L), T = 1e4, runs from different start rows.
+  test accepts against L), T = 1e4, runs from different start rows, with the
+  fast form (Algorithm 2) and the original one (Algorithm 1, batched).
 * ``fluctuation``: the run-to-run fluctuation of Sec. 4.3 against L on one
   dataset (the Gaussianity test omitted, as there).
 
@@ -78,12 +79,31 @@ def _deflate(ctx, Xw32, V, L, seed, gaussianity_test=True, precision="f32"):
     return Wr, steps, ms
 
 
+def _original(ctx, Xw32, V, L, seed):
+    import torch
+    N = Xw32.shape[0]
+    starts = synth.draw_original_starts(np.random.default_rng(seed), L, N)
+    flat = torch.from_numpy(np.concatenate([b.astype(np.float32).ravel() for b in starts])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, steps = ctx.ordering_original(Xw32, flat)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    Wr = (W @ V).cpu().numpy()
+    if len(Wr):
+        Wr /= np.linalg.norm(Wr, axis=1, keepdims=True)
+    return Wr, steps, ms
+
+
 def artificial(ctx, n_gauss: int = 0, Ls=(1, 2, 5, 10, 20, 40, 60, 80, 100), runs: int = 10,
-               data_seed: int = 0, start_seed: int = 1000, precision: str = "f32"):
+               data_seed: int = 0, start_seed: int = 1000, precision: str = "f32",
+               original: bool = True):
     """Sec. 4.2 on one generated dataset: for every L, `runs` deflation runs
-    from different start rows.  Returns one record per L with the mean and
-    spread of the ordering error (n_gauss = 0) and of the number of accepted
-    components, and the mean time per run."""
+    from different start rows (and, with `original`, as many runs of
+    Algorithm 1's batched variant for the fast-versus-original comparison).
+    Returns one record per L with the mean and spread of the ordering error
+    (n_gauss = 0) and of the number of accepted components, and the mean time
+    per run of each form."""
     import torch
     prob = synth.artificial_gg(data_seed, n_gauss=n_gauss)
     X = torch.from_numpy(prob.X).cuda()
@@ -102,6 +122,18 @@ def artificial(ctx, n_gauss: int = 0, Ls=(1, 2, 5, 10, 20, 40, 60, 80, 100), run
                "n_found": [int(f) for f in found], "ms_mean": float(np.mean(times))}
         if errs:
             rec.update(e_ordering_mean=float(np.mean(errs)), e_ordering_max=float(np.max(errs)))
+        if original:
+            o_err, o_found, o_ms = [], [], []
+            for r in range(runs):
+                Wr, steps, ms = _original(ctx, Xw32, V, L, start_seed + 1000 * L + r + 500)
+                o_found.append(len(Wr))
+                o_ms.append(ms)
+                if n_gauss == 0:
+                    o_err.append(ordering_error(Wr, prob.A, order))
+            rec.update(original_ms_mean=float(np.mean(o_ms)),
+                       original_n_found_mean=float(np.mean(o_found)))
+            if o_err:
+                rec.update(original_e_ordering_mean=float(np.mean(o_err)))
         out.append(rec)
     return {"N": prob.N, "T": prob.T, "n_gauss": n_gauss, "records": out}
 

@@ -184,6 +184,16 @@ def run(lib):
     expect("deflation N", dfl(N=0), E_ARG)
     expect("deflation valid", dfl(), E_DEVICE)
 
+    # ---- original algorithm
+    def org(N=8, L=16, p=None, W0=P):
+        prm = p if p is not None else fp()
+        return lib.oica_ordering_original(ctx, N, 100, P, L, W0, C.byref(prm), 1e-3, 1, P,
+                                          C.byref(nf), steps)
+    expect("original L", org(L=0), E_ARG)
+    expect("original bf16", org(p=fp(precision=BF16)), E_UNSUP)
+    expect("original W0", org(W0=NUL), E_ARG)
+    expect("original valid", org(), E_DEVICE)
+
     # ---- pruner (no pruner object can exist without a device)
     w = (C.c_float * oica.Pruner.N_PARAMS)()
     m16 = (C.c_float * 16)(*([0.0] * 16))
