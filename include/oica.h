@@ -182,7 +182,8 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
  *
  * precision = OICA_F32: the passes run on FP32 data (Xw of xw_t = OICA_F32).
  * precision = OICA_BF16: the passes run on BF16 data (Xw of xw_t = OICA_BF16;
- *   each row carried as BF16 hi + lo parts, z^3 rounded to BF16, FP32 sums)
+ *   each row rounded once to BF16 while its steps are large, then carried as
+ *   BF16 hi + lo parts (bf16_row_terms below), z^3 rounded to BF16, FP32 sums)
  *   with threshold tol_bf16, until every row has stopped, at most K/64 rows
  *   are left, or the active count has not shrunk over two polls.  Then every
  *   row that converged on BF16 data or was still moving continues on the FP32
@@ -229,6 +230,17 @@ typedef struct {
   int prune_pass;        /* pass after which to prune (8..16; 0 = 8)       */
   int guard_top;         /* see pruner (0 = every accepted component)      */
   int guard_min;         /* rows each of them must keep (0 = 4)            */
+  int bf16_row_terms;    /* BF16 only: how the passes carry each row.
+                            2: BF16 hi + lo parts (z to about 2^-17
+                            relative; two GEMM1 products per pass), the
+                            linear term -3P on the FP32 row.  1: the row
+                            rounded once to BF16 (one product), the linear
+                            term on the same rounded row, so each pass is
+                            the exact update of the rounded row.  3: form 1
+                            while a row's last step is >= bf16_switch_step
+                            (every row at the first pass; such a row never
+                            converges), then form 2.  0: the default (3). */
+  double bf16_switch_step; /* form 3's switch step (0 = 3e-2)             */
 } oica_fp_params;
 
 typedef struct {         /* host */

@@ -321,6 +321,16 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
 // ---------------------------------------------------------------------------
 namespace {
 
+// The BF16 row form a run asks for (bf16_row_terms; 0 = the default, the
+// switched form).
+int bf16_form(const oica_fp_params *p) {
+  switch (p->bf16_row_terms) {
+    case 1: return BF_ONE;
+    case 2: return BF_HILO;
+    default: return BF_SWITCH;
+  }
+}
+
 int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
   if (!p) return fail(ctx, OICA_E_ARG, "params must be non-null");
   if (p->max_iter < 1) return fail(ctx, OICA_E_ARG, "max_iter must be >= 1");
@@ -332,6 +342,10 @@ int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
   if (p->refine_iters < 0) return fail(ctx, OICA_E_ARG, "refine_iters must be >= 0");
   if (p->traj_iters < 0 || p->traj_iters > 16) return fail(ctx, OICA_E_ARG, "traj_iters must be in [0, 16]");
   if (p->check_every < 0) return fail(ctx, OICA_E_ARG, "check_every must be >= 0");
+  if (p->bf16_row_terms < 0 || p->bf16_row_terms > 3)
+    return fail(ctx, OICA_E_ARG, "bf16_row_terms must be 0, 1, 2 or 3");
+  if (p->bf16_switch_step < 0 || !isfinite(p->bf16_switch_step))
+    return fail(ctx, OICA_E_ARG, "bf16_switch_step must be >= 0");
   return OICA_OK;
 }
 
@@ -353,11 +367,17 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
                float *traj, int traj_iters, bool profile, int *launched, double *kernel_ms,
                int exit_below = 0, int stall_polls = 0, const PrunerState *pruner = nullptr,
                int prune_pass = 0, int *keep = nullptr, int *prune_counts = nullptr,
-               const double *proj = nullptr, int n_proj = 0) {
+               const double *proj = nullptr, int n_proj = 0, int bf_form = BF_HILO,
+               double switch_step = 0.0, int *fine_list = nullptr) {
   // exit_below > 0: stop once at most exit_below rows are active;
-  // stall_polls > 0: stop once the active count has not shrunk over that many polls.
+  // stall_polls > 0: stop once the active count has not shrunk over that many polls
+  // (switched BF16 form: the active count plus the one-term count, so a row
+  // that moves to the hi + lo form counts as progress).
+  if (!bf16) bf_form = BF_HILO;
+  if (bf_form == BF_SWITCH && !fine_list) bf_form = BF_HILO;
   int kmax = K;  // upper bound on the active count (it never grows)
   int stalled = 0;
+  long long work_prev = 2LL * K + 1;
   *launched = 0;
   *kernel_ms = 0.0;
   // few rows active: the thin items (FP32, up to THIN_PLAN_ROWS rows), or one
@@ -381,17 +401,22 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
     // the z^4 sums only feed the trajectory; BF16 passes past it skip them
     float *s4p = (bf16 && pass >= traj_iters) ? nullptr : s4part;
     HIP_TRY(ctx, launch_fused_update(ctx->stream, pp, N, T, X, bf16, B, cur, &ctl->kact[0], 0,
-                                     gpart, s4p, ctl, pass));
+                                     gpart, s4p, ctl, pass, bf_form));
     if (profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * pass + 1], ctx->stream));
     *launched = pass + 1;
     HIP_TRY(ctx, launch_epilogue(ctx->stream, pp, N, T, kmax, B, cur, nxt, ctl, pass, gpart,
-                                 s4p, red, tol, iters, status, traj, traj_iters, proj, n_proj));
+                                 s4p, red, tol, iters, status, traj, traj_iters, proj, n_proj,
+                                 bf16 ? bf_form : 0, switch_step, fine_list));
     if (pruner && pass + 1 == prune_pass) {
       // the list of pass prune_pass is nxt, its count kact[prune_pass & 1]
       HIP_TRY(ctx, hipMemsetAsync(prune_counts, 0, sizeof(int), ctx->stream));
       HIP_TRY(ctx, launch_prune(ctx->stream, pruner, traj, 2 * traj_iters, nxt,
                                 &ctl->kact[prune_pass & 1], kmax, status, keep, prune_counts,
                                 prune_counts + 1));
+      // the survivors are compacted in no particular order: every one of them
+      // takes the hi + lo form from here on
+      if (bf_form == BF_SWITCH)
+        HIP_TRY(ctx, hipMemsetAsync(&ctl->kc[prune_pass & 1], 0, sizeof(int), ctx->stream));
     }
     if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
@@ -400,7 +425,9 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       const FpControl *h = (const FpControl *)ctx->small_host;
       const int left = h->kact[(pass + 1) & 1];
       if (left == 0) break;
-      stalled = (left >= kmax) ? stalled + 1 : 0;
+      const long long work = left + (bf_form == BF_SWITCH ? (long long)h->kc[(pass + 1) & 1] : 0LL);
+      stalled = (work >= work_prev) ? stalled + 1 : 0;
+      work_prev = work;
       kmax = left;
       if (exit_below > 0 && left <= exit_below) break;
       if (stall_polls > 0 && stalled >= stall_polls) break;
@@ -499,7 +526,8 @@ static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oic
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
   const size_t red_n = fp_reduce_doubles(plan, N, K);
   need += red_n * sizeof(double) + 256;         // split-group sums
-  need += 5 * ((size_t)K * sizeof(int) + 256);  // act lists, kurtosis list, prune survivors
+  need += 6 * ((size_t)K * sizeof(int) + 256);  // act lists, kurtosis list, prune survivors,
+                                                // rows entering the BF16 hi + lo form
   need += 4 * (sizeof(FpControl) + 256);
   need += unique_workspace_bytes(K, N) + 256;   // grouping of BF16 fixed points / guard
   if (pruner && !traj) need += (size_t)K * traj_n * 2 * sizeof(float) + 256;
@@ -518,6 +546,7 @@ static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oic
   int *act2 = cv.take<int>(K);
   int *kurt_list = cv.take<int>(K);
   int *keep = cv.take<int>(K);
+  int *fine_list = cv.take<int>(K);
   FpControl *ctl = cv.take<FpControl>(1);
   FpControl *ctl2 = cv.take<FpControl>(1);
   (void)cv.take<FpControl>(1);  // third control block (kurtosis list), ctl2 + 256 bytes
@@ -573,7 +602,8 @@ static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oic
                     params->max_iter, bf16 ? params->tol_bf16 : params->tol, check_every, iters,
                     status, attempt == 0 ? traj_buf : nullptr, attempt == 0 ? traj_n : 0, profile,
                     &launched, &kernel_ms, bf16_exit, bf16_stall, prune_now ? pruner : nullptr,
-                    prune_pass, keep, prune_counts, proj, n_proj);
+                    prune_pass, keep, prune_counts, proj, n_proj, bf16_form(params),
+                    params->bf16_switch_step > 0 ? params->bf16_switch_step : 3e-2, fine_list);
     if (rc) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
                                 ctx->stream));

@@ -186,7 +186,11 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_f32_thin(
   }
 }
 
-template <int NP, int WK>
+// FORM (BfRowForm): BF_HILO every row as hi + lo parts; BF_ONE every row
+// rounded once to BF16; BF_SWITCH the first kc rows of the active list
+// rounded once (every row at a run's first pass) and the rest as hi + lo, per
+// work item (an item with any hi + lo row takes that form for all its rows).
+template <int NP, int WK, int FORM>
 __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
     const __bf16 *__restrict__ X, int N, long long T, FusedPlan plan, const float *__restrict__ Bm,
     const int *__restrict__ act, const int *__restrict__ kact_dev, int kact_host,
@@ -198,8 +202,13 @@ __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
   __shared__ __attribute__((aligned(16))) __bf16 xt[2 * BfTile<NP>::xt_elems];
 
   const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
+  // rows of the one-term form: the head of the list (read before block 0
+  // resets the next pass's counters; kc of this pass is not written here)
+  const int kc = FORM == BF_SWITCH ? (pass == 0 ? kact : ctl->kc[pass & 1])
+                                   : (FORM == BF_ONE ? kact : 0);
   if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->kact[(pass + 1) & 1] = 0;
+    if (FORM == BF_SWITCH) ctl->kf = 0;
     if (kact > 0) {
       ctl->passes = pass + 1;
       ctl->thread_iters += kact;
@@ -220,10 +229,19 @@ __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
   for (int it = local; it < per_xcd_items; it += per_xcd_wgs) {
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
-    if (s4part)
-      item_bf16<NP, WK, true, NW>(c, w_item % n_kb, w_item / n_kb, xs, xt);
-    else
-      item_bf16<NP, WK, false, NW>(c, w_item % n_kb, w_item / n_kb, xs, xt);
+    const int kb = w_item % n_kb, sp = w_item / n_kb;
+    const bool one = (kb + 1) * KWG <= kc;  // every row of the item takes the one-term form
+    if (FORM != BF_HILO && one) {
+      if (s4part)
+        item_bf16<NP, WK, true, NW, false>(c, kb, sp, xs, xt);
+      else
+        item_bf16<NP, WK, false, NW, false>(c, kb, sp, xs, xt);
+    } else if (FORM != BF_ONE) {
+      if (s4part)
+        item_bf16<NP, WK, true, NW, true>(c, kb, sp, xs, xt);
+      else
+        item_bf16<NP, WK, false, NW, true>(c, kb, sp, xs, xt);
+    }
   }
 }
 
@@ -305,9 +323,12 @@ __global__ __launch_bounds__(256) void k_epilogue(
     int *__restrict__ act_next, FpControl *ctl, int pass, const double *__restrict__ red,
     double tol, int32_t *__restrict__ iters, uint8_t *__restrict__ status,
     float *__restrict__ traj, int traj_iters, int rows_per_wave, const double *__restrict__ proj,
-    int n_proj) {
+    int n_proj, int bf_form, double switch_step, int *__restrict__ fine_list) {
   constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
+  // rows of the one-term BF16 form (head of the list), as the fused kernel saw them
+  const int kc = bf_form == BF_SWITCH ? (pass == 0 ? kact : ctl->kc[pass & 1])
+                                      : (bf_form == BF_ONE ? kact : 0);
   const int lane = threadIdx.x % 64;
   // rows_per_wave (<= EPI_ROWS) rows per wave, one after the other; the rows
   // that stay active are appended with one atomic per wave
@@ -318,11 +339,12 @@ __global__ __launch_bounds__(256) void k_epilogue(
   const int groups = (n_sp + SPLIT_GROUP - 1) / SPLIT_GROUP;
   const int n0 = lane, n1 = lane + 64;
   const double invT = 1.0 / (double)T;
-  bool stay = false;
+  bool stay = false, stay_one = false;
   int stay_row = -1;
   for (int r = 0; r < rows_per_wave && posn0 + r < kact; ++r) {
     const int posn = posn0 + r;
     const int row = act_cur[posn];
+    const bool one = posn < kc;
     double g0 = 0.0, g1 = 0.0, s4 = 0.0;
     // second stage: group sums in group order, EPI_U loads in flight per lane
     constexpr int EPI_U = 8;
@@ -347,8 +369,12 @@ __global__ __launch_bounds__(256) void k_epilogue(
     float *brow = Bm + (size_t)row * N;
     const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
     const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
-    g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
-    g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+    // the linear term: the row the pass's z came from (rounded to BF16 when
+    // the pass ran on one BF16 part, so the pass is that row's exact update)
+    const double bl0 = (one && n0 < N) ? (double)(float)(__bf16)brow[n0] : bp0;
+    const double bl1 = (one && n1 < N) ? (double)(float)(__bf16)brow[n1] : bp1;
+    g0 = n0 < N ? g0 * invT - 3.0 * bl0 : 0.0;
+    g1 = n1 < N ? g1 * invT - 3.0 * bl1 : 0.0;
     project_out(g0, g1, proj, n_proj, N, lane);  // Algorithm 1 only (n_proj > 0)
     const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
     s4 = __shfl(s4, 0);
@@ -364,13 +390,17 @@ __global__ __launch_bounds__(256) void k_epilogue(
       d = sqrt(dm < dp ? dm : dp);
       if (n0 < N) brow[n0] = (float)b0;
       if (n1 < N) brow[n1] = (float)b1;
+      // in the switched form a one-term row never converges: it takes the
+      // hi + lo form once its step is below switch_step
+      const bool coarse = bf_form == BF_SWITCH && one;
       if (lane == 0) {
         iters[row] += 1;
-        if (d < tol) status[row] = OICA_ROW_CONV;
+        if (!coarse && d < tol) status[row] = OICA_ROW_CONV;
       }
-      if (lane == r && !(d < tol)) {
+      if (lane == r && (coarse || !(d < tol))) {
         stay = true;
         stay_row = row;
+        stay_one = coarse && !(d < switch_step);
       }
     }
     if (lane == 0 && pass < traj_iters) {
@@ -378,7 +408,29 @@ __global__ __launch_bounds__(256) void k_epilogue(
       traj[((size_t)row * traj_iters + pass) * 2 + 1] = (float)d;
     }
   }
-  wave_append(stay, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
+  if (bf_form == BF_SWITCH) {
+    wave_append(stay && stay_one, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
+    wave_append(stay && !stay_one, stay_row, fine_list, &ctl->kf);
+  } else {
+    wave_append(stay, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
+  }
+}
+
+// Switched BF16 form: the rows staged for the hi + lo form join the next
+// pass's list after its one-term rows; the one-term count is recorded.  One
+// work-group.
+__global__ __launch_bounds__(1024) void k_join_fine(int *__restrict__ act_next,
+                                                    const int *__restrict__ fine_list,
+                                                    FpControl *ctl, int pass) {
+  const int nx = (pass + 1) & 1;
+  const int kc = ctl->kact[nx];
+  const int kf = ctl->kf;
+  for (int j = threadIdx.x; j < kf; j += blockDim.x) act_next[kc + j] = fine_list[j];
+  __syncthreads();  // every thread has read the counts
+  if (threadIdx.x == 0) {
+    ctl->kc[nx] = kc;
+    ctl->kact[nx] = kc + kf;
+  }
 }
 
 // Row initialisation: normalise W0 in FP64, mark zero/non-finite rows
@@ -515,21 +567,33 @@ hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float
 hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_t T, const void *X,
                                bool bf16, const float *B, const int *act, const int *kact_dev,
                                int kact_host, float *gpart, float *s4part, FpControl *ctl,
-                               int pass) {
+                               int pass, int bf_form) {
   const int np = fused_np(N);
   if (bf16) {
+    // the switched form needs the device counters (and a list to split)
+    if (bf_form == BF_SWITCH && (!ctl || !kact_dev)) bf_form = BF_HILO;
     const bool wk1 = p.kwg == bf16_waves(np) * 32;  // one 32-row block per wave (narrow plan)
-#define OICA_BF16_LAUNCH(WKV)                                                              \
-  hipLaunchKernelGGL((k_fused_bf16<NP_, WKV>), dim3(p.grid), dim3(bf16_waves(NP_) * 64), 0, st, \
-                     (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,        \
+#define OICA_BF16_LAUNCH(WKV, FV)                                                          \
+  hipLaunchKernelGGL((k_fused_bf16<NP_, WKV, FV>), dim3(p.grid), dim3(bf16_waves(NP_) * 64), 0,  \
+                     st, (const __bf16 *)X, N, (long long)T, p, B, act, kact_dev, kact_host,    \
                      gpart, s4part, ctl, pass)
+#define OICA_BF16_FORMS(WKV)                 \
+  do {                                       \
+    if (bf_form == BF_ONE)                   \
+      OICA_BF16_LAUNCH(WKV, BF_ONE);         \
+    else if (bf_form == BF_SWITCH)           \
+      OICA_BF16_LAUNCH(WKV, BF_SWITCH);      \
+    else                                     \
+      OICA_BF16_LAUNCH(WKV, BF_HILO);        \
+  } while (0)
     OICA_NP_SWITCH(np, {
       constexpr int WK2 = NP_ <= 64 ? 2 : 1;  // the wide variant
       if (!wk1)
-        OICA_BF16_LAUNCH(WK2);
+        OICA_BF16_FORMS(WK2);
       else
-        OICA_BF16_LAUNCH(1);
+        OICA_BF16_FORMS(1);
     });
+#undef OICA_BF16_FORMS
 #undef OICA_BF16_LAUNCH
     return hipGetLastError();
   }
@@ -560,7 +624,9 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            const int *act_cur, int *act_next, FpControl *ctl, int pass,
                            const float *gpart, const float *s4part, double *red, double tol,
                            int32_t *iters, uint8_t *status, float *traj, int traj_iters,
-                           const double *proj, int n_proj) {
+                           const double *proj, int n_proj, int bf_form, double switch_step,
+                           int *fine_list) {
+  if (bf_form == BF_SWITCH && !fine_list) bf_form = BF_HILO;
   const int np = fused_np(N);
   OICA_NP_SWITCH(np, {
     hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
@@ -569,8 +635,11 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
     hipLaunchKernelGGL((k_epilogue<NP_>), dim3((kmax + 4 * rpw - 1) / (4 * rpw)), dim3(256), 0,
                        st, p, N, (long long)T, B, act_cur, act_next, ctl, pass,
                        (const double *)red, tol, iters, status, traj, traj_iters, rpw, proj,
-                       n_proj);
+                       n_proj, bf_form, switch_step, fine_list);
   });
+  if (bf_form == BF_SWITCH)
+    hipLaunchKernelGGL(k_join_fine, dim3(1), dim3(1024), 0, st, act_next, (const int *)fine_list,
+                       ctl, pass);
   return hipGetLastError();
 }
 

@@ -422,7 +422,11 @@ template <int NP> struct BfTile {
 // the sums are skipped and a non-null s4part receives zeros.
 // NW: waves of the work-group (all stage the shared X tile; each holds its own
 // WK x 32 rows).
-template <int NP, int WK, bool S4 = true, int NW = WAVES>
+// LO: rows carried as hi + lo BF16 parts (two GEMM1 MFMAs per step); without
+// it each row is rounded once to BF16 (the hi part alone) and the pass is the
+// update of that rounded row (the epilogue takes the linear term from the same
+// rounding).
+template <int NP, int WK, bool S4 = true, int NW = WAVES, bool LO = true>
 __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs_base,
                                           __bf16 *xt_base) {
   constexpr int KWG = NW * WK * 32;
@@ -466,7 +470,7 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
           const float b = (row >= 0 && n < N) ? Bm[(size_t)row * N + n] : 0.f;
           const __bf16 hi = (__bf16)b;
           breg[w][s][j] = hi;
-          blo[w][s][j] = (__bf16)(b - (float)hi);
+          blo[w][s][j] = LO ? (__bf16)(b - (float)hi) : (__bf16)0.f;
         }
       }
     }
@@ -594,7 +598,8 @@ __device__ __forceinline__ void item_bf16(const ItemCtx &c, int kb, int sp, __bf
 #pragma unroll
           for (int w = 0; w < WK; ++w) {
             zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, breg[w][s], zacc[w], 0, 0, 0);
-            zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[w][s], zacc[w], 0, 0, 0);
+            if constexpr (LO)
+              zacc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[w][s], zacc[w], 0, 0, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
           if (s + AH < S1) abuf[s % AH] = ga(s + AH);

@@ -27,7 +27,15 @@ struct FpControl {
   int passes;             // passes that had at least one active row
   int pad;
   long long thread_iters; // sum over passes of the active-row count
+  int kc[2];              // BF16 switched form: the first kc rows of a pass's
+                          // active list take the one-term (coarse) form; the
+                          // first pass of a run takes it for every row
+  int kf;                 // rows entering the hi + lo (fine) form, staged by
+                          // the epilogue before they join the list's tail
+  int pad2;
 };
+// How BF16 passes carry a row (the BF16 kernel's row form).
+enum BfRowForm { BF_ONE = 1, BF_HILO = 2, BF_SWITCH = 3 };
 
 // Launch plan of the fused update kernel.  The grid is fixed for a whole run;
 // each work-group derives its (row block, sample split) from the active count
@@ -219,13 +227,14 @@ hipError_t launch_init_rows(hipStream_t st, int K, int N, const float *W0, float
 hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                                const void *X, bool bf16, const float *B, const int *act,
                                const int *kact_dev, int kact_host, float *gpart, float *s4part,
-                               FpControl *ctl, int pass);
+                               FpControl *ctl, int pass, int bf_form = BF_HILO);
 size_t fp_reduce_doubles(const FusedPlan &p, int N, int kmax);
 hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T, int kmax,
                            float *B, const int *act_cur, int *act_next, FpControl *ctl, int pass,
                            const float *gpart, const float *s4part, double *red, double tol,
                            int32_t *iters, uint8_t *status, float *traj, int traj_iters,
-                           const double *proj = nullptr, int n_proj = 0);
+                           const double *proj = nullptr, int n_proj = 0, int bf_form = 0,
+                           double switch_step = 0.0, int *fine_list = nullptr);
 hipError_t launch_update_out(hipStream_t st, const FusedPlan &p, int N, int64_t T, int K,
                              const float *B, const float *gpart, const float *s4part, double *G,
                              double *s4);

@@ -39,7 +39,8 @@ class FpParams(C.Structure):
                 ("tol_bf16", C.c_double), ("refine_iters", C.c_int), ("traj_iters", C.c_int),
                 ("check_every", C.c_int), ("profile", C.c_int), ("refine_groups", C.c_int),
                 ("pruner", C.c_void_p), ("prune_pass", C.c_int), ("guard_top", C.c_int),
-                ("guard_min", C.c_int)]
+                ("guard_min", C.c_int), ("bf16_row_terms", C.c_int),
+                ("bf16_switch_step", C.c_double)]
 
 
 class FpStats(C.Structure):
@@ -283,7 +284,8 @@ class Context:
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
                     tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
-                    refine_groups=True, pruner=None, prune_pass=8, guard_top=0, guard_min=4):
+                    refine_groups=True, pruner=None, prune_pass=8, guard_top=0, guard_min=4,
+                    bf16_row_terms=0, bf16_switch_step=0.0):
         _dev(Xw, "Xw", torch.bfloat16 if precision == "bf16" else torch.float32, (None, None))
         N, T = Xw.shape
         _dev(W0, "W0", torch.float32, (None, N))
@@ -300,7 +302,7 @@ class Context:
         p = FpParams(max_iter, tol, OICA_BF16 if precision == "bf16" else OICA_F32, tol_bf16,
                      refine_iters, traj_iters, check_every, 1 if profile else 0,
                      1 if refine_groups else 0, pruner.h if pruner is not None else None,
-                     prune_pass, guard_top, guard_min)
+                     prune_pass, guard_top, guard_min, bf16_row_terms, bf16_switch_step)
         st = FpStats()
         rc = self.lib.oica_fixed_point(self.h, N, T, _ptr(Xw), _DT[Xw.dtype], _ptr(Xw_f32), K,
                                        _ptr(W0), C.byref(p), _ptr(W), _ptr(kurt), _ptr(iters),
@@ -625,13 +627,15 @@ def get_option(option: int) -> int:
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
                  tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
-                 profile=False, refine_groups=True, pruner=None, traj_iters=0):
+                 profile=False, refine_groups=True, pruner=None, traj_iters=0, bf16_row_terms=0,
+                 bf16_switch_step=0.0):
     """Whole hot path on device-resident raw data: whiten -> fixed point -> unique."""
     xw_dtype = torch.bfloat16 if precision == "bf16" else torch.float32
     Xw, Xw32, V, mean, eig = ctx.whiten(X, out_dtype=xw_dtype)
     fp = ctx.fixed_point(Xw, W0, Xw_f32=Xw32, max_iter=max_iter, tol=tol, precision=precision,
                          tol_bf16=tol_bf16, refine_iters=refine_iters, profile=profile,
-                         refine_groups=refine_groups, pruner=pruner, traj_iters=traj_iters)
+                         refine_groups=refine_groups, pruner=pruner, traj_iters=traj_iters,
+                         bf16_row_terms=bf16_row_terms, bf16_switch_step=bf16_switch_step)
     res = ctx.unique(fp["W"], fp["kurt"], fp["status"], X.shape[1], tau=tau,
                      gaussianity_test=gaussianity_test)
     res.update(fp=fp, V=V, mean=mean, eig=eig, Xw=Xw, Xw_f32=Xw32)
