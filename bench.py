@@ -229,7 +229,8 @@ def main():
     wk_ = 2 if np_ <= 64 else 1
     if bf16:
         tail = f"; <{np_},1> in passes with <= 128 active rows" if wk_ == 2 else ""
-        kname = f"k_fused_bf16<{np_},{wk_}> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA{tail})"
+        kname = (f"k_fused_bf16<{np_},{wk_},3> (switched row form: GEMM1 on the BF16-rounded row "
+                 f"while its step is >= 3e-2, then on BF16 hi+lo rows; cube; GEMM2; BF16 MFMA{tail})")
     else:
         kname = (f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA; "
                  f"k_fused_f32_thin<{np_}> in passes with <= 256 active rows)")

@@ -230,7 +230,8 @@ __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
     const int kb = w_item % n_kb, sp = w_item / n_kb;
-    const bool one = (kb + 1) * KWG <= kc;  // every row of the item takes the one-term form
+    // every row of the item takes the one-term form
+    const bool one = ((kb + 1) * KWG < kact ? (kb + 1) * KWG : kact) <= kc;
     if (FORM != BF_HILO && one) {
       if (s4part)
         item_bf16<NP, WK, true, NW, false>(c, kb, sp, xs, xt);
