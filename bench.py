@@ -199,7 +199,7 @@ def main():
 
     def step(profile=False):
         return oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, tau=1e-3, profile=profile,
-                                 precision=precision, tol_bf16=1e-5, refine_iters=5, pruner=pruner)
+                                 precision=precision, tol_bf16=1e-3, refine_iters=5, pruner=pruner)
 
     for i in range(args.warmup):
         r = step()
@@ -229,8 +229,7 @@ def main():
     wk_ = 2 if np_ <= 64 else 1
     if bf16:
         tail = f"; <{np_},1> in passes with <= 128 active rows" if wk_ == 2 else ""
-        kname = (f"k_fused_bf16<{np_},{wk_},3> (switched row form: GEMM1 on the BF16-rounded row "
-                 f"while its step is >= 3e-2, then on BF16 hi+lo rows; cube; GEMM2; BF16 MFMA{tail})")
+        kname = f"k_fused_bf16<{np_},{wk_},2> (GEMM1 on bf16 hi+lo rows + cube + GEMM2, BF16 MFMA{tail})"
     else:
         kname = (f"k_fused_f32<{np_},{wk_}> (GEMM1 + cube + GEMM2, FP32 MFMA; "
                  f"k_fused_f32_thin<{np_}> in passes with <= 256 active rows)")
@@ -250,6 +249,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "T": T, "K": K, "tol": 1e-6,
                    "max_iter": 1000, "precision": precision,
+                   "tol_bf16": 1e-3 if bf16 else None,
                    "seed": {"eeg_shaped_n64": 1, "precision_n128": 3, "pruner_n64": 5300}[args.workload],
                    "passes": last["fp"]["passes"], "thread_iters_per_step": last["fp"]["thread_iters"],
                    "fp32_thread_iters_per_step": last["fp"]["refine_thread_iters"],
@@ -298,12 +298,12 @@ def main():
         out["plain_fp32"] = pf
         out["speedup_vs_plain_fp32"] = pf["time_to_unique_ms"] / ms_per_step
     elif args.workload == "eeg_shaped_n64":
-        mp = compare("bf16 + fp32 finish (mixed precision)", precision="bf16", tol_bf16=1e-5)
+        mp = compare("bf16 + fp32 finish (mixed precision)", precision="bf16", tol_bf16=1e-3)
         mp["speedup_vs_plain_fp32"] = ms_per_step / mp["time_to_unique_ms"]
         out["mixed_precision"] = mp
     elif args.workload == "pruner_n64":
         pf = compare("plain fp32", precision="f32")
-        ub = compare("bf16 without pruner", precision="bf16", tol_bf16=1e-5)
+        ub = compare("bf16 without pruner", precision="bf16", tol_bf16=1e-3)
         out["plain_fp32"] = pf
         out["bf16_unpruned"] = ub
         out["speedup_vs_plain_fp32"] = pf["time_to_unique_ms"] / ms_per_step
@@ -341,7 +341,7 @@ def bench_batched(args):
         if len(Xs) % 16 == 0:
             print(f"generated {len(Xs)} datasets", file=sys.stderr, flush=True)
     ctx = oica.Context(0)
-    kw = dict(tol=1e-6, max_iter=1000, tau=1e-3, precision="bf16", tol_bf16=1e-5, refine_iters=5)
+    kw = dict(tol=1e-6, max_iter=1000, tau=1e-3, precision="bf16", tol_bf16=1e-3, refine_iters=5)
 
     def step(profile=False, **over):
         return oica.ordering_ica_batched(ctx, Xs, W0s, profile=profile, **{**kw, **over})
@@ -392,7 +392,7 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": "batched_n16_128", "datasets": len(Xs), "K_each": 1024,
                    "sum_NT": int(sum(n * t for n, t in NT)), "tol": 1e-6, "max_iter": 1000,
-                   "precision": "bf16", "seed": 4, "passes": lst["passes"],
+                   "precision": "bf16", "tol_bf16": 1e-3, "seed": 4, "passes": lst["passes"],
                    "thread_iters_per_step": lst["thread_iters"],
                    "fp32_thread_iters_per_step": lst["refine_thread_iters"],
                    "grid": lst["grid"], "wk32": lst["wk32"], "wk64": lst["wk64"],

@@ -182,9 +182,9 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
  *
  * precision = OICA_F32: the passes run on FP32 data (Xw of xw_t = OICA_F32).
  * precision = OICA_BF16: the passes run on BF16 data (Xw of xw_t = OICA_BF16;
- *   each row rounded once to BF16 while its steps are large, then carried as
- *   BF16 hi + lo parts (bf16_row_terms below), z^3 rounded to BF16, FP32 sums)
- *   with threshold tol_bf16, until every row has stopped, at most K/64 rows
+ *   by default each row carried as BF16 hi + lo parts, see bf16_row_terms;
+ *   z^3 rounded to BF16, FP32 sums) with threshold tol_bf16 (1e-3 leaves the
+ *   rest to the grouped FP32 passes), until every row has stopped, at most K/64 rows
  *   are left, or the active count has not shrunk over two polls.  Then every
  *   row that converged on BF16 data or was still moving continues on the FP32
  *   copy Xw_f32 (FP32 kernels, threshold tol) for up to
@@ -239,7 +239,13 @@ typedef struct {
                             the exact update of the rounded row.  3: form 1
                             while a row's last step is >= bf16_switch_step
                             (every row at the first pass; such a row never
-                            converges), then form 2.  0: the default (3). */
+                            converges), then form 2.  0: the default (2).
+                            Forms 1 and 3 move each row by about 2^-9 of
+                            itself per one-term pass, so a start near the
+                            boundary of a basin can end at another fixed
+                            point than on FP32 or FP64 data; form 2 does
+                            not.  The batched entry point has forms 1 and
+                            2 (3 runs as 2).                               */
   double bf16_switch_step; /* form 3's switch step (0 = 3e-2)             */
 } oica_fp_params;
 

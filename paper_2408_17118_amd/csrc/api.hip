@@ -321,13 +321,12 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
 // ---------------------------------------------------------------------------
 namespace {
 
-// The BF16 row form a run asks for (bf16_row_terms; 0 = the default, the
-// switched form).
+// The BF16 row form a run asks for (bf16_row_terms; 0 = the default, hi + lo).
 int bf16_form(const oica_fp_params *p) {
   switch (p->bf16_row_terms) {
     case 1: return BF_ONE;
-    case 2: return BF_HILO;
-    default: return BF_SWITCH;
+    case 3: return BF_SWITCH;
+    default: return BF_HILO;
   }
 }
 
@@ -1157,6 +1156,9 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     b.B = q.W_out;
     b.iters = q.iters;
     b.status = q.status;
+    // the batched form has the one-term and the hi + lo row forms (the
+    // switched form runs as hi + lo)
+    b.bf_one = (bf16 && bf16_form(params) == BF_ONE) ? 1 : 0;
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemsetAsync(ctl_base, 0, (size_t)D * 256 * 2, ctx->stream));
@@ -1392,6 +1394,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       b.ctl = c2;
       b.X = b.X32;
       b.ld = b.ld32;
+      b.bf_one = 0;
     }
     // the FP32 passes update few rows per problem: one 32-row block per wave,
     // and the thin items where few enough rows start

@@ -119,9 +119,9 @@ template <int NP, int WK>
 __device__ __noinline__ void call_f32(const ItemCtx &c, int kb, int sp, float *xs) {
   item_f32<NP, WK, false, false>(c, kb, sp, xs);
 }
-template <int NP, int WK>
+template <int NP, int WK, bool LO>
 __device__ __noinline__ void call_bf16(const ItemCtx &c, int kb, int sp, __bf16 *xs, __bf16 *xt) {
-  item_bf16<NP, WK, false>(c, kb, sp, xs, xt);   // no trajectories in the batched form
+  item_bf16<NP, WK, false, WAVES, LO>(c, kb, sp, xs, xt);   // no trajectories in the batched form
 }
 
 template <int NP>
@@ -181,14 +181,26 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
     } else {
       __bf16 *xs16 = reinterpret_cast<__bf16 *>(buf);
       __bf16 *xt16 = reinterpret_cast<__bf16 *>(buf + 2 * 128 * BSX * 2);
-      switch (b.variant) {
-        case 8: call_bf16<32, 1>(c, kb, sp, xs16, xt16); break;
-        case 9: call_bf16<32, 2>(c, kb, sp, xs16, xt16); break;
-        case 10: call_bf16<64, 1>(c, kb, sp, xs16, xt16); break;
-        case 11: call_bf16<64, 2>(c, kb, sp, xs16, xt16); break;
-        case 12: call_bf16<96, 1>(c, kb, sp, xs16, xt16); break;
-        case 14: call_bf16<128, 1>(c, kb, sp, xs16, xt16); break;
-        default: break;
+      if (b.bf_one) {
+        switch (b.variant) {
+          case 8: call_bf16<32, 1, false>(c, kb, sp, xs16, xt16); break;
+          case 9: call_bf16<32, 2, false>(c, kb, sp, xs16, xt16); break;
+          case 10: call_bf16<64, 1, false>(c, kb, sp, xs16, xt16); break;
+          case 11: call_bf16<64, 2, false>(c, kb, sp, xs16, xt16); break;
+          case 12: call_bf16<96, 1, false>(c, kb, sp, xs16, xt16); break;
+          case 14: call_bf16<128, 1, false>(c, kb, sp, xs16, xt16); break;
+          default: break;
+        }
+      } else {
+        switch (b.variant) {
+          case 8: call_bf16<32, 1, true>(c, kb, sp, xs16, xt16); break;
+          case 9: call_bf16<32, 2, true>(c, kb, sp, xs16, xt16); break;
+          case 10: call_bf16<64, 1, true>(c, kb, sp, xs16, xt16); break;
+          case 11: call_bf16<64, 2, true>(c, kb, sp, xs16, xt16); break;
+          case 12: call_bf16<96, 1, true>(c, kb, sp, xs16, xt16); break;
+          case 14: call_bf16<128, 1, true>(c, kb, sp, xs16, xt16); break;
+          default: break;
+        }
       }
     }
   }
@@ -264,8 +276,11 @@ __global__ __launch_bounds__(256) void k_epilogue_batched(const BatchDesc *__res
   const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
   const double bp1 = n1 < N ? (double)brow[n1] : 0.0;
   const double invT = 1.0 / (double)b.T;
-  g0 = n0 < N ? g0 * invT - 3.0 * bp0 : 0.0;
-  g1 = n1 < N ? g1 * invT - 3.0 * bp1 : 0.0;
+  // one-term form: the linear term on the BF16-rounded row the pass's z came from
+  const double bl0 = (b.bf_one && n0 < N) ? (double)(float)(__bf16)brow[n0] : bp0;
+  const double bl1 = (b.bf_one && n1 < N) ? (double)(float)(__bf16)brow[n1] : bp1;
+  g0 = n0 < N ? g0 * invT - 3.0 * bl0 : 0.0;
+  g1 = n1 < N ? g1 * invT - 3.0 * bl1 : 0.0;
   const double gn = sqrt(wave_sum(g0 * g0 + g1 * g1));
   if (!(gn > 0.0) || !isfinite(gn)) {
     if (lane == 0) b.status[row] = OICA_ROW_DEGENERATE;

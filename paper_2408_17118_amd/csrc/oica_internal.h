@@ -97,6 +97,7 @@ struct BatchDesc {
   long long T;
   long long ld, ld32;  // row strides of X and X32 (elements)
   int N, K, np, wk, kwg, n_sp, n_sub, variant;
+  int bf_one;          // BF16 passes on the BF16-rounded rows (one-term form)
 };
 
 // Batched FP32 variants from THIN_VARIANT on (+ np / 32 - 1), for problems

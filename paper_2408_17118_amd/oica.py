@@ -283,7 +283,7 @@ class Context:
 
     # ---- a4-a11, a14 ----------------------------------------------------------
     def fixed_point(self, Xw, W0, Xw_f32=None, max_iter=1000, tol=1e-6, precision="f32",
-                    tol_bf16=1e-5, refine_iters=5, traj_iters=0, check_every=4, profile=False,
+                    tol_bf16=1e-3, refine_iters=5, traj_iters=0, check_every=4, profile=False,
                     refine_groups=True, pruner=None, prune_pass=8, guard_top=0, guard_min=4,
                     bf16_row_terms=0, bf16_switch_step=0.0):
         _dev(Xw, "Xw", torch.bfloat16 if precision == "bf16" else torch.float32, (None, None))
@@ -315,9 +315,9 @@ class Context:
                 "pruned": int(st.pruned), "guard_tripped": int(st.guard_tripped)}
 
     def fixed_point_batched(self, problems, max_iter=1000, tol=1e-6, precision="f32",
-                            tol_bf16=1e-5, refine_iters=5, check_every=4, profile=False,
+                            tol_bf16=1e-3, refine_iters=5, check_every=4, profile=False,
                             autotune=True, cache_path=None, force_wk=0, force_grid=0,
-                            refine_groups=True):
+                            refine_groups=True, bf16_row_terms=0):
         """problems: list of dicts with device tensors Xw (N x T), W0 (K x N float32) and,
         for BF16 data, Xw_f32.  Returns (list of per-problem outputs, stats dict)."""
         D = len(problems)
@@ -342,7 +342,8 @@ class Context:
             outs.append(o)
         xw_t = OICA_BF16 if precision == "bf16" else OICA_F32
         p = FpParams(max_iter, tol, xw_t, tol_bf16, refine_iters, 0, check_every,
-                     1 if profile else 0, 1 if refine_groups else 0, None, 0, 0, 0)
+                     1 if profile else 0, 1 if refine_groups else 0, None, 0, 0, 0,
+                     bf16_row_terms)
         bp = BatchParams(1 if autotune else 0, cache_path.encode() if cache_path else None,
                          force_wk, force_grid)
         st = BatchStats()
@@ -388,7 +389,7 @@ class Context:
         return kurt
 
     # ---- deflation driver (Algorithm 2's outer loop) ------------------------------
-    def deflation(self, Xw, W0_blocks, max_iter=1000, tol=1e-6, precision="f32", tol_bf16=1e-5,
+    def deflation(self, Xw, W0_blocks, max_iter=1000, tol=1e-6, precision="f32", tol_bf16=1e-3,
                   refine_iters=5, tau=1e-3, check_every=4, gaussianity_test=True):
         """Xw: N x T float32 whitened data; W0_blocks: the start rows of every
         step, step i's block L x (N - i + 1) float32 (a list of N tensors, or
@@ -626,7 +627,7 @@ def get_option(option: int) -> int:
 
 
 def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_iter=1000,
-                 tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
+                 tau=1e-3, gaussianity_test=True, precision="f32", tol_bf16=1e-3, refine_iters=5,
                  profile=False, refine_groups=True, pruner=None, traj_iters=0, bf16_row_terms=0,
                  bf16_switch_step=0.0):
     """Whole hot path on device-resident raw data: whiten -> fixed point -> unique."""
@@ -643,7 +644,7 @@ def ordering_ica(ctx: Context, X: torch.Tensor, W0: torch.Tensor, tol=1e-6, max_
 
 
 def ordering_ica_deflation(ctx: Context, X: torch.Tensor, W0_blocks, tol=1e-6, max_iter=1000,
-                           tau=1e-3, precision="f32", tol_bf16=1e-5, refine_iters=5):
+                           tau=1e-3, precision="f32", tol_bf16=1e-3, refine_iters=5):
     """The paper's full method on device-resident raw data: whiten, then the
     deflation driver (one component per step).  Returns a dict with the
     components in whitened space (W), in raw-data space (W V, unit rows), the
@@ -657,7 +658,7 @@ def ordering_ica_deflation(ctx: Context, X: torch.Tensor, W0_blocks, tol=1e-6, m
 
 
 def ordering_ica_batched(ctx: Context, Xs, W0s, tol=1e-6, max_iter=1000, tau=1e-3,
-                         gaussianity_test=True, precision="f32", tol_bf16=1e-5, refine_iters=5,
+                         gaussianity_test=True, precision="f32", tol_bf16=1e-3, refine_iters=5,
                          profile=False, autotune=True, cache_path=None, refine_groups=True):
     """Whole hot path for many device-resident raw datasets: whiten each, one
     batched fixed point over all of them, unique set of each.  Returns (list of

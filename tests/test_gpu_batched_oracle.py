@@ -75,7 +75,7 @@ def compare_with_oracle(res, ref, label):
 def _run(ctx, Xs, W0s, precision):
     from paper_2408_17118_amd import oica
     res, st = oica.ordering_ica_batched(ctx, Xs, W0s, tol=1e-6, max_iter=1000, precision=precision,
-                                        tol_bf16=1e-5, refine_iters=5)
+                                        refine_iters=5)
     return res
 
 

@@ -80,7 +80,7 @@ def test_update_bf16_within_rounding_bound(ctx, N, T, K):
 def _run(ctx, p, precision):
     from paper_2408_17118_amd import oica
     return oica.ordering_ica(ctx, dev(p.X), dev(p.W0.astype(np.float32)), tol=1e-6, max_iter=1000,
-                             precision=precision, tol_bf16=1e-5, refine_iters=5)
+                             precision=precision, refine_iters=5)
 
 
 def _check_against(res, Ur_raw, ar, upsr, n_acc, label):

@@ -35,7 +35,7 @@ def runs():
     ctx = oica.Context(0)
     X = torch.from_numpy(p.X).cuda()
     W0 = torch.from_numpy(p.W0.astype(np.float32)).cuda()
-    r16 = oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, precision="bf16", tol_bf16=1e-5,
+    r16 = oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, precision="bf16",
                             refine_iters=5)
     r32 = oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, precision="f32")
     del X
