@@ -43,6 +43,7 @@ PEAK_HBM_GBS = 8000.0
 HBM_PROFILES = {
     "eeg_shaped_n64": os.path.join(ROOT, "profiles", "fused_update_eeg_shaped_n64_hbm_counters.txt"),
     "precision_n128": os.path.join(ROOT, "profiles", "fused_update_bf16_precision_n128_hbm_counters.txt"),
+    "batched_n16_128": os.path.join(ROOT, "profiles", "batched_n16_128_hbm_counters.txt"),
 }
 GOLDEN = os.path.join(ROOT, "tests", "golden", "{}_oracle.json")
 
@@ -89,6 +90,16 @@ def parse():
                     help="launch the all-rounds clustering without the cooperative-launch API "
                          "(profiling runs: the same kernel, a launch the profiler follows)")
     return ap.parse_args()
+
+
+def copy_calibration(dev):
+    """One plain 256 MiB device copy: the reference for the HBM counters."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_model() -> str:
@@ -191,11 +202,7 @@ def main():
         pruner = oica.Pruner(ctx, np.array(m["weights"], np.float32), m["feat_mean"], m["feat_std"])
         pruner.set_threshold(m["theta"])
     if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(dev)
 
     def step(profile=False):
         return oica.ordering_ica(ctx, X, W0, tol=1e-6, max_iter=1000, tau=1e-3, profile=profile,
@@ -340,6 +347,8 @@ def bench_batched(args):
         del p
         if len(Xs) % 16 == 0:
             print(f"generated {len(Xs)} datasets", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        copy_calibration(dev)
     ctx = oica.Context(0)
     kw = dict(tol=1e-6, max_iter=1000, tau=1e-3, precision="bf16", tol_bf16=1e-3, refine_iters=5)
 
@@ -404,7 +413,7 @@ def bench_batched(args):
             "peak": PEAK_BF16_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_MFMA_TFLOPS if achieved else None,
-            "traffic": None,
+            "traffic": counted_traffic("batched_n16_128"),
             "avg_launch_ms": upd_ms / launches if launches else None,
             "update_share_of_step": (upd_ms / args.steps) / ms_per_step,
         },
