@@ -239,14 +239,17 @@ typedef struct {
                             the exact update of the rounded row.  3: form 1
                             while a row's last step is >= bf16_switch_step
                             (every row at the first pass; such a row never
-                            converges), then form 2.  0: the default (2).
-                            Forms 1 and 3 move each row by about 2^-9 of
-                            itself per one-term pass, so a start near the
-                            boundary of a basin can end at another fixed
-                            point than on FP32 or FP64 data; form 2 does
-                            not.  The batched entry point has forms 1 and
-                            2 (3 runs as 2).                               */
-  double bf16_switch_step; /* form 3's switch step (0 = 3e-2)             */
+                            converges), then form 2.  4: form 2 while the
+                            row's last step is >= bf16_switch_step (every
+                            row at the first pass), then form 1.  0: the
+                            default (2).  Forms 1 and 3 move each row by
+                            about 2^-9 of itself per early one-term pass,
+                            so a start near the boundary of a basin can
+                            end at another fixed point than on FP32 or FP64
+                            data; forms 2 and 4 do not in the tests.  The
+                            batched entry point has forms 1 and 2 (3 and 4
+                            run as 2).                                     */
+  double bf16_switch_step; /* forms 3 and 4: switch step (0 = 3e-2)       */
 } oica_fp_params;
 
 typedef struct {         /* host */

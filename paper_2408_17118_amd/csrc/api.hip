@@ -326,6 +326,7 @@ int bf16_form(const oica_fp_params *p) {
   switch (p->bf16_row_terms) {
     case 1: return BF_ONE;
     case 3: return BF_SWITCH;
+    case 4: return BF_LATE;
     default: return BF_HILO;
   }
 }
@@ -341,8 +342,8 @@ int check_fp_params(oica_ctx *ctx, const oica_fp_params *p) {
   if (p->refine_iters < 0) return fail(ctx, OICA_E_ARG, "refine_iters must be >= 0");
   if (p->traj_iters < 0 || p->traj_iters > 16) return fail(ctx, OICA_E_ARG, "traj_iters must be in [0, 16]");
   if (p->check_every < 0) return fail(ctx, OICA_E_ARG, "check_every must be >= 0");
-  if (p->bf16_row_terms < 0 || p->bf16_row_terms > 3)
-    return fail(ctx, OICA_E_ARG, "bf16_row_terms must be 0, 1, 2 or 3");
+  if (p->bf16_row_terms < 0 || p->bf16_row_terms > 4)
+    return fail(ctx, OICA_E_ARG, "bf16_row_terms must be 0 to 4");
   if (p->bf16_switch_step < 0 || !isfinite(p->bf16_switch_step))
     return fail(ctx, OICA_E_ARG, "bf16_switch_step must be >= 0");
   return OICA_OK;
@@ -373,7 +374,7 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
   // (switched BF16 form: the active count plus the one-term count, so a row
   // that moves to the hi + lo form counts as progress).
   if (!bf16) bf_form = BF_HILO;
-  if (bf_form == BF_SWITCH && !fine_list) bf_form = BF_HILO;
+  if ((bf_form == BF_SWITCH || bf_form == BF_LATE) && !fine_list) bf_form = BF_HILO;
   int kmax = K;  // upper bound on the active count (it never grows)
   int stalled = 0;
   long long work_prev = 2LL * K + 1;
@@ -416,6 +417,9 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       // takes the hi + lo form from here on
       if (bf_form == BF_SWITCH)
         HIP_TRY(ctx, hipMemsetAsync(&ctl->kc[prune_pass & 1], 0, sizeof(int), ctx->stream));
+      if (bf_form == BF_LATE)  // every survivor in the head: hi + lo from here on
+        HIP_TRY(ctx, hipMemcpyAsync(&ctl->kc[prune_pass & 1], &ctl->kact[prune_pass & 1],
+                                    sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
     }
     if ((pass + 1) % check_every == 0 || pass + 1 == max_iter) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctl, sizeof(FpControl), hipMemcpyDeviceToHost,
@@ -424,7 +428,8 @@ int run_passes(oica_ctx *ctx, const FusedPlan &plan, int N, int64_t T, const voi
       const FpControl *h = (const FpControl *)ctx->small_host;
       const int left = h->kact[(pass + 1) & 1];
       if (left == 0) break;
-      const long long work = left + (bf_form == BF_SWITCH ? (long long)h->kc[(pass + 1) & 1] : 0LL);
+      const long long work =
+          left + ((bf_form == BF_SWITCH || bf_form == BF_LATE) ? (long long)h->kc[(pass + 1) & 1] : 0LL);
       stalled = (work >= work_prev) ? stalled + 1 : 0;
       work_prev = work;
       kmax = left;

@@ -204,11 +204,11 @@ __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
   const int kact = kact_dev ? kact_dev[pass & 1] : kact_host;
   // rows of the one-term form: the head of the list (read before block 0
   // resets the next pass's counters; kc of this pass is not written here)
-  const int kc = FORM == BF_SWITCH ? (pass == 0 ? kact : ctl->kc[pass & 1])
-                                   : (FORM == BF_ONE ? kact : 0);
+  const int kc = (FORM == BF_SWITCH || FORM == BF_LATE) ? (pass == 0 ? kact : ctl->kc[pass & 1])
+                                                        : (FORM == BF_ONE ? kact : 0);
   if (ctl && blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->kact[(pass + 1) & 1] = 0;
-    if (FORM == BF_SWITCH) ctl->kf = 0;
+    if (FORM == BF_SWITCH || FORM == BF_LATE) ctl->kf = 0;
     if (kact > 0) {
       ctl->passes = pass + 1;
       ctl->thread_iters += kact;
@@ -230,8 +230,9 @@ __global__ __launch_bounds__(bf16_waves(NP) * 64, 2) void k_fused_bf16(
     const int w_item = xcd * per_xcd_items + it;
     if (w_item >= work) break;
     const int kb = w_item % n_kb, sp = w_item / n_kb;
-    // every row of the item takes the one-term form
-    const bool one = ((kb + 1) * KWG < kact ? (kb + 1) * KWG : kact) <= kc;
+    // every row of the item takes the one-term form (BF_LATE: the list's tail)
+    const bool one = FORM == BF_LATE ? kb * KWG >= kc
+                                     : ((kb + 1) * KWG < kact ? (kb + 1) * KWG : kact) <= kc;
     if (FORM != BF_HILO && one) {
       if (s4part)
         item_bf16<NP, WK, true, NW, false>(c, kb, sp, xs, xt);
@@ -328,8 +329,8 @@ __global__ __launch_bounds__(256) void k_epilogue(
   constexpr int RS = NP + 1;
   const int kact = ctl->kact[pass & 1];
   // rows of the one-term BF16 form (head of the list), as the fused kernel saw them
-  const int kc = bf_form == BF_SWITCH ? (pass == 0 ? kact : ctl->kc[pass & 1])
-                                      : (bf_form == BF_ONE ? kact : 0);
+  const bool split = bf_form == BF_SWITCH || bf_form == BF_LATE;
+  const int kc = split ? (pass == 0 ? kact : ctl->kc[pass & 1]) : (bf_form == BF_ONE ? kact : 0);
   const int lane = threadIdx.x % 64;
   // rows_per_wave (<= EPI_ROWS) rows per wave, one after the other; the rows
   // that stay active are appended with one atomic per wave
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
   for (int r = 0; r < rows_per_wave && posn0 + r < kact; ++r) {
     const int posn = posn0 + r;
     const int row = act_cur[posn];
-    const bool one = posn < kc;
+    const bool one = bf_form == BF_LATE ? posn >= kc : posn < kc;
     double g0 = 0.0, g1 = 0.0, s4 = 0.0;
     // second stage: group sums in group order, EPI_U loads in flight per lane
     constexpr int EPI_U = 8;
@@ -401,7 +402,9 @@ __global__ __launch_bounds__(256) void k_epilogue(
       if (lane == r && (coarse || !(d < tol))) {
         stay = true;
         stay_row = row;
-        stay_one = coarse && !(d < switch_step);
+        // BF_SWITCH: stays one-term while the step is large; BF_LATE: takes
+        // the one-term form once the step is small (and keeps it)
+        stay_one = bf_form == BF_LATE ? (one || d < switch_step) : (coarse && !(d < switch_step));
       }
     }
     if (lane == 0 && pass < traj_iters) {
@@ -412,6 +415,9 @@ __global__ __launch_bounds__(256) void k_epilogue(
   if (bf_form == BF_SWITCH) {
     wave_append(stay && stay_one, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
     wave_append(stay && !stay_one, stay_row, fine_list, &ctl->kf);
+  } else if (bf_form == BF_LATE) {
+    wave_append(stay && !stay_one, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
+    wave_append(stay && stay_one, stay_row, fine_list, &ctl->kf);
   } else {
     wave_append(stay, stay_row, act_next, &ctl->kact[(pass + 1) & 1]);
   }
@@ -572,7 +578,7 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
   const int np = fused_np(N);
   if (bf16) {
     // the switched form needs the device counters (and a list to split)
-    if (bf_form == BF_SWITCH && (!ctl || !kact_dev)) bf_form = BF_HILO;
+    if ((bf_form == BF_SWITCH || bf_form == BF_LATE) && (!ctl || !kact_dev)) bf_form = BF_HILO;
     const bool wk1 = p.kwg == bf16_waves(np) * 32;  // one 32-row block per wave (narrow plan)
 #define OICA_BF16_LAUNCH(WKV, FV)                                                          \
   hipLaunchKernelGGL((k_fused_bf16<NP_, WKV, FV>), dim3(p.grid), dim3(bf16_waves(NP_) * 64), 0,  \
@@ -584,6 +590,8 @@ hipError_t launch_fused_update(hipStream_t st, const FusedPlan &p, int N, int64_
       OICA_BF16_LAUNCH(WKV, BF_ONE);         \
     else if (bf_form == BF_SWITCH)           \
       OICA_BF16_LAUNCH(WKV, BF_SWITCH);      \
+    else if (bf_form == BF_LATE)             \
+      OICA_BF16_LAUNCH(WKV, BF_LATE);        \
     else                                     \
       OICA_BF16_LAUNCH(WKV, BF_HILO);        \
   } while (0)
@@ -627,7 +635,7 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                            int32_t *iters, uint8_t *status, float *traj, int traj_iters,
                            const double *proj, int n_proj, int bf_form, double switch_step,
                            int *fine_list) {
-  if (bf_form == BF_SWITCH && !fine_list) bf_form = BF_HILO;
+  if ((bf_form == BF_SWITCH || bf_form == BF_LATE) && !fine_list) bf_form = BF_HILO;
   const int np = fused_np(N);
   OICA_NP_SWITCH(np, {
     hipLaunchKernelGGL((k_split_reduce<NP_>), dim3(RED_GRID), dim3(256), 0, st, p,
@@ -638,7 +646,7 @@ hipError_t launch_epilogue(hipStream_t st, const FusedPlan &p, int N, int64_t T,
                        (const double *)red, tol, iters, status, traj, traj_iters, rpw, proj,
                        n_proj, bf_form, switch_step, fine_list);
   });
-  if (bf_form == BF_SWITCH)
+  if (bf_form == BF_SWITCH || bf_form == BF_LATE)
     hipLaunchKernelGGL(k_join_fine, dim3(1), dim3(1024), 0, st, act_next, (const int *)fine_list,
                        ctl, pass);
   return hipGetLastError();

@@ -34,8 +34,11 @@ struct FpControl {
                           // the epilogue before they join the list's tail
   int pad2;
 };
-// How BF16 passes carry a row (the BF16 kernel's row form).
-enum BfRowForm { BF_ONE = 1, BF_HILO = 2, BF_SWITCH = 3 };
+// How BF16 passes carry a row (the BF16 kernel's row form).  BF_SWITCH: one
+// term while the row's step is large, then hi + lo; BF_LATE: hi + lo while the
+// step is large, then one term.  Both keep the active list as a head (the
+// first form) and a tail (the second).
+enum BfRowForm { BF_ONE = 1, BF_HILO = 2, BF_SWITCH = 3, BF_LATE = 4 };
 
 // Launch plan of the fused update kernel.  The grid is fixed for a whole run;
 // each work-group derives its (row block, sample split) from the active count

@@ -103,7 +103,7 @@ def run(lib):
     expect("fp traj", fpc(p=fp(traj_iters=17)), E_ARG)
     expect("fp traj null", fpc(p=fp(traj_iters=4)), E_ARG)
     expect("fp check_every", fpc(p=fp(check_every=-1)), E_ARG)
-    expect("fp row terms", fpc(p=fp(bf16_row_terms=4)), E_ARG)
+    expect("fp row terms", fpc(p=fp(bf16_row_terms=5)), E_ARG)
     expect("fp row terms neg", fpc(p=fp(bf16_row_terms=-1)), E_ARG)
     expect("fp switch step", fpc(p=fp(bf16_switch_step=-1.0)), E_ARG)
     expect("fp switch step inf", fpc(p=fp(bf16_switch_step=float("inf"))), E_ARG)

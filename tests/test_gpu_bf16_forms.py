@@ -1,8 +1,8 @@
 """The three row forms of the BF16 passes (bf16_row_terms): 1 = the row rounded
 once to BF16 and the linear term on the same rounded row, 2 = hi + lo BF16
 parts with the linear term on the FP32 row, 3 = form 1 while a row's last
-step is large, then form 2; 0 = the default (form 2; the Python entry points
-default to tol_bf16 = 1e-3).
+step is large, then form 2, 4 = form 2 while the step is large, then form 1;
+0 = the default (form 2; the Python entry points default to tol_bf16 = 1e-3).
 
 * One pass of form 1 is the update (eqs. 4-5) of the BF16-rounded row: its
   output equals the normalised G of the single-update entry point given the
@@ -74,7 +74,8 @@ def test_one_term_pass_is_update_of_rounded_row(ctx, N, T, K):
     assert np.median(np.linalg.norm(W1 - sgn * Gxn, axis=1)) > 50 * 2e-6
 
 
-@pytest.mark.parametrize("form,tol_bf16", [(0, 1e-3), (1, 1e-5), (2, 1e-5), (3, 1e-5), (2, 1e-3)])
+@pytest.mark.parametrize("form,tol_bf16", [(0, 1e-3), (1, 1e-5), (2, 1e-5), (3, 1e-5), (2, 1e-3),
+                                           (4, 1e-3)])
 def test_row_forms_match_oracle_eeg_shaped(form, tol_bf16):
     from paper_2408_17118_amd import oica
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
