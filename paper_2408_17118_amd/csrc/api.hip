@@ -520,7 +520,15 @@ static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oic
     q.ld = ld32;
     return q;
   };
-  const size_t gfl = fp_workspace_floats(plan, N, K);
+  // the partial and reduction buffers serve every plan of the run: the BF16
+  // passes' and, for BF16 runs, the FP32 finish's and the kurtosis pass's
+  size_t gfl = fp_workspace_floats(plan, N, K);
+  size_t red_n = fp_reduce_doubles(plan, N, K);
+  if (bf16) {
+    const FusedPlan p32 = plan_f32();
+    gfl = std::max(gfl, fp_workspace_floats(p32, N, K));
+    red_n = std::max(red_n, fp_reduce_doubles(p32, N, K));
+  }
   const int np = fused_np(N);
   const size_t rows_max = gfl / np;
   const int gcap = guard_top > 0 ? guard_top + 64 : K;  // room for the ties / every cluster
@@ -528,7 +536,6 @@ static int fixed_point_impl(oica_ctx *ctx, int N, int64_t T, const void *Xw, oic
   need += gfl * sizeof(float) + 256;            // gpart
   need += rows_max * sizeof(float) + 256;       // s4part
   need += rows_max * sizeof(double) + 256;      // s4part64 (kurtosis)
-  const size_t red_n = fp_reduce_doubles(plan, N, K);
   need += red_n * sizeof(double) + 256;         // split-group sums
   need += 6 * ((size_t)K * sizeof(int) + 256);  // act lists, kurtosis list, prune survivors,
                                                 // rows entering the BF16 hi + lo form
