@@ -1029,6 +1029,24 @@ void set_thin(BatchDesc &b) {
 // splits, rows padded to 32) must fit the buffers sized for K + 256 rows.
 int thin_max_rows(int K) { return K >= 256 ? 128 : 32; }
 
+// Thin items of a problem with at most two row blocks left take twice the
+// splits again (each wave walks half the samples, so a pass that only such
+// problems still run finishes sooner), when the doubled splits' partials fit
+// the buffers: 2 THIN_SPLITS x padded rows <= K + 256 per split of the
+// problem's own partition, and their first-stage sums (groups x active rows)
+// within red_doubles.  Returns whether the shape changed.
+size_t red_doubles(int n_sp, int K, int np);
+bool thin_wider(BatchDesc &b, int kd) {
+  const int base = batch_splits(b.T);
+  if (b.variant < THIN_VARIANT || b.n_sp != THIN_SPLITS * base || kd > 64 || kd <= 0) return false;
+  const int wide = 2 * THIN_SPLITS * base;
+  if ((size_t)wide * 32 * ((kd + 31) / 32) > (size_t)base * (b.K + 256)) return false;
+  const size_t groups = (size_t)(wide + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST;
+  if (groups * (size_t)kd * (size_t)(b.np + 1) > red_doubles(base, b.K, b.np)) return false;
+  b.n_sp = wide;
+  return true;
+}
+
 // First-stage reduction sums of one problem: enough for the regular shapes
 // (up to K rows) and for the thin ones.
 size_t red_doubles(int n_sp, int K, int np) {
@@ -1302,6 +1320,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
             set_thin(hd[d]);
             reshaped = true;
           }
+          if (!data_bf16 && thin_wider(hd[d], kd)) reshaped = true;
           // BF16, few rows: THIN_SPLITS times the splits (shorter items, so the
           // long latency-bound items of a few problems no longer set the pass);
           // the partial buffers (K + 256 rows per split) must hold the
@@ -1414,10 +1433,13 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     HIP_TRY(ctx, hipMemcpyAsync(ctl_host.data() + (size_t)D * 256, ctl_base + (size_t)D * 256,
                                 (size_t)D * 256, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    for (int d = 0; d < D; ++d)
-      if (((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->kact[0] <=
-          thin_max_rows(hd[d].K))
+    for (int d = 0; d < D; ++d) {
+      const int k0 = ((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->kact[0];
+      if (k0 <= thin_max_rows(hd[d].K)) {
         set_thin(hd[d]);
+        thin_wider(hd[d], k0);
+      }
+    }
     HIP_TRY(ctx, hipMemcpyAsync(ddesc, hd.data(), (size_t)D * sizeof(BatchDesc),
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
