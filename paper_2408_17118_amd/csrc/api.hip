@@ -1029,17 +1029,18 @@ void set_thin(BatchDesc &b) {
 // splits, rows padded to 32) must fit the buffers sized for K + 256 rows.
 int thin_max_rows(int K) { return K >= 256 ? 128 : 32; }
 
-// Thin items of a problem with at most two row blocks left take twice the
-// splits again (each wave walks half the samples, so a pass that only such
-// problems still run finishes sooner), when the doubled splits' partials fit
-// the buffers: 2 THIN_SPLITS x padded rows <= K + 256 per split of the
-// problem's own partition, and their first-stage sums (groups x active rows)
-// within red_doubles.  Returns whether the shape changed.
+// Thin items of a problem with at most two row blocks left take four times the
+// splits again (each wave walks a quarter of the samples, so a pass that only
+// such problems still run finishes sooner; twice was 1 % slower on the
+// many-dataset workload), when those splits' partials fit the buffers:
+// 4 THIN_SPLITS x padded rows <= K + 256 per split of the problem's own
+// partition, and their first-stage sums (groups x active rows) within
+// red_doubles.  Returns whether the shape changed.
 size_t red_doubles(int n_sp, int K, int np);
 bool thin_wider(BatchDesc &b, int kd) {
   const int base = batch_splits(b.T);
   if (b.variant < THIN_VARIANT || b.n_sp != THIN_SPLITS * base || kd > 64 || kd <= 0) return false;
-  const int wide = 2 * THIN_SPLITS * base;
+  const int wide = 4 * THIN_SPLITS * base;
   if ((size_t)wide * 32 * ((kd + 31) / 32) > (size_t)base * (b.K + 256)) return false;
   const size_t groups = (size_t)(wide + SPLIT_GROUP_HOST - 1) / SPLIT_GROUP_HOST;
   if (groups * (size_t)kd * (size_t)(b.np + 1) > red_doubles(base, b.K, b.np)) return false;
