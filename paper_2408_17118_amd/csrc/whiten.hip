@@ -237,56 +237,118 @@ __device__ __forceinline__ void cov_part_body(const WJob &j, int c, double *lds)
 // N > 64 (5 to 8 row blocks, up to 36 block pairs): the four waves split the
 // block pairs instead of the samples (wave w forms the pairs p = w mod 4 of
 // the bi <= bj enumeration over every sample of the chunk, at most 9
-// accumulators) and each writes its own entries.  Operands are read six steps
-// ahead; the waves read the same X rows, mostly from L1.
+// accumulators) and each writes its own entries.  The chunk passes through
+// LDS in tiles of COV_TS samples, stored as X - mean in FP64 (rows past N and
+// samples past the chunk as zero), in two buffers: the work-group's loads of
+// tile i + 1 (4 consecutive samples of a row per thread, so 8 threads read one
+// row's 32 samples) are issued before the MFMAs of tile i and written to the
+// other buffer after them, with one barrier per tile, so no load is still in
+// flight at the loop's back-edge (a prefetch carried in registers across it
+// was waited for at every iteration).  Step s of a tile takes samples
+// tb + 4 s + (0..3), the order of a walk over the chunk in steps of four.
+constexpr int COV_TS = 32;   // samples per tile
+// LDS row stride in doubles, 2 mod 32: the 16 rows x 4 samples of an operand
+// read fall in distinct banks
+constexpr int COV_LDR = COV_TS + 2;
+static size_t cov_tile_lds_bytes(int N) {
+  const int nrb = (N + 15) / 16;
+  return (size_t)2 * 16 * nrb * COV_LDR * sizeof(double);
+}
+template <typename TIN> struct Vec4;
+template <> struct Vec4<float> {
+  // dword alignment is all a multi-dword global load needs
+  typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <> struct Vec4<double> {
+  typedef double type __attribute__((ext_vector_type(4), aligned(8)));
+};
 template <int NRB, int PH, typename TIN>
-__device__ __forceinline__ void cov_pairs_body(const WJob &j, int c) {
+__device__ __forceinline__ void cov_pairs_body(const WJob &j, int c, double *lds) {
   typedef __attribute__((address_space(1))) const TIN gin;
+  typedef __attribute__((address_space(1))) const typename Vec4<TIN>::type gin4;
+  constexpr int NP = 16 * NRB;
   constexpr int NPAIR = NRB * (NRB + 1) / 2;
   constexpr int NMINE = (NPAIR - PH + 3) / 4;
+  constexpr int SPT = COV_TS / 4;       // threads per row of a tile
+  constexpr int RSTEP = 256 / SPT;      // rows staged per pass of the work-group
+  constexpr int RPT = (NP + RSTEP - 1) / RSTEP;
   const int N = j.N;
   const long long T = j.T;
   const long long t0 = (long long)c * T / j.cch, t1 = (long long)(c + 1) * T / j.cch;
   gin *X = (gin *)j.X;
   const long long ldx = j.ld;
-  const int lane = threadIdx.x % 64;
+  const int tid = threadIdx.x, lane = tid % 64;
   const int rr = lane % 16, q = lane / 16;
-  double mu[NRB];
-  gin *xr[NRB];
+  const int sr = tid / SPT, sj = tid % SPT;  // staging: rows sr + RSTEP i, samples 4 sj .. 4 sj + 3
+  double smu[RPT];
 #pragma unroll
-  for (int b = 0; b < NRB; ++b) {
-    const int r = b * 16 + rr < N ? b * 16 + rr : N - 1;
-    mu[b] = j.mean[r];
-    xr[b] = X + (size_t)r * (size_t)ldx;
+  for (int i = 0; i < RPT; ++i) {
+    const int row = sr + RSTEP * i;
+    smu[i] = row < N ? j.mean[row] : 0.0;
   }
-  // step s of the chunk covers samples t0 + 4 s + (0..3); lane takes t0 + 4 s + q
-  const long long nsteps = (t1 - t0 + 3) / 4;
-  auto load = [&](long long st, int b) -> double {
-    long long m = t0 + 4 * st + q;
-    if (m > t1 - 1) m = t1 - 1;
-    return (double)xr[b][m];
+  // rows past N load row N - 1 (stored as zero)
+  gin *srow[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = sr + RSTEP * i;
+    srow[i] = X + (size_t)(row < N ? row : N - 1) * (size_t)ldx;
+  }
+  TIN reg[RPT][4];
+  // a whole tile inside the chunk: one vector load per row, no branch
+  auto load_full = [&](long long tb) {
+    const size_t m = (size_t)(tb + 4 * sj);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const typename Vec4<TIN>::type v = *(gin4 *)(srow[i] + m);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) reg[i][e] = v[e];
+    }
+  };
+  // the chunk's last, partial tile: element loads at indices clamped into it
+  auto load_tail = [&](long long tb) {
+    const long long m = tb + 4 * sj;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) reg[i][e] = srow[i][m + e < t1 ? m + e : t1 - 1];
+  };
+  auto store_tile = [&](double *buf, long long tb) {
+    const long long m = tb + 4 * sj;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = sr + RSTEP * i;
+      if (RSTEP * i + RSTEP <= NP || row < NP) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          buf[row * COV_LDR + 4 * sj + e] =
+              row < N && m + e < t1 ? (double)reg[i][e] - smu[i] : 0.0;
+      }
+    }
   };
   cov_f64x4 acc[NMINE];
 #pragma unroll
   for (int p = 0; p < NMINE; ++p) acc[p] = cov_f64x4{0.0, 0.0, 0.0, 0.0};
-  // operands PD steps ahead: a step is at most 9 MFMAs, and at one wave per
-  // SIMD the first touch of a sample comes from HBM
-  constexpr int PD = 6;
-  double buf[PD][NRB];
+  double *buf0 = lds, *buf1 = lds + NP * COV_LDR;
+  // nfull whole tiles, then at most one partial tile (work-group uniform)
+  const long long nfull = (t1 - t0) / COV_TS;
+  const long long ntiles = nfull + ((t1 - t0) % COV_TS != 0);
+  if (ntiles > 0) {
+    if (nfull > 0) load_full(t0);
+    else load_tail(t0);
+    store_tile(buf0, t0);
+  }
+  __syncthreads();
+  for (long long it = 0; it < ntiles; ++it) {
+    const long long tb = t0 + it * COV_TS;
+    const double *cur = (it & 1) ? buf1 : buf0;
+    double *nxt = (it & 1) ? buf0 : buf1;
+    if (it + 1 < nfull) load_full(tb + COV_TS);
+    else if (it + 1 < ntiles) load_tail(tb + COV_TS);
 #pragma unroll
-  for (int h = 0; h < PD; ++h)
-#pragma unroll
-    for (int b = 0; b < NRB; ++b) buf[h][b] = load(h, b);
-  for (long long st = 0; st < nsteps; st += PD) {
-#pragma unroll
-    for (int h = 0; h < PD; ++h) {
-      const long long m = t0 + 4 * (st + h) + q;
+    for (int s = 0; s < COV_TS / 4; ++s) {
       double v[NRB];
 #pragma unroll
-      for (int b = 0; b < NRB; ++b) {
-        v[b] = m < t1 ? buf[h][b] - mu[b] : 0.0;
-        buf[h][b] = load(st + h + PD, b);
-      }
+      for (int b = 0; b < NRB; ++b) v[b] = cur[(16 * b + rr) * COV_LDR + 4 * s + q];
       int p = 0, mine = 0;
 #pragma unroll
       for (int bi = 0; bi < NRB; ++bi)
@@ -296,8 +358,9 @@ __device__ __forceinline__ void cov_pairs_body(const WJob &j, int c) {
             acc[mine] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[bi], v[bj], acc[mine], 0, 0, 0);
             ++mine;
           }
-      __builtin_amdgcn_sched_barrier(0);
     }
+    if (it + 1 < ntiles) store_tile(nxt, tb + COV_TS);
+    __syncthreads();
   }
   int p = 0, mine = 0;
 #pragma unroll
@@ -315,12 +378,12 @@ __device__ __forceinline__ void cov_pairs_body(const WJob &j, int c) {
 }
 
 template <int NRB, typename TIN>
-__device__ __forceinline__ void cov_pairs(const WJob &j, int c) {
+__device__ __forceinline__ void cov_pairs(const WJob &j, int c, double *lds) {
   switch (threadIdx.x / 64) {
-    case 0: cov_pairs_body<NRB, 0, TIN>(j, c); break;
-    case 1: cov_pairs_body<NRB, 1, TIN>(j, c); break;
-    case 2: cov_pairs_body<NRB, 2, TIN>(j, c); break;
-    default: cov_pairs_body<NRB, 3, TIN>(j, c); break;
+    case 0: cov_pairs_body<NRB, 0, TIN>(j, c, lds); break;
+    case 1: cov_pairs_body<NRB, 1, TIN>(j, c, lds); break;
+    case 2: cov_pairs_body<NRB, 2, TIN>(j, c, lds); break;
+    default: cov_pairs_body<NRB, 3, TIN>(j, c, lds); break;
   }
 }
 
@@ -331,12 +394,11 @@ template <int RB, typename TIN>
 __device__ __forceinline__ void cov_dispatch(const WJob &j, int c, double *lds) {
   const int nrb = (j.N + 15) / 16;
   if constexpr (RB == 8) {
-    (void)lds;
     switch (nrb) {
-      case 5: cov_pairs<5, TIN>(j, c); break;
-      case 6: cov_pairs<6, TIN>(j, c); break;
-      case 7: cov_pairs<7, TIN>(j, c); break;
-      default: cov_pairs<8, TIN>(j, c); break;
+      case 5: cov_pairs<5, TIN>(j, c, lds); break;
+      case 6: cov_pairs<6, TIN>(j, c, lds); break;
+      case 7: cov_pairs<7, TIN>(j, c, lds); break;
+      default: cov_pairs<8, TIN>(j, c, lds); break;
     }
   } else {
     switch (nrb) {
@@ -348,9 +410,12 @@ __device__ __forceinline__ void cov_dispatch(const WJob &j, int c, double *lds) 
   }
 }
 
+// RB = 8: two work-groups per CU (the tile buffers take 68 KiB of LDS each)
 template <int RB>
-__global__ __launch_bounds__(256) void k_cov_part(const WJob *__restrict__ jobs, WJob one,
-                                                  const int *__restrict__ start, int D) {
+__global__ __launch_bounds__(256, RB == 8 ? 2 : 1) void k_cov_part(const WJob *__restrict__ jobs,
+                                                                   WJob one,
+                                                                   const int *__restrict__ start,
+                                                                   int D) {
   extern __shared__ double cov_lds[];
   int c = blockIdx.x;
   const int d = start ? job_of(start, D, c) : 0;
@@ -363,7 +428,7 @@ __global__ __launch_bounds__(256) void k_cov_part(const WJob *__restrict__ jobs,
 // Dynamic LDS of k_cov_part<RB> for problems up to n_max features.
 template <int RB>
 static size_t cov_prepare(int n_max) {
-  const size_t lds = cov_lds_bytes(n_max);
+  const size_t lds = RB == 8 ? cov_tile_lds_bytes(n_max) : cov_lds_bytes(n_max);
   (void)hipFuncSetAttribute((const void *)k_cov_part<RB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
