@@ -766,32 +766,53 @@ __global__ void k_canon(const WJob *__restrict__ jobs, WJob one) {
 // (no intermediate FP32 rounding).
 __device__ inline uint16_t bf16_rne(double x) {
   const unsigned long long u = __double_as_longlong(x);
-  const unsigned long long sign = u >> 63;
+  const unsigned sgn = (unsigned)(u >> 63) << 15;
   const int exp = (int)((u >> 52) & 0x7FF);
-  if (exp == 0) return (uint16_t)(sign << 15);                     // zero / subnormal -> signed 0
-  if (exp == 0x7FF) return (uint16_t)((sign << 15) | 0x7FC0);       // Inf/NaN (data is finite)
   const unsigned long long mag = u & 0x7FFFFFFFFFFFFFFFull;
   const unsigned long long lsb = (mag >> 45) & 1ull;
   const unsigned long long r = (mag + 0x0FFFFFFFFFFFull + lsb) >> 45;  // 11-bit exp : 7-bit mant
-  int e = (int)(r >> 7) - 1023 + 127;
-  const int mant = (int)(r & 0x7F);
-  if (e <= 0) return (uint16_t)(sign << 15);
-  if (e >= 255) return (uint16_t)((sign << 15) | 0x7F80);
-  return (uint16_t)((sign << 15) | ((unsigned)e << 7) | (unsigned)mant);
+  const int e = (int)(r >> 7) - 1023 + 127;
+  // the normal result is r with its exponent rebiased; the special cases
+  // replace it through masks (a select chain here was compiled to branches):
+  // zero / subnormal input or underflow -> signed 0, overflow -> Inf,
+  // Inf/NaN input -> NaN (the data are finite)
+  const unsigned norm = sgn | (unsigned)(r - ((1023ull - 127ull) << 7));
+  const unsigned m_zero = 0u - (unsigned)((exp == 0) | (e <= 0));
+  const unsigned m_inf = 0u - (unsigned)(e >= 255);
+  const unsigned m_nan = 0u - (unsigned)(exp == 0x7FF);
+  unsigned v = norm;
+  v = (v & ~m_inf) | ((sgn | 0x7F80u) & m_inf);
+  v = (v & ~m_zero) | (sgn & m_zero);
+  v = (v & ~m_nan) | ((sgn | 0x7FC0u) & m_nan);
+  return (uint16_t)v;
 }
 
 // Xw = Wh (X - mu) on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register r holds
 // D[l / 16 + 4 r][l % 16]).  A work-group takes apply_cols(N) consecutive
-// samples of one problem (1024 for N > 64, where loading Wh into LDS costs
-// the most; 256 below, so that short problems still spread over the CUs).  Wh, zero-padded to 16 * NRB rows and columns, sits in LDS
-// with a row stride of 2 mod 32 doubles, so the 16 rows x 2 columns that one
-// A-operand read touches per half-wave fall in distinct banks.  Each wave
-// takes 16-sample column blocks in turn; its B operands (4 features x 16
-// samples of X per step, less the means) come straight from global memory
-// into registers, the next block's loads issued before the current block's
-// MFMAs, so the reduction over features needs no barrier.  A problem's work
-// items are numbered in sample order.
+// samples of one problem (1024 for N > 64; 256 below, so that short problems
+// still spread over the CUs); a problem's work items are numbered in sample
+// order.  Every output accumulates the feature steps 0, 1, ... in order from
+// zero, as a single dot product would, in both forms:
+//   N <= 64 (apply_stream_body): Wh, zero-padded to 16 * NRB rows and
+//     columns, sits in LDS with a row stride of 2 mod 32 doubles (the 16 rows
+//     x 2 columns of one A-operand read per half-wave fall in distinct banks).
+//     Each wave takes 16-sample column blocks in turn; its B operands (4
+//     features x 16 samples of X per step, less the means) come straight from
+//     global memory into registers, the next block's loads issued before the
+//     current block's MFMAs, so the reduction over features needs no barrier.
+//   N > 64 (apply_tiled_body): wave w keeps the A operands of row blocks w and
+//     w + 4 of Wh in registers for the whole item (64 doubles per lane) and
+//     takes both 16-sample blocks of each 32-sample tile.  The samples pass
+//     through LDS as X - mu in FP64, sample-major with a row stride of 2 mod
+//     32 doubles (the 16 samples x 2 features of one B-operand read per
+//     half-wave fall in distinct banks; features past N and samples past the
+//     item are zero), in two buffers: the work-group's loads of the next tile
+//     (4 consecutive samples of a feature per thread) are issued before the
+//     current tile's MFMAs and written to the other buffer after them and
+//     after the current tile's outputs, one barrier per tile.  One B read
+//     serves two MFMAs, and two waves fit on a SIMD.  (For N <= 64 the tiles
+//     hold too little MFMA work per barrier: measured slower there.)
 constexpr int AP_MAX_RB = NMAX / 16;
 __host__ __device__ constexpr int apply_cols(int N) { return N > 64 ? 1024 : 256; }
 static inline int apply_tiles(int N, long long T) {
@@ -800,14 +821,16 @@ static inline int apply_tiles(int N, long long T) {
 __host__ __device__ constexpr int wh_ld(int nrb) {
   return nrb * 16 + ((2 - (nrb * 16) % 32) + 32) % 32;
 }
+constexpr int AP_TS = 32;  // samples per tile of the tiled form
 static size_t apply_lds_bytes(int N) {
   const int nrb = (N + 15) / 16;
-  return ((size_t)wh_ld(nrb) * nrb * 16 + (size_t)nrb * 16) * sizeof(double);
+  if (nrb > 4) return (size_t)2 * AP_TS * wh_ld(nrb) * sizeof(double);  // two tiles
+  return ((size_t)wh_ld(nrb) * nrb * 16 + (size_t)nrb * 16) * sizeof(double);  // Wh, means
 }
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <int NRB, typename TIN>
-__device__ __forceinline__ void apply_body(const WJob &j, int item, double *lds) {
+__device__ __forceinline__ void apply_stream_body(const WJob &j, int item, double *lds) {
   typedef __attribute__((address_space(1))) const TIN gin;
   typedef __attribute__((address_space(1))) float gf32;
   typedef __attribute__((address_space(1))) uint16_t gu16;
@@ -907,6 +930,153 @@ __device__ __forceinline__ void apply_body(const WJob &j, int item, double *lds)
   }
 }
 
+template <int NRB, typename TIN>
+__device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double *lds) {
+  typedef __attribute__((address_space(1))) const TIN gin;
+  typedef __attribute__((address_space(1))) const typename Vec4<TIN>::type gin4;
+  typedef __attribute__((address_space(1))) float gf32;
+  typedef __attribute__((address_space(1))) uint16_t gu16;
+  static_assert(NRB > 4, "the tiled form takes N > 64");
+  constexpr int NP = NRB * 16;
+  constexpr int NK = NRB * 4;          // steps of 4 features
+  constexpr int LDF = wh_ld(NRB);      // tile row stride (one row per sample)
+  constexpr int TS = AP_TS;            // samples per tile
+  constexpr int RBW = 2;               // row blocks per wave
+  constexpr int SBW = TS / 16;         // 16-sample blocks per wave and tile
+  constexpr int SPT = TS / 4;          // staging threads per feature
+  constexpr int FSTEP = 256 / SPT;     // features staged per pass of the work-group
+  constexpr int FPT = (NP + FSTEP - 1) / FSTEP;
+  gin *X = (gin *)j.X;
+  gf32 *o32 = (gf32 *)j.o32, *o32b = (gf32 *)j.o32b;
+  gu16 *obf = (gu16 *)j.obf;
+  const int N = j.N;
+  const int n_out = j.n_out > 0 ? j.n_out : N;
+  const long long T = j.T;
+  const long long ldx = j.ld;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);  // uniform: row blocks in SGPRs
+  const int li = lane % 16, lk = lane / 16;
+  const long long m_item = (long long)item * apply_cols(NP);
+  long long m_end = m_item + apply_cols(NP);
+  if (m_end > T) m_end = T;
+  // this wave's row blocks; a row block past NRB (NRB < 8, waves w + 4 >=
+  // NRB) multiplies zeros and stores nothing, in the time the wave would
+  // otherwise wait at the tile barrier
+  int rbw[RBW];
+#pragma unroll
+  for (int i = 0; i < RBW; ++i) rbw[i] = wave + 4 * i;
+  const int sb0 = 0;
+  // A operands: wa[i][s] = Wh[16 rb + li][4 s + lk], read at clamped indices
+  // and zeroed past N
+  const double *Wh = j.Wh;
+  double wa[RBW][NK];
+#pragma unroll
+  for (int i = 0; i < RBW; ++i) {
+    const int row = rbw[i] * 16 + li;
+    const int rowc = row < N ? row : N - 1;
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      const int col = 4 * s + lk;
+      const double w = Wh[rowc * N + (col < N ? col : N - 1)];
+      wa[i][s] = row < N && col < N ? w : 0.0;
+    }
+  }
+  // staging: features sf + FSTEP i, samples 4 sj .. 4 sj + 3 of a tile;
+  // features past N load feature N - 1 (stored as zero)
+  const int sf = tid / SPT, sj = tid % SPT;
+  double smu[FPT];
+  gin *srow[FPT];
+#pragma unroll
+  for (int i = 0; i < FPT; ++i) {
+    const int f = sf + FSTEP * i;
+    smu[i] = f < N ? j.mean[f] : 0.0;
+    srow[i] = X + (size_t)(f < N ? f : N - 1) * (size_t)ldx;
+  }
+  TIN reg[FPT][4];
+  auto load_full = [&](long long tb) {
+    const size_t m = (size_t)(tb + 4 * sj);
+#pragma unroll
+    for (int i = 0; i < FPT; ++i) {
+      const typename Vec4<TIN>::type v = *(gin4 *)(srow[i] + m);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) reg[i][e] = v[e];
+    }
+  };
+  auto load_tail = [&](long long tb) {
+    const long long m = tb + 4 * sj;
+#pragma unroll
+    for (int i = 0; i < FPT; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) reg[i][e] = srow[i][m + e < m_end ? m + e : m_end - 1];
+  };
+  auto store_tile = [&](double *buf, long long tb) {
+    const long long m = tb + 4 * sj;
+#pragma unroll
+    for (int i = 0; i < FPT; ++i) {
+      const int f = sf + FSTEP * i;
+      if (FSTEP * i + FSTEP <= NP || f < NP) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          buf[(4 * sj + e) * LDF + f] = f < N && m + e < m_end ? (double)reg[i][e] - smu[i] : 0.0;
+      }
+    }
+  };
+  double *buf0 = lds, *buf1 = lds + TS * LDF;
+  const long long nfull = (m_end - m_item) / TS;
+  const long long ntiles = nfull + ((m_end - m_item) % TS != 0);
+  if (ntiles > 0) {
+    if (nfull > 0) load_full(m_item);
+    else load_tail(m_item);
+    store_tile(buf0, m_item);
+  }
+  __syncthreads();
+  for (long long it = 0; it < ntiles; ++it) {
+    const long long tb = m_item + it * TS;
+    const double *cur = (it & 1) ? buf1 : buf0;
+    double *nxt = (it & 1) ? buf0 : buf1;
+    if (it + 1 < nfull) load_full(tb + TS);
+    else if (it + 1 < ntiles) load_tail(tb + TS);
+#pragma unroll
+    for (int jb = 0; jb < SBW; ++jb) {
+      const int sb = sb0 + jb;
+      f64x4 acc[RBW];
+#pragma unroll
+      for (int i = 0; i < RBW; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        const double bv = cur[(sb * 16 + li) * LDF + 4 * s + lk];
+#pragma unroll
+        for (int i = 0; i < RBW; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[i][s], bv, acc[i], 0, 0, 0);
+      }
+      const long long m = tb + sb * 16 + li;
+      // an opaque copy of the lane's row offset, so that the output rows'
+      // 64-bit offsets are formed here rather than all kept live
+      int lko = lk;
+      asm volatile("" : "+v"(lko));
+      const bool all_m = tb + sb * 16 + 16 <= m_end;  // work-group uniform
+#pragma unroll
+      for (int i = 0; i < RBW; ++i) {
+        // every row of the block stored (wave uniform); a block past NRB
+        // stores nothing, its rows being past n_out
+        const bool all_r = rbw[i] * 16 + 16 <= n_out;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rbw[i] * 16 + lko + 4 * r;
+          if (!(all_m && all_r) && (m >= m_end || row >= n_out)) continue;
+          const size_t o = (size_t)row * (size_t)T + (size_t)m;
+          const double v = acc[i][r];
+          if (o32) o32[o] = (float)v;
+          if (obf) obf[o] = bf16_rne(v);
+          if (o32b) o32b[o] = (float)v;
+        }
+      }
+    }
+    if (it + 1 < ntiles) store_tile(nxt, tb + TS);
+    __syncthreads();
+  }
+}
+
 // BIG: the kernel for N > 64 (5 to 8 row blocks); the other takes N <= 64,
 // so each has the register budget of its own row-block counts.
 template <bool BIG, typename TIN>
@@ -914,24 +1084,25 @@ __device__ __forceinline__ void apply_dispatch(const WJob &j, int item, double *
   const int nrb = (j.N + 15) / 16;
   if constexpr (BIG) {
     switch (nrb) {
-      case 5: apply_body<5, TIN>(j, item, lds); break;
-      case 6: apply_body<6, TIN>(j, item, lds); break;
-      case 7: apply_body<7, TIN>(j, item, lds); break;
-      default: apply_body<8, TIN>(j, item, lds); break;
+      case 5: apply_tiled_body<5, TIN>(j, item, lds); break;
+      case 6: apply_tiled_body<6, TIN>(j, item, lds); break;
+      case 7: apply_tiled_body<7, TIN>(j, item, lds); break;
+      default: apply_tiled_body<8, TIN>(j, item, lds); break;
     }
   } else {
     switch (nrb) {
-      case 1: apply_body<1, TIN>(j, item, lds); break;
-      case 2: apply_body<2, TIN>(j, item, lds); break;
-      case 3: apply_body<3, TIN>(j, item, lds); break;
-      default: apply_body<4, TIN>(j, item, lds); break;
+      case 1: apply_stream_body<1, TIN>(j, item, lds); break;
+      case 2: apply_stream_body<2, TIN>(j, item, lds); break;
+      case 3: apply_stream_body<3, TIN>(j, item, lds); break;
+      default: apply_stream_body<4, TIN>(j, item, lds); break;
     }
   }
 }
 
+// two work-groups per CU (LDS: at most 66 KiB of tiles or 34 KiB of Wh each)
 template <bool BIG>
-__global__ __launch_bounds__(256) void k_apply(const WJob *__restrict__ jobs, WJob one,
-                                               const int *__restrict__ start, int D) {
+__global__ __launch_bounds__(256, 2) void k_apply(const WJob *__restrict__ jobs, WJob one,
+                                                  const int *__restrict__ start, int D) {
   extern __shared__ double ap_lds[];
   int t = blockIdx.x;
   const int d = start ? job_of(start, D, t) : 0;
