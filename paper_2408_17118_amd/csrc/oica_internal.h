@@ -290,7 +290,7 @@ hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpC
 struct CoopSlot {      // one work-group's arg-max in the all-rounds clustering
   double key;
   int idx;
-  int pad;
+  unsigned int stamp;  // round + 1 once key and idx are this round's
 };
 struct UJob {          // one unique-components problem
   int K, N;

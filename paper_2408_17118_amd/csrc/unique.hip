@@ -390,8 +390,13 @@ hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
 // thread keeps its candidate row in registers; a round is the dot products
 // with the current representative, a work-group arg-max, and a grid-wide
 // exchange of the per-group arg-maxes through `slots` (two sets, by round
-// parity) behind an arrival counter.  Every work-group reduces the same slots
-// in the same way, so all agree on the next representative.  A wait that
+// parity): a work-group stores its arg-max and then, with release order, the
+// round's stamp in its slot, and the first wave of every work-group polls all
+// slots (one lane per slot) until each carries the stamp, then reduces them.
+// Every work-group reduces the same slots in the same way, so all agree on
+// the next representative.  (An arrival counter that every work-group
+// incremented, waited on by one thread before a separate read of the slots,
+// took ~9.5 us per round at K = 16384.)  A wait that
 // exceeds its bound (about half a second) sets done[1]; every work-group then
 // ends at its next exchange and puts its rows back in their state on entry,
 // and the host redoes the clustering round by round.  The dot products are
@@ -445,69 +450,63 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
       wi[wave] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      double k0 = wk[0];
-      int i0 = wi[0];
-      for (int w = 1; w < CO_BLOCK / 64; ++w)
-        if (ranks_above(wk[w], wi[w], k0, i0)) {
-          k0 = wk[w];
-          i0 = wi[w];
-        }
-      CoopSlot *sl = slots + (size_t)(round & 1) * nwg + blockIdx.x;
-      __hip_atomic_store(&sl->key, k0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&sl->idx, i0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      atomicAdd(&done[0], 1u);
-      const unsigned int target = (round + 1) * (unsigned int)nwg;
-      int spins = 0;
-      while (__hip_atomic_load(&done[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (++spins > CO_SPIN_LIMIT ||
-            __hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          atomicOr(&done[1], 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    if (wave == 0) {
+      // publish this work-group's arg-max for the round: key and index, then
+      // the stamp with release order
+      if (tid == 0) {
+        double k0 = wk[0];
+        int i0 = wi[0];
+        for (int w = 1; w < CO_BLOCK / 64; ++w)
+          if (ranks_above(wk[w], wi[w], k0, i0)) {
+            k0 = wk[w];
+            i0 = wi[w];
+          }
+        CoopSlot *sl = slots + (size_t)(round & 1) * nwg + blockIdx.x;
+        __hip_atomic_store(&sl->key, k0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sl->idx, i0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sl->stamp, round + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
-    }
-    __syncthreads();
-    // every work-group reduces the same slots to the next representative
-    double gk = -INFINITY;
-    int gi = -1;
-    for (int b = tid; b < nwg; b += CO_BLOCK) {
-      const CoopSlot *sl = slots + (size_t)(round & 1) * nwg + b;
-      const double k2 = __hip_atomic_load(&sl->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int i2 = __hip_atomic_load(&sl->idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ranks_above(k2, i2, gk, gi)) {
-        gk = k2;
-        gi = i2;
+      // every work-group waits for and reduces the same slots (lane b polls
+      // work-group b's), so all agree on the next representative
+      double gk = -INFINITY;
+      int gi = -1;
+      bool quit = false;
+      for (int b = lane; b < nwg && !quit; b += 64) {
+        const CoopSlot *sl = slots + (size_t)(round & 1) * nwg + b;
+        int spins = 0;
+        while (__hip_atomic_load(&sl->stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+               round + 1u) {
+          if (++spins > CO_SPIN_LIMIT ||
+              __hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            quit = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (quit) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // key and idx after the stamp
+        const double k2 = __hip_atomic_load(&sl->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int i2 = __hip_atomic_load(&sl->idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ranks_above(k2, i2, gk, gi)) {
+          gk = k2;
+          gi = i2;
+        }
       }
-    }
+      if (quit) atomicOr(&done[1], 1u);
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double k2 = __shfl_xor(gk, o);
-      const int i2 = __shfl_xor(gi, o);
-      if (ranks_above(k2, i2, gk, gi)) {
-        gk = k2;
-        gi = i2;
-      }
-    }
-    __syncthreads();  // wk / wi of this round have been read
-    if (lane == 0) {
-      wk[wave] = gk;
-      wi[wave] = gi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double k0 = wk[0];
-      int i0 = wi[0];
-      for (int w = 1; w < CO_BLOCK / 64; ++w)
-        if (ranks_above(wk[w], wi[w], k0, i0)) {
-          k0 = wk[w];
-          i0 = wi[w];
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double k2 = __shfl_xor(gk, o);
+        const int i2 = __shfl_xor(gi, o);
+        if (ranks_above(k2, i2, gk, gi)) {
+          gk = k2;
+          gi = i2;
         }
-      if (__hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) i0 = -1;
-      s_leader = i0;
-      if (blockIdx.x == 0) reps[r + 1] = i0;  // -1 after the last cluster
+      }
+      if (lane == 0) {
+        if (__hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) gi = -1;
+        s_leader = gi;
+        if (blockIdx.x == 0) reps[r + 1] = gi;  // -1 after the last cluster
+      }
     }
     __syncthreads();
     leader = s_leader;
@@ -524,6 +523,13 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
     ctl[1] = r + 1;
     ctl[2] = 1;
   }
+}
+
+// The stamps start at zero for every all-rounds launch, so a stamp left by an
+// earlier launch on the same workspace never matches a round.
+__global__ void k_coop_reset(CoopSlot *slots, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) slots[i].stamp = 0u;
 }
 
 static std::atomic<int> g_coop_give_up{0};
@@ -559,6 +565,7 @@ static hipError_t launch_cluster_coop(hipStream_t st, int N, int K, const float 
   int *cluster = cw.cluster, *reps = cw.reps;
   CoopSlot *slots = cw.slots;
   unsigned int *done = cw.done;
+  hipLaunchKernelGGL(k_coop_reset, dim3((2 * grid + 255) / 256), dim3(256), 0, st, slots, 2 * grid);
   if (g_coop_give_up.load()) {  // test switch: start with the give-up flag set
     e = hipMemsetAsync(done + 1, 0xFF, sizeof(unsigned int), st);
     if (e != hipSuccess) return e;

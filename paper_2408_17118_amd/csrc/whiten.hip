@@ -533,6 +533,25 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
   bool still = false;  // the last sweep run rotated
   const int limit = jb.max_sweeps;
   for (; sweep < limit && ne > 1; ++sweep) {
+    // A sweep rotates iff some pair passes the rotation test on entry (until
+    // a rotation, every round tests pairs of the entry matrix), so a sweep
+    // that would rotate nothing is not run: every pair is tested first.
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    {
+      bool any = false;  // wave per row p, lanes over q > p
+      for (int p = tid / 64; p < N; p += JAC_THREADS / 64) {
+        const double app = a[p * LD + p];
+        for (int q = p + 1 + tid % 64; q < N; q += 64) {
+          const double apq = a[p * LD + q], aqq = a[q * LD + q];
+          any = any || (fabs(apq) > dscale && apq * apq > thr * thr * fabs(app * aqq));
+        }
+      }
+      if (any) rotated = 1;
+    }
+    __syncthreads();
+    if (rotated == 0) break;
+    __syncthreads();
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < ne - 1; ++r) {
