@@ -288,9 +288,8 @@ hipError_t launch_unprune(hipStream_t st, int K, uint8_t *status, int *list, FpC
 
 // unique.hip
 struct CoopSlot {      // one work-group's arg-max in the all-rounds clustering
-  double key;
-  int idx;
-  unsigned int stamp;  // round + 1 once key and idx are this round's
+  unsigned long long word;  // (round + 1) << 32 | row index (0xFFFFFFFF: none)
+  unsigned long long spare;
 };
 struct UJob {          // one unique-components problem
   int K, N;

@@ -390,9 +390,12 @@ hipError_t launch_cluster_wg(hipStream_t st, int D, const ClusterJob *jobs_dev,
 // thread keeps its candidate row in registers; a round is the dot products
 // with the current representative, a work-group arg-max, and a grid-wide
 // exchange of the per-group arg-maxes through `slots` (two sets, by round
-// parity): a work-group stores its arg-max and then, with release order, the
-// round's stamp in its slot, and the first wave of every work-group polls all
-// slots (one lane per slot) until each carries the stamp, then reduces them.
+// parity): a work-group stores the round's stamp and its arg-max's row index
+// in one 64-bit word of its slot, and the first wave of every work-group polls
+// all slots (one lane per slot) until each carries the stamp, then reduces
+// them by key[index].  No store is ordered after another, so no fence is
+// needed (an acquire fence there would also drop the L2 lines that the next
+// representative's row is read from).
 // Every work-group reduces the same slots in the same way, so all agree on
 // the next representative.  (An arrival counter that every work-group
 // incremented, waited on by one thread before a separate read of the slots,
@@ -451,8 +454,9 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
     }
     __syncthreads();
     if (wave == 0) {
-      // publish this work-group's arg-max for the round: key and index, then
-      // the stamp with release order
+      // publish this work-group's arg-max for the round: the row index and
+      // the round's stamp in one 64-bit word (its key is key[index], which
+      // no work-group writes), so no other store needs ordering
       if (tid == 0) {
         double k0 = wk[0];
         int i0 = wi[0];
@@ -462,9 +466,9 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
             i0 = wi[w];
           }
         CoopSlot *sl = slots + (size_t)(round & 1) * nwg + blockIdx.x;
-        __hip_atomic_store(&sl->key, k0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&sl->idx, i0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&sl->stamp, round + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long word =
+            ((unsigned long long)(round + 1u) << 32) | (unsigned long long)(unsigned int)i0;
+        __hip_atomic_store(&sl->word, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       // every work-group waits for and reduces the same slots (lane b polls
       // work-group b's), so all agree on the next representative
@@ -474,8 +478,9 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
       for (int b = lane; b < nwg && !quit; b += 64) {
         const CoopSlot *sl = slots + (size_t)(round & 1) * nwg + b;
         int spins = 0;
-        while (__hip_atomic_load(&sl->stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-               round + 1u) {
+        unsigned long long word;
+        while (((word = __hip_atomic_load(&sl->word, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)) >> 32) != round + 1u) {
           if (++spins > CO_SPIN_LIMIT ||
               __hip_atomic_load(&done[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             quit = true;
@@ -484,9 +489,8 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
           __builtin_amdgcn_s_sleep(1);
         }
         if (quit) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // key and idx after the stamp
-        const double k2 = __hip_atomic_load(&sl->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int i2 = __hip_atomic_load(&sl->idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int i2 = (int)(unsigned int)word;
+        const double k2 = i2 >= 0 ? key[i2] : -INFINITY;
         if (ranks_above(k2, i2, gk, gi)) {
           gk = k2;
           gi = i2;
@@ -529,7 +533,7 @@ __global__ __launch_bounds__(CO_BLOCK) void k_cluster_coop(int K, int N, const f
 // earlier launch on the same workspace never matches a round.
 __global__ void k_coop_reset(CoopSlot *slots, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) slots[i].stamp = 0u;
+  if (i < n) slots[i].word = 0ull;
 }
 
 static std::atomic<int> g_coop_give_up{0};
