@@ -296,6 +296,9 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
   __shared__ double wk[CW_THREADS / 64];
   __shared__ int wi[CW_THREADS / 64];
   __shared__ int s_leader;
+  // representatives in LDS while the rounds run (a global store in the
+  // loop would leave the loads' wait counter ambiguous), written at the end
+  __shared__ int s_reps[CW_MAX_K + 1];
   const ClusterJob jb = jobs ? jobs[blockIdx.x] : one;
   const int K = jb.K, N = jb.N;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -317,19 +320,72 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
       double dot[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) dot[i] = 0.0;
-      for (int n0 = 0; n0 < N; n0 += C) {
-        float v[R][C];  // every load of the chunk first, then the FMAs in order
+      if constexpr (R == 1) {
+        // one row per thread: the chunks unrolled up to OICA_MAX_N features,
+        // the loads PF chunks ahead of the FMAs (no loop back-edge, so each
+        // wait is for the chunk in use only; same FMAs in the same order)
+        constexpr int NCH = (OICA_MAX_N + C - 1) / C;
+        const bool live = cl[0] == -1;
+        // feature n of this thread's row through a buffer resource: the
+        // column offset n K is a scalar offset and the row the one vector
+        // offset, so the loads need no address registers
+        // (the job's fields are uniform; readfirstlane lets the compiler know)
+        const unsigned long long wp = (unsigned long long)(size_t)Wt;
+        const unsigned int wlo = __builtin_amdgcn_readfirstlane((unsigned int)wp);
+        const unsigned int whi = __builtin_amdgcn_readfirstlane((unsigned int)(wp >> 32));
+        const int Ku = __builtin_amdgcn_readfirstlane(K), Nu = __builtin_amdgcn_readfirstlane(N);
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(size_t)(((unsigned long long)whi << 32) | wlo), (short)0,
+            Ku * Nu * (int)sizeof(float), 0x00020000);
+        // A row that is not live takes a vector offset past the records, which
+        // the range check turns into a zero without a memory access; features
+        // past N (the prefetch of the last chunks) read feature N - 1, whose
+        // products are never added.
+        const int voff = live ? tid * (int)sizeof(float) : (int)0x80000000u;
+        auto ld = [&](int n) -> float {
+          const int soff = (n < Nu ? n : Nu - 1) * Ku * (int)sizeof(float);
+          return __builtin_bit_cast(float,
+                                    __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0));
+        };
+        // PF chunks of loads in flight ahead of the FMAs (a chunk's FMAs are
+        // far shorter than an L2 latency)
+        constexpr int PF = 3;
+        float v[PF + 1][C];
 #pragma unroll
-        for (int i = 0; i < R; ++i)
+        for (int c0 = 0; c0 < PF && c0 < NCH; ++c0)
+#pragma unroll
+          for (int j = 0; j < C; ++j) v[c0][j] = ld(c0 * C + j);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int n0 = ch * C;
+          if (n0 >= Nu) break;
+          if (ch + PF < NCH) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[(ch + PF) % (PF + 1)][j] = ld(n0 + PF * C + j);
+          }
 #pragma unroll
           for (int j = 0; j < C; ++j)
-            v[i][j] = (cl[i] == -1 && n0 + j < N) ? Wt[(size_t)(n0 + j) * K + tid + i * CW_THREADS]
-                                                  : 0.f;
+            if (n0 + j < Nu) dot[0] = fma((double)v[ch % (PF + 1)][j], lw[n0 + j], dot[0]);
+          // keep each chunk's LDS reads in its own step (hoisted together
+          // they would need 2 * OICA_MAX_N registers)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        for (int n0 = 0; n0 < N; n0 += C) {
+          float v[R][C];  // every load of the chunk first, then the FMAs in order
 #pragma unroll
-        for (int i = 0; i < R; ++i)
+          for (int i = 0; i < R; ++i)
 #pragma unroll
-          for (int j = 0; j < C; ++j)
-            if (n0 + j < N) dot[i] = fma((double)v[i][j], lw[n0 + j], dot[i]);
+            for (int j = 0; j < C; ++j)
+              v[i][j] = (cl[i] == -1 && n0 + j < N)
+                            ? Wt[(size_t)(n0 + j) * K + tid + i * CW_THREADS]
+                            : 0.f;
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < C; ++j)
+              if (n0 + j < N) dot[i] = fma((double)v[i][j], lw[n0 + j], dot[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < R; ++i)
@@ -356,7 +412,7 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
       int i0 = wi[0];
       for (int w = 1; w < CW_THREADS / 64; ++w) cw_better(k0, i0, wk[w], wi[w]);
       s_leader = i0;
-      jb.reps[r + 1] = i0;  // -1 after the last cluster
+      s_reps[r + 1] = i0;  // -1 after the last cluster
     }
     __syncthreads();
     leader = s_leader;
@@ -370,6 +426,7 @@ __global__ __launch_bounds__(CW_THREADS) void k_cluster_wg(const ClusterJob *__r
     const int l = tid + i * CW_THREADS;
     if (l < K) jb.cluster[l] = cl[i];
   }
+  for (int i = tid; i <= r + 1; i += CW_THREADS) jb.reps[i] = s_reps[i];
   if (tid == 0) {
     jb.ctl[1] = r + 1;
     jb.ctl[2] = 1;
