@@ -206,22 +206,42 @@ __global__ __launch_bounds__(WAVES * 64, 2) void k_fused_batched(const BatchDesc
   }
 }
 
+// A dataset's fields that the first-stage reduction reads, cached in LDS
+// once per work-group (per element they were a dependent chain of global
+// loads: the descriptor, then its control block's active count).
+struct RedParams {
+  const float *gpart, *s4part;
+  double *red;
+  int kact, rows_pad, np, n_sp;
+};
+static size_t red_lds_bytes(int D) {
+  return (size_t)((D + 2) & ~1) * sizeof(long long) + (size_t)D * sizeof(RedParams);
+}
+
 __global__ __launch_bounds__(256) void k_split_reduce_batched(const BatchDesc *__restrict__ descs,
                                                               int D, const BatchCtl *bctl,
                                                               const long long *__restrict__ red_start,
                                                               int pass) {
-  __shared__ long long s_start[MAX_D + 1];
+  // dynamic LDS: (D + 1) starts, then D parameter sets (red_lds_bytes)
+  extern __shared__ long long red_lds[];
+  long long *s_start = red_lds;
+  RedParams *s_p = (RedParams *)(red_lds + ((D + 2) & ~1));
   for (int d = threadIdx.x; d <= D; d += blockDim.x) s_start[d] = red_start[d];
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    const BatchDesc &b = descs[d];
+    const int kact = b.ctl->kact[pass & 1];
+    const int n_kb = (kact + b.kwg - 1) / b.kwg;
+    s_p[d] = RedParams{b.gpart, b.s4part, b.red, kact, n_kb * b.kwg, b.np, b.n_sp};
+  }
   __syncthreads();
   const long long total = bctl->total_red;
   for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * 256) {
     const int d = find_dataset(s_start, D, idx);
-    const BatchDesc &b = descs[d];
-    const int kact = b.ctl->kact[pass & 1];
-    const int n_kb = (kact + b.kwg - 1) / b.kwg;
-    const int rows_pad = n_kb * b.kwg;
-    const int RS = b.np + 1;
+    const RedParams &q = s_p[d];
+    const int kact = q.kact;
+    const int rows_pad = q.rows_pad;
+    const int RS = q.np + 1;
     const long long local = idx - s_start[d];
     const long long per_group = (long long)kact * RS;
     const int g = (int)(local / per_group);
@@ -234,14 +254,14 @@ __global__ __launch_bounds__(256) void k_split_reduce_batched(const BatchDesc *_
     for (int u = 0; u < SPLIT_GROUP; ++u) {
       const int sp = sp0 + u;
       v[u] = 0.f;
-      if (sp < b.n_sp)
-        v[u] = n < b.np ? b.gpart[((size_t)sp * rows_pad + posn) * b.np + n]
-                        : b.s4part[(size_t)sp * rows_pad + posn];
+      if (sp < q.n_sp)
+        v[u] = n < q.np ? q.gpart[((size_t)sp * rows_pad + posn) * q.np + n]
+                        : q.s4part[(size_t)sp * rows_pad + posn];
     }
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < SPLIT_GROUP; ++u) acc += (double)v[u];
-    b.red[local] = acc;
+    q.red[local] = acc;
   }
 }
 
@@ -325,8 +345,8 @@ hipError_t launch_fused_batched(hipStream_t st, const BatchDesc *descs, int D, B
 hipError_t launch_epilogue_batched(hipStream_t st, const BatchDesc *descs, int D,
                                    const BatchCtl *bctl, const long long *red_start,
                                    const int *epi_start, int pass, double tol, int kmax_total) {
-  hipLaunchKernelGGL(k_split_reduce_batched, dim3(RED_GRID), dim3(256), 0, st, descs, D, bctl,
-                     red_start, pass);
+  hipLaunchKernelGGL(k_split_reduce_batched, dim3(RED_GRID), dim3(256), red_lds_bytes(D), st,
+                     descs, D, bctl, red_start, pass);
   hipLaunchKernelGGL(k_epilogue_batched, dim3((kmax_total + 3) / 4), dim3(256), 0, st, descs, D,
                      epi_start, pass, tol);
   return hipGetLastError();
