@@ -73,25 +73,27 @@ FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
 }
 
 template <typename E>
-__global__ void k_pad_rows(const E *__restrict__ src, int N, long long T, E *__restrict__ dst,
+__global__ void k_pad_rows(const E *__restrict__ src, long long T, E *__restrict__ dst,
                            long long ld) {
-  const long long total = (long long)N * T;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (long long)gridDim.x * 256) {
-    const long long n = i / T, m = i - n * T;
-    dst[n * ld + m] = src[i];
-  }
+  // row blockIdx.y; the work-groups of a row stride over its samples (no
+  // division per element)
+  const E *s = src + (size_t)blockIdx.y * (size_t)T;
+  E *d = dst + (size_t)blockIdx.y * (size_t)ld;
+  for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < T;
+       m += (long long)gridDim.x * 256)
+    d[m] = s[m];
 }
 
 hipError_t launch_pad_rows(hipStream_t st, const void *src, int esize, int N, long long T,
                            void *dst, long long ld) {
-  const long long total = (long long)N * T;
-  const int grid = (int)std::min<long long>((total + 255) / 256, 8192);
+  if (N <= 0 || T <= 0) return hipSuccess;
+  const int per_row = (int)std::min<long long>((T + 255) / 256, std::max(1, 16384 / N));
+  const dim3 grid(per_row, N);
   if (esize == 2)
-    hipLaunchKernelGGL(k_pad_rows<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t *)src, N,
-                       T, (uint16_t *)dst, ld);
+    hipLaunchKernelGGL(k_pad_rows<uint16_t>, grid, dim3(256), 0, st, (const uint16_t *)src, T,
+                       (uint16_t *)dst, ld);
   else
-    hipLaunchKernelGGL(k_pad_rows<float>, dim3(grid), dim3(256), 0, st, (const float *)src, N, T,
+    hipLaunchKernelGGL(k_pad_rows<float>, grid, dim3(256), 0, st, (const float *)src, T,
                        (float *)dst, ld);
   return hipGetLastError();
 }
