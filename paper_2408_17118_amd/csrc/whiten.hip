@@ -89,11 +89,23 @@ __device__ void mean_part_body(const WJob &j, int c) {
   const long long T = j.T;
   const long long t0 = (long long)c * T / j.ch, t1 = (long long)(c + 1) * T / j.ch;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  constexpr int U = 8;  // a lane's samples loaded ahead of their (in-order) adds
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
     bool bad = false;
     const TIN *row = X + (size_t)n * (size_t)j.ld;
-    for (long long m = t0 + lane; m < t1; m += 64) {
+    long long m = t0 + lane;
+    for (; m + 64 * (U - 1) < t1; m += 64 * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ld(row, (size_t)(m + 64 * u));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        bad |= !isfinite(v[u]);
+        s += v[u];
+      }
+    }
+    for (; m < t1; m += 64) {
       const double v = ld(row, (size_t)m);
       bad |= !isfinite(v);
       s += v;
