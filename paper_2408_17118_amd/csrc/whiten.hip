@@ -495,7 +495,7 @@ static int g_jacobi_sweeps = JAC_MAX_SWEEPS;
 int jacobi_max_sweeps() { return g_jacobi_sweeps; }
 void set_jacobi_max_sweeps(int s) { g_jacobi_sweeps = s; }
 constexpr double JAC_EPS = 2.220446049250313e-16;
-constexpr int JV_ROWS = 8;       // rows of E per work-group
+constexpr int JV_ROWS = 8;       // rows of E per work-group, at most (two per wave)
 constexpr int JV_THREADS = 256;
 constexpr int JV_CHUNK = 32;     // logged rounds staged in LDS at a time
 
@@ -672,16 +672,20 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
   }
 }
 
+// rows_wg (<= JV_ROWS) rows of E per work-group: one per wave for a single
+// matrix (twice the work-groups, each wave half the work), two per wave in a
+// batched call (where twice the work-groups, each staging the whole rotation
+// log, measured slower)
 __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__restrict__ jobs,
-                                                               JacJob one) {
+                                                               JacJob one, int rows_wg) {
   __shared__ double e[JV_ROWS][NMAX + 1];
   __shared__ double2 cs[JV_CHUNK * (NMAX / 2)];
   __shared__ int pqs[JV_CHUNK * (NMAX / 2)];
   const JacJob jb = jobs ? jobs[blockIdx.x] : one;
   const int N = jb.N;
-  const int row0 = blockIdx.y * JV_ROWS;
+  const int row0 = blockIdx.y * rows_wg;
   if (row0 >= N) return;  // uniform over the work-group
-  const int rows = N - row0 < JV_ROWS ? N - row0 : JV_ROWS;
+  const int rows = N - row0 < rows_wg ? N - row0 : rows_wg;
   const int tid = threadIdx.x;
   for (int x = tid; x < rows * N; x += JV_THREADS) {
     const int i = x / N, j = x % N;
@@ -738,8 +742,9 @@ hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const Ja
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_jacobi_values, dim3(D), dim3(JAC_THREADS), lds, st, jobs_dev, one);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3(D, (n_max + JV_ROWS - 1) / JV_ROWS), dim3(JV_THREADS),
-                     0, st, jobs_dev, one);
+  const int rows_wg = D == 1 ? JV_THREADS / 64 : JV_ROWS;
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3(D, (n_max + rows_wg - 1) / rows_wg), dim3(JV_THREADS),
+                     0, st, jobs_dev, one, rows_wg);
   return hipGetLastError();
 }
 
