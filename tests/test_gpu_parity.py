@@ -212,7 +212,10 @@ def test_whiten_reads_a_window_in_place(ctx):
     and samples outside the window (here NaN) are never read."""
     from paper_2408_17118_amd import oica
     L = 12_000
-    cases = [(9, 5000, 700, np.float64), (64, 7001, 1234, np.float32), (1, 999, 3, np.float64)]
+    # N > 64 takes the tiled covariance and apply, whose vector loads then start at
+    # addresses aligned to 4 bytes only (FP32 window at offset 333)
+    cases = [(9, 5000, 700, np.float64), (64, 7001, 1234, np.float32), (1, 999, 3, np.float64),
+             (100, 5003, 333, np.float32), (128, 4001, 77, np.float64)]
     wins, refs = [], []
     for i, (N, T, a, dt) in enumerate(cases):
         rec = _mixture(N, L, 1, seed=700 + i).X.astype(dt) + 0.5
