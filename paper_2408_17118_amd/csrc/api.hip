@@ -46,6 +46,8 @@ hipError_t scratch_address(int device, void **out) {
 }
 }  // namespace
 
+constexpr int KURT_STREAMS = 4;  // a batched call's concurrent kurtosis passes
+
 struct oica_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -58,6 +60,11 @@ struct oica_ctx {
   void *scratch = nullptr;     // device address of the fixed noalloc array on `device`
   void *ws2 = nullptr;         // deflation driver's buffers (the calls it makes use ws)
   size_t ws2_bytes = 0;
+  // streams (default priority) on which a batched call runs its datasets'
+  // kurtosis passes side by side, with the events that order them against
+  // `stream`; created by the first batched call
+  hipStream_t aux[KURT_STREAMS] = {};
+  hipEvent_t aux_ev[KURT_STREAMS + 1] = {};
   std::string err;
 };
 
@@ -109,6 +116,15 @@ int ensure_buf(oica_ctx *ctx, void **buf, size_t *have, size_t bytes) {
   return OICA_OK;
 }
 int ensure_ws(oica_ctx *ctx, size_t bytes) { return ensure_buf(ctx, &ctx->ws, &ctx->ws_bytes, bytes); }
+
+// The auxiliary streams and their events, created once per context.
+int ensure_aux(oica_ctx *ctx) {
+  for (int i = 0; i < KURT_STREAMS; ++i)
+    if (!ctx->aux[i]) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+  for (int i = 0; i <= KURT_STREAMS; ++i)
+    if (!ctx->aux_ev[i]) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming));
+  return OICA_OK;
+}
 
 struct Carve {
   char *p;
@@ -194,6 +210,10 @@ void oica_destroy(oica_ctx *ctx) {
   if (ctx->small_dev) (void)hipFree(ctx->small_dev);
   if (ctx->small_host) (void)hipHostFree(ctx->small_host);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  for (hipStream_t a : ctx->aux)
+    if (a) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : ctx->aux_ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1120,7 +1140,7 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   add(sizeof(BatchCtl));
   add((size_t)(D + 1) * 4 * 2 + (size_t)(D + 1) * 8);
   add((size_t)D * 256 * 2);  // two control blocks per problem
-  add(kurt_rows * 8);
+  for (int i = 0; i < KURT_STREAMS; ++i) add(kurt_rows * 8);  // one partial buffer per stream
   const bool grouped = bf16 && params->refine_groups;
   if (grouped) {
     add((size_t)D * 256);                 // clustering control, 4 ints per problem
@@ -1140,7 +1160,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   int *epi_start = cv.take<int>(D + 1);
   long long *red_start = cv.take<long long>(D + 1);
   char *ctl_base = cv.take<char>((size_t)D * 256 * 2);
-  double *s4part64 = cv.take<double>(kurt_rows);
+  double *s4part64[KURT_STREAMS];
+  for (int i = 0; i < KURT_STREAMS; ++i) s4part64[i] = cv.take<double>(kurt_rows);
   int *gctl = nullptr;
   ClusterJob *gjobs_dev = nullptr;
   std::vector<ClusterJob> gjobs;
@@ -1458,29 +1479,37 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     for (int d = 0; d < D; ++d)
       refine_ti += ((const FpControl *)(ctl_host.data() + (size_t)(D + d) * 256))->thread_iters;
   }
-  if (grouped) {
-    // kurtosis of the group representatives and of the ungrouped rows, then
-    // every group member takes its representative's row, status and kurtosis
-    for (int d = 0; d < D; ++d) {
-      const oica_problem &q = pr[d];
+  // The datasets' kurtosis passes (each alone too small to fill the GPU) run
+  // side by side on the auxiliary streams, dataset d on stream d mod
+  // KURT_STREAMS with that stream's partial buffer; the streams start after
+  // everything enqueued so far and the call's stream waits for all of them.
+  rc = ensure_aux(ctx);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[KURT_STREAMS], ctx->stream));
+  for (int i = 0; i < KURT_STREAMS; ++i)
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->aux_ev[KURT_STREAMS], 0));
+  for (int d = 0; d < D; ++d) {
+    const oica_problem &q = pr[d];
+    hipStream_t sd = ctx->aux[d % KURT_STREAMS];
+    double *s4d = s4part64[d % KURT_STREAMS];
+    FusedPlan kp = make_plan(q.N, q.T, q.K, false);
+    kp.ld = hd[d].ld32;
+    if (grouped) {
+      // kurtosis of the group representatives and of the ungrouped rows, then
+      // every group member takes its representative's row, status and kurtosis
       FpControl *c3 = (FpControl *)(ctl_base + (size_t)(D + d) * 256 + 128);
-      FusedPlan kp = make_plan(q.N, q.T, q.K, false);
-      kp.ld = hd[d].ld32;
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4part64,
-                                   q.kurt, kurt_list[d], &c3->kact[0]));
-      HIP_TRY(ctx, launch_propagate(ctx->stream, q.K, q.N, gjobs[d].cluster, gjobs[d].reps, q.W_out,
+      HIP_TRY(ctx, launch_kurtosis(sd, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4d, q.kurt,
+                                   kurt_list[d], &c3->kact[0]));
+      HIP_TRY(ctx, launch_propagate(sd, q.K, q.N, gjobs[d].cluster, gjobs[d].reps, q.W_out,
                                     q.status, q.kurt));
+    } else {
+      // final kurtosis of every row, FP32 data, FP64 sums
+      HIP_TRY(ctx, launch_kurtosis(sd, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4d, q.kurt));
     }
-  } else
-  {
-    // final kurtosis of every row, FP32 data, FP64 sums
-    for (int d = 0; d < D; ++d) {
-      const oica_problem &q = pr[d];
-      FusedPlan kp = make_plan(q.N, q.T, q.K, false);
-      kp.ld = hd[d].ld32;
-      HIP_TRY(ctx, launch_kurtosis(ctx->stream, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4part64,
-                                   q.kurt));
-    }
+  }
+  for (int i = 0; i < KURT_STREAMS; ++i) {
+    HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[i], ctx->aux[i]));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->aux_ev[i], 0));
   }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
