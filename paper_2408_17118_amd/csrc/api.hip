@@ -126,6 +126,24 @@ int ensure_aux(oica_ctx *ctx) {
   return OICA_OK;
 }
 
+// Work enqueued on the auxiliary streams between aux_fork and aux_join runs
+// after everything enqueued on the call's stream before the fork, and
+// everything enqueued on the call's stream after the join waits for it.
+int aux_fork(oica_ctx *ctx) {
+  if (int rc = ensure_aux(ctx)) return rc;
+  HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[KURT_STREAMS], ctx->stream));
+  for (int i = 0; i < KURT_STREAMS; ++i)
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->aux_ev[KURT_STREAMS], 0));
+  return OICA_OK;
+}
+int aux_join(oica_ctx *ctx) {
+  for (int i = 0; i < KURT_STREAMS; ++i) {
+    HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[i], ctx->aux[i]));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->aux_ev[i], 0));
+  }
+  return OICA_OK;
+}
+
 struct Carve {
   char *p;
   template <typename T>
@@ -1483,11 +1501,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   // side by side on the auxiliary streams, dataset d on stream d mod
   // KURT_STREAMS with that stream's partial buffer; the streams start after
   // everything enqueued so far and the call's stream waits for all of them.
-  rc = ensure_aux(ctx);
+  rc = aux_fork(ctx);
   if (rc) return rc;
-  HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[KURT_STREAMS], ctx->stream));
-  for (int i = 0; i < KURT_STREAMS; ++i)
-    HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux[i], ctx->aux_ev[KURT_STREAMS], 0));
   for (int d = 0; d < D; ++d) {
     const oica_problem &q = pr[d];
     hipStream_t sd = ctx->aux[d % KURT_STREAMS];
@@ -1507,10 +1522,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       HIP_TRY(ctx, launch_kurtosis(sd, kp, q.N, q.T, hd[d].X32, q.K, q.W_out, s4d, q.kurt));
     }
   }
-  for (int i = 0; i < KURT_STREAMS; ++i) {
-    HIP_TRY(ctx, hipEventRecord(ctx->aux_ev[i], ctx->aux[i]));
-    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->aux_ev[i], 0));
-  }
+  rc = aux_join(ctx);
+  if (rc) return rc;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (stats) {
     stats->thread_iters = main_ti;
