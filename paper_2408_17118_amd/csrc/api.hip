@@ -1232,9 +1232,17 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemsetAsync(ctl_base, 0, (size_t)D * 256 * 2, ctx->stream));
+  // the per-dataset launches of a few microseconds each (start rows here,
+  // the grouping's preparation and lists below) side by side on the
+  // auxiliary streams
+  rc = aux_fork(ctx);
+  if (rc) return rc;
   for (int d = 0; d < D; ++d)
-    HIP_TRY(ctx, launch_init_rows(ctx->stream, pr[d].K, pr[d].N, pr[d].W0, pr[d].W_out, pr[d].iters,
-                                  pr[d].status, hd[d].act0, hd[d].ctl, nullptr, 0));
+    HIP_TRY(ctx, launch_init_rows(ctx->aux[d % KURT_STREAMS], pr[d].K, pr[d].N, pr[d].W0,
+                                  pr[d].W_out, pr[d].iters, pr[d].status, hd[d].act0, hd[d].ctl,
+                                  nullptr, 0));
+  rc = aux_join(ctx);
+  if (rc) return rc;
 
   // ---- tile shapes: forced, cached, tuned or default -------------------------
   int wk32 = 2, wk64 = 2, grid = 1024, tuned = 0;
@@ -1422,9 +1430,13 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
     // otherwise for every row that converged on BF16 data or is still moving
     if (grouped) {
       HIP_TRY(ctx, hipMemsetAsync(gctl, 0, (size_t)D * 64 * sizeof(int), ctx->stream));
+      rc = aux_fork(ctx);
+      if (rc) return rc;
       for (int d = 0; d < D; ++d)
-        HIP_TRY(ctx, launch_prep_groups(ctx->stream, pr[d].K, pr[d].N, pr[d].status, pr[d].W_out,
-                                        gws[d]));
+        HIP_TRY(ctx, launch_prep_groups(ctx->aux[d % KURT_STREAMS], pr[d].K, pr[d].N, pr[d].status,
+                                        pr[d].W_out, gws[d]));
+      rc = aux_join(ctx);
+      if (rc) return rc;
       std::vector<ClusterJob> small;
       for (int d = 0; d < D; ++d)
         if (cluster_in_one_wg(pr[d].K, true)) small.push_back(gjobs[d]);
@@ -1444,6 +1456,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
                                      (void *)gws[d].key, gjobs[d].ctl, ctx->small_host, &cl, &reps));
         }
     }
+    rc = aux_fork(ctx);
+    if (rc) return rc;
     for (int d = 0; d < D; ++d) {
       const FpControl *c = (const FpControl *)(ctl_host.data() + (size_t)d * 256);
       BatchDesc &b = hd[d];
@@ -1452,13 +1466,14 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       const int par = parked ? park_parity[d] : (launched & 1);
       const int *left_list = par ? b.act1 : b.act0;
       const int left = parked ? park_count[d] : c->kact[launched & 1];
+      hipStream_t sd = ctx->aux[d % KURT_STREAMS];
       if (grouped)
-        HIP_TRY(ctx, launch_group_lists(ctx->stream, b.K, gjobs[d].cluster, gjobs[d].reps,
+        HIP_TRY(ctx, launch_group_lists(sd, b.K, gjobs[d].cluster, gjobs[d].reps,
                                         gjobs[d].ctl + 1, b.status, pr[d].kurt, act2[d], c2,
                                         left_list, left, kurt_list[d],
                                         (FpControl *)((char *)c2 + 128)));
       else
-        HIP_TRY(ctx, launch_refine_select(ctx->stream, b.K, b.status, act2[d], c2, left_list, left));
+        HIP_TRY(ctx, launch_refine_select(sd, b.K, b.status, act2[d], c2, left_list, left));
       int *old0 = b.act0;
       b.act0 = act2[d];
       b.act1 = old0;
@@ -1467,6 +1482,8 @@ int oica_fixed_point_batched(oica_ctx *ctx, int D, const oica_problem *pr, oica_
       b.ld = b.ld32;
       b.bf_one = 0;
     }
+    rc = aux_join(ctx);
+    if (rc) return rc;
     // the FP32 passes update few rows per problem: one 32-row block per wave,
     // and the thin items where few enough rows start
     set_shapes(hd, 1, 1, false);
