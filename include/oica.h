@@ -19,7 +19,11 @@
  *    workspace that grows on demand and is freed by oica_destroy.
  *  - All work is enqueued on the context's HIP stream.  A call returns after
  *    enqueueing unless its comment says it synchronises (calls that report a
- *    count or a data-dependent error to the host do).
+ *    count or a data-dependent error to the host do).  The batched fixed point
+ *    also runs per-dataset work on four streams of its own (default priority,
+ *    created on first use, destroyed with the context), ordered against the
+ *    context's stream by events, so that the context's stream is still the
+ *    only one the caller orders against; it synchronises before returning.
  *  - Return value: OICA_OK (0) or a negative OICA_E_* code.  Argument errors
  *    are detected on the host before any device work, so they can be tested
  *    without a GPU.  After an error, oica_last_error() gives a readable detail.
