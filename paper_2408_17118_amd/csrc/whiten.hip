@@ -966,6 +966,8 @@ __device__ __forceinline__ void apply_stream_body(const WJob &j, int item, doubl
   }
 }
 
+template <int R> struct RowCount { static constexpr int value = R; };
+
 template <int NRB, typename TIN>
 __device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double *lds) {
   typedef __attribute__((address_space(1))) const TIN gin;
@@ -995,13 +997,21 @@ __device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double
   const long long m_item = (long long)item * apply_cols(NP);
   long long m_end = m_item + apply_cols(NP);
   if (m_end > T) m_end = T;
-  // this wave's row blocks; a row block past NRB (NRB < 8, waves w + 4 >=
-  // NRB) multiplies zeros and stores nothing, in the time the wave would
-  // otherwise wait at the tile barrier
+  // this wave's row blocks.  NRB 7 and 8: blocks w and w + 4 on both sample
+  // blocks of a tile (for NRB 7, wave 3's block 7 multiplies zeros and stores
+  // nothing, in the time the wave would otherwise wait at the tile barrier).
+  // NRB 5 and 6 (SPLIT): block w on both sample blocks and block 4 + w / 2
+  // (NRB 6; NRB 5: block 4, waves 0 and 1 only) on sample block w % 2 only,
+  // so that no wave multiplies a block of zeros and the longest wave does 3
+  // block products per tile instead of 4.  Every output comes from the same
+  // chain of MFMAs either way.
+  constexpr bool SPLIT = NRB <= 6;
+  static_assert(!SPLIT || SBW == 2, "the split takes two sample blocks per tile");
   int rbw[RBW];
-#pragma unroll
-  for (int i = 0; i < RBW; ++i) rbw[i] = wave + 4 * i;
-  const int sb0 = 0;
+  rbw[0] = wave;
+  rbw[1] = SPLIT ? 4 + (NRB == 6 ? wave / 2 : 0) : wave + 4;
+  const bool extra = !SPLIT || NRB == 6 || wave < 2;  // wave uniform
+  const int xsb = SPLIT ? wave % 2 : 0;               // sample block with both rows
   // A operands: wa[i][s] = Wh[16 rb + li][4 s + lk], read at clamped indices
   // and zeroed past N
   const double *Wh = j.Wh;
@@ -1072,17 +1082,18 @@ __device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double
     double *nxt = (it & 1) ? buf0 : buf1;
     if (it + 1 < nfull) load_full(tb + TS);
     else if (it + 1 < ntiles) load_tail(tb + TS);
+    // the products of R of this wave's row blocks with sample block sb of
+    // the tile, and their stores
+    auto block = [&](auto rows, int sb) {
+      constexpr int R = decltype(rows)::value;
+      f64x4 acc[R];
 #pragma unroll
-    for (int jb = 0; jb < SBW; ++jb) {
-      const int sb = sb0 + jb;
-      f64x4 acc[RBW];
-#pragma unroll
-      for (int i = 0; i < RBW; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < R; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < NK; ++s) {
         const double bv = cur[(sb * 16 + li) * LDF + 4 * s + lk];
 #pragma unroll
-        for (int i = 0; i < RBW; ++i)
+        for (int i = 0; i < R; ++i)
           acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[i][s], bv, acc[i], 0, 0, 0);
       }
       const long long m = tb + sb * 16 + li;
@@ -1092,7 +1103,7 @@ __device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double
       asm volatile("" : "+v"(lko));
       const bool all_m = tb + sb * 16 + 16 <= m_end;  // work-group uniform
 #pragma unroll
-      for (int i = 0; i < RBW; ++i) {
+      for (int i = 0; i < R; ++i) {
         // every row of the block stored (wave uniform); a block past NRB
         // stores nothing, its rows being past n_out
         const bool all_r = rbw[i] * 16 + 16 <= n_out;
@@ -1107,6 +1118,14 @@ __device__ __forceinline__ void apply_tiled_body(const WJob &j, int item, double
           if (o32b) o32b[o] = (float)v;
         }
       }
+    };
+    if (SPLIT) {
+      if (extra) block(RowCount<2>(), xsb);
+      else block(RowCount<1>(), xsb);
+      block(RowCount<1>(), 1 - xsb);
+    } else {
+#pragma unroll
+      for (int sb = 0; sb < SBW; ++sb) block(RowCount<RBW>(), sb);
     }
     if (it + 1 < ntiles) store_tile(nxt, tb + TS);
     __syncthreads();
