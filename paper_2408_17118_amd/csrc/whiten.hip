@@ -498,6 +498,14 @@ constexpr double JAC_EPS = 2.220446049250313e-16;
 constexpr int JV_ROWS = 8;       // rows of E per work-group, at most (two per wave)
 constexpr int JV_THREADS = 256;
 constexpr int JV_CHUNK = 32;     // logged rounds staged in LDS at a time
+constexpr int JAC_STAGE = 8;     // loads in flight per thread while staging C
+// log entries per thread and staged chunk
+constexpr int JV_STAGE = JV_CHUNK * (NMAX / 2) / JV_THREADS;
+static_assert(JV_STAGE * JV_THREADS == JV_CHUNK * (NMAX / 2), "a chunk splits evenly");
+typedef double jac_dv2 __attribute__((ext_vector_type(2)));  // the log's (c, s)
+typedef __attribute__((address_space(1))) double jac_gd;
+typedef __attribute__((address_space(1))) jac_dv2 jac_gd2;
+typedef __attribute__((address_space(1))) int jac_gi;
 
 size_t jacobi_log_entries(int N) {
   const int ne = N + (N & 1);
@@ -522,19 +530,41 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
   __shared__ int rotated;
   __shared__ double dscale;
   const JacJob jb = jobs ? jobs[blockIdx.x] : one;
+  // global (not generic) pointers: a generic store counts against the LDS
+  // counter too, so the LDS wait before each round's barrier would also wait
+  // for the round's log stores to reach memory
+  const jac_gd *Cg = (const jac_gd *)jb.C;
+  jac_gd2 *rot_log = (jac_gd2 *)jb.rot;
+  jac_gi *pq_log = (jac_gi *)jb.pq;
   const int N = jb.N;
   const int LD = jac_ld(N);
   double *a = jac_smem;
   const int tid = threadIdx.x;
   const double thr = JAC_EPS * (double)N;
-  for (int e = tid; e < N * N; e += JAC_THREADS) {
-    const int i = e / N, j = e % N;
-    if (i <= j) a[i * LD + j] = jb.C[e];
+  // the upper triangle into LDS, JAC_STAGE loads in flight per thread
+  const int NN = N * N;
+  for (int e0 = 0; e0 < NN; e0 += JAC_STAGE * JAC_THREADS) {
+    double v[JAC_STAGE];
+#pragma unroll
+    for (int k = 0; k < JAC_STAGE; ++k) {
+      const int e = e0 + k * JAC_THREADS + tid;
+      v[k] = Cg[e < NN ? e : NN - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < JAC_STAGE; ++k) {
+      const int e = e0 + k * JAC_THREADS + tid;
+      const int i = e / N, j = e - i * N;
+      if (e < NN && i <= j) a[i * LD + j] = v[k];
+    }
   }
-  if (tid == 0) {
+  __syncthreads();
+  // the largest |C_ii|, over the diagonal now in LDS (one wave; the maximum
+  // does not depend on the order it is taken in)
+  if (tid < 64) {
     double m = 0.0;
-    for (int i = 0; i < N; ++i) m = fmax(m, fabs(jb.C[i * N + i]));
-    dscale = JAC_EPS * m;
+    for (int i = tid; i < N; i += 64) m = fmax(m, fabs(a[i * LD + i]));
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (tid == 0) dscale = JAC_EPS * m;
   }
   __syncthreads();
   const int ne = N + (N & 1);
@@ -606,8 +636,8 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
         rp[tid] = p;
         rq[tid] = q < N ? q : -1;
         const size_t li = ((size_t)sweep * (ne - 1) + r) * npair + tid;
-        jb.rot[li] = make_double2(c, sn);
-        jb.pq[li] = p | ((q < N ? q : 0xFFFF) << 16);
+        rot_log[li] = jac_dv2{c, sn};
+        pq_log[li] = p | ((q < N ? q : 0xFFFF) << 16);
       }
       __syncthreads();
       // block (k, l), l = k + m (mod npair): every unordered pair of index
@@ -679,9 +709,11 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
 __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__restrict__ jobs,
                                                                JacJob one, int rows_wg) {
   __shared__ double e[JV_ROWS][NMAX + 1];
-  __shared__ double2 cs[JV_CHUNK * (NMAX / 2)];
+  __shared__ jac_dv2 cs[JV_CHUNK * (NMAX / 2)];
   __shared__ int pqs[JV_CHUNK * (NMAX / 2)];
   const JacJob jb = jobs ? jobs[blockIdx.x] : one;
+  const jac_gd2 *rot_log = (const jac_gd2 *)jb.rot;
+  const jac_gi *pq_log = (const jac_gi *)jb.pq;
   const int N = jb.N;
   const int row0 = blockIdx.y * rows_wg;
   if (row0 >= N) return;  // uniform over the work-group
@@ -694,21 +726,42 @@ __global__ __launch_bounds__(JV_THREADS) void k_jacobi_vectors(const JacJob *__r
   const int ne = N + (N & 1);
   const int npair = ne / 2;
   const long long rounds = (long long)jb.sweeps[0] * (ne - 1);
+  // a chunk of the log is loaded into registers while the previous one is
+  // replayed, and stored to LDS between two barriers
+  jac_dv2 vcs[JV_STAGE];
+  int vpq[JV_STAGE];
+  auto fetch = [&](long long r0) {
+    const int cnt = (rounds - r0 < JV_CHUNK ? (int)(rounds - r0) : JV_CHUNK) * npair;
+    const size_t base = (size_t)r0 * npair;
+#pragma unroll
+    for (int k = 0; k < JV_STAGE; ++k) {
+      const int x = tid + k * JV_THREADS;
+      const size_t o = base + (size_t)(x < cnt ? x : cnt - 1);
+      vcs[k] = rot_log[o];
+      vpq[k] = pq_log[o];
+    }
+  };
+  if (rounds > 0) fetch(0);
   for (long long r0 = 0; r0 < rounds; r0 += JV_CHUNK) {
     const int nr = rounds - r0 < JV_CHUNK ? (int)(rounds - r0) : JV_CHUNK;
     __syncthreads();
-    for (int x = tid; x < nr * npair; x += JV_THREADS) {
-      cs[x] = jb.rot[(size_t)r0 * npair + x];
-      pqs[x] = jb.pq[(size_t)r0 * npair + x];
+#pragma unroll
+    for (int k = 0; k < JV_STAGE; ++k) {
+      const int x = tid + k * JV_THREADS;
+      if (x < nr * npair) {
+        cs[x] = vcs[k];
+        pqs[x] = vpq[k];
+      }
     }
     __syncthreads();
+    if (r0 + JV_CHUNK < rounds) fetch(r0 + JV_CHUNK);
     // a row of E is one wave's alone: lane k applies pair k of every round in
     // turn, and the wave's LDS accesses complete in order, so the rounds of a
     // chunk need no work-group barrier
     const int lane = tid % 64, wave = tid / 64;
     for (int rr = 0; rr < nr; ++rr) {
       if (lane < npair) {
-        const double2 v = cs[rr * npair + lane];
+        const jac_dv2 v = cs[rr * npair + lane];
         if (v.y != 0.0) {
           const int pq = pqs[rr * npair + lane];
           const int p = pq & 0xFFFF, q = pq >> 16;
