@@ -512,7 +512,12 @@ size_t jacobi_log_entries(int N) {
   return (size_t)JAC_MAX_SWEEPS * (size_t)(ne > 1 ? ne - 1 : 1) * (size_t)(ne / 2 > 0 ? ne / 2 : 1);
 }
 
-__device__ inline int jac_sym(int i, int j, int LD) { return i <= j ? i * LD + j : j * LD + i; }
+// Element (i, j) of the upper triangle.  Indices and LD are below 2^24, so
+// the full-rate 24-bit multiply gives the row offset (a 32-bit multiply
+// issues at a quarter of the rate, and the solve is bound by its issue rate).
+__device__ inline int jac_sym(int i, int j, int LD) {
+  return i <= j ? (int)__umul24(i, LD) + j : (int)__umul24(j, LD) + i;
+}
 
 // Row stride of A in LDS: the smallest LD >= N + 1 with LD = 2 (mod 4).  In a
 // round, neighbouring lanes' elements often differ by one row and one column
@@ -615,9 +620,11 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
         }
         double c = 1.0, sn = 0.0;
         if (q < N) {
-          const double apq = a[p * LD + q];
-          const double app = a[p * LD + p], aqq = a[q * LD + q];
-          if (fabs(apq) > dscale && apq * apq > thr * thr * fabs(app * aqq)) {
+          const double apq = a[__umul24(p, LD) + q];
+          const double app = a[__umul24(p, LD) + p], aqq = a[__umul24(q, LD) + q];
+          // both comparisons taken (no short circuit), so that the three
+          // reads above go out together
+          if ((fabs(apq) > dscale) & (apq * apq > thr * thr * fabs(app * aqq))) {
             // With x = a_qq - a_pp, y = 2 a_pq (cot 2phi = x / y) and r = |(x, y)|,
             // the smaller rotation angle has t = tan phi = sgn(xy) |y| / (|x| + r),
             // so cos phi = (|x| + r) / w and sin phi = sgn(xy) |y| / w with
@@ -678,9 +685,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
         const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
         const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
         if (k == l) {  // diagonal block, pk < qk
-          a[pk * LD + pk] = n00;
-          a[pk * LD + qk] = n01;
-          a[qk * LD + qk] = n11;
+          a[__umul24(pk, LD) + pk] = n00;
+          a[__umul24(pk, LD) + qk] = n01;
+          a[__umul24(qk, LD) + qk] = n11;
         } else {
           a[jac_sym(pk, pl, LD)] = n00;
           if (ql >= 0) a[jac_sym(pk, ql, LD)] = n01;
