@@ -72,22 +72,40 @@ FusedPlan make_plan(int N, int64_t T, int kmax, bool bf16) {
   return p;
 }
 
+constexpr int PAD_U = 8;  // elements per thread and trip, 256 apart
+
 template <typename E>
-__global__ void k_pad_rows(const E *__restrict__ src, long long T, E *__restrict__ dst,
-                           long long ld) {
+__global__ __launch_bounds__(256) void k_pad_rows(const E *__restrict__ src, long long T,
+                                                  E *__restrict__ dst, long long ld) {
   // row blockIdx.y; the work-groups of a row stride over its samples (no
-  // division per element)
+  // division per element); each thread has all PAD_U loads of a trip in
+  // flight before its stores (one load at a time left the copy latency-bound)
   const E *s = src + (size_t)blockIdx.y * (size_t)T;
   E *d = dst + (size_t)blockIdx.y * (size_t)ld;
-  for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < T;
-       m += (long long)gridDim.x * 256)
-    d[m] = s[m];
+  constexpr long long TILE = 256LL * PAD_U;
+  for (long long b = (long long)blockIdx.x * TILE; b < T; b += (long long)gridDim.x * TILE) {
+    const long long m0 = b + threadIdx.x;
+    E v[PAD_U];
+    if (b + TILE <= T) {  // work-group uniform: the whole tile inside the row
+#pragma unroll
+      for (int u = 0; u < PAD_U; ++u) v[u] = s[m0 + 256 * u];
+#pragma unroll
+      for (int u = 0; u < PAD_U; ++u) d[m0 + 256 * u] = v[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < PAD_U; ++u) v[u] = s[m0 + 256 * u < T ? m0 + 256 * u : T - 1];
+#pragma unroll
+      for (int u = 0; u < PAD_U; ++u)
+        if (m0 + 256 * u < T) d[m0 + 256 * u] = v[u];
+    }
+  }
 }
 
 hipError_t launch_pad_rows(hipStream_t st, const void *src, int esize, int N, long long T,
                            void *dst, long long ld) {
   if (N <= 0 || T <= 0) return hipSuccess;
-  const int per_row = (int)std::min<long long>((T + 255) / 256, std::max(1, 16384 / N));
+  const int per_row = (int)std::min<long long>((T + 256 * PAD_U - 1) / (256 * PAD_U),
+                                               std::max(1, 16384 / N));
   const dim3 grid(per_row, N);
   if (esize == 2)
     hipLaunchKernelGGL(k_pad_rows<uint16_t>, grid, dim3(256), 0, st, (const uint16_t *)src, T,
