@@ -244,19 +244,34 @@ __global__ __launch_bounds__(256) void k_split_reduce_batched(const BatchDesc *_
     const int RS = q.np + 1;
     const long long local = idx - s_start[d];
     const long long per_group = (long long)kact * RS;
-    const int g = (int)(local / per_group);
-    const int rem = (int)(local - (long long)g * per_group);
+    int g, rem;
+    if (local <= 0x7fffffffLL && per_group <= 0x7fffffffLL) {
+      // the usual case: 32-bit division (a 64-bit one is a long call)
+      g = (int)local / (int)per_group;
+      rem = (int)local - g * (int)per_group;
+    } else {
+      g = (int)(local / per_group);
+      rem = (int)(local - (long long)g * per_group);
+    }
     const int posn = rem / RS;
     const int n = rem - posn * RS;
     const int sp0 = g * SPLIT_GROUP;
+    // every load of the group issued before the sums (a split past the last
+    // reads the last and adds zero)
+    // (one base and stride per element, read through a global pointer: a
+    // generic load also counts against the LDS counter, so the LDS reads
+    // between the loads would wait for each one)
+    typedef __attribute__((address_space(1))) const float gcf;
+    const bool is_g = n < q.np;
+    gcf *src = is_g ? (gcf *)(q.gpart + (size_t)posn * q.np + n) : (gcf *)(q.s4part + posn);
+    const size_t stride = is_g ? (size_t)rows_pad * q.np : (size_t)rows_pad;
+    const int n_sp = q.n_sp;
     float v[SPLIT_GROUP];
 #pragma unroll
     for (int u = 0; u < SPLIT_GROUP; ++u) {
-      const int sp = sp0 + u;
-      v[u] = 0.f;
-      if (sp < q.n_sp)
-        v[u] = n < q.np ? q.gpart[((size_t)sp * rows_pad + posn) * q.np + n]
-                        : q.s4part[(size_t)sp * rows_pad + posn];
+      const int sp = sp0 + u < n_sp ? sp0 + u : n_sp - 1;
+      const float x = src[(size_t)sp * stride];
+      v[u] = sp0 + u < n_sp ? x : 0.f;
     }
     double acc = 0.0;
 #pragma unroll
@@ -286,11 +301,26 @@ __global__ __launch_bounds__(256) void k_epilogue_batched(const BatchDesc *__res
   const int row = act_cur[posn];
   const int n0 = lane, n1 = lane + 64;
   double g0 = 0.0, g1 = 0.0, s4 = 0.0;
-  for (int q = 0; q < groups; ++q) {
-    const double *src = b.red + ((size_t)q * kact + posn) * RS;
-    if (n0 < NP) g0 += src[n0];
-    if (n1 < NP) g1 += src[n1];
-    if (lane == 0) s4 += src[NP];
+  // group sums in group order, EPI_U loads in flight per lane (a group past
+  // the last adds zero)
+  constexpr int EPI_U = 8;
+  for (int q0 = 0; q0 < groups; q0 += EPI_U) {
+    double v0[EPI_U], v1[EPI_U], v4[EPI_U];
+#pragma unroll
+    for (int u = 0; u < EPI_U; ++u) {
+      const int q = q0 + u;
+      const bool ok = q < groups;
+      const double *src = b.red + ((size_t)(ok ? q : 0) * kact + posn) * RS;
+      v0[u] = (ok && n0 < NP) ? src[n0] : 0.0;
+      v1[u] = (ok && n1 < NP) ? src[n1] : 0.0;
+      v4[u] = (ok && lane == 0) ? src[NP] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPI_U; ++u) {
+      g0 += v0[u];
+      g1 += v1[u];
+      s4 += v4[u];
+    }
   }
   float *brow = b.B + (size_t)row * N;
   const double bp0 = n0 < N ? (double)brow[n0] : 0.0;
