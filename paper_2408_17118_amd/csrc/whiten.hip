@@ -89,26 +89,28 @@ __device__ void mean_part_body(const WJob &j, int c) {
   const long long T = j.T;
   const long long t0 = (long long)c * T / j.ch, t1 = (long long)(c + 1) * T / j.ch;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  constexpr int U = 8;  // a lane's samples loaded ahead of their (in-order) adds
+  // a lane's samples m, m + 64, ... are loaded U at a time ahead of their
+  // (in-order) adds; past the chunk's end a load reads its last sample and
+  // adds +0.0, which leaves the sum as it is (it starts at +0.0, so it is
+  // never -0.0), so the chunk's tail needs no loads one at a time
+  constexpr int U = 16;
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
     bool bad = false;
     const TIN *row = X + (size_t)n * (size_t)j.ld;
-    long long m = t0 + lane;
-    for (; m + 64 * (U - 1) < t1; m += 64 * U) {
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = ld(row, (size_t)(m + 64 * u));
+    for (long long m = t0 + lane; m < t1; m += 64 * U) {
+      TIN v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        bad |= !isfinite(v[u]);
-        s += v[u];
+        const long long i = m + 64 * u;
+        v[u] = row[(size_t)(i < t1 ? i : t1 - 1)];
       }
-    }
-    for (; m < t1; m += 64) {
-      const double v = ld(row, (size_t)m);
-      bad |= !isfinite(v);
-      s += v;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double x = m + 64 * u < t1 ? (double)v[u] : 0.0;
+        bad |= !isfinite(x);
+        s += x;
+      }
     }
     s = wsum(s);
     if (bad) atomicOr(j.flags, 1);
