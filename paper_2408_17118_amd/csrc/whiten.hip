@@ -493,6 +493,8 @@ constexpr int JAC_THREADS = 1024;
 // 2 x 2 blocks per thread and round, at most: npair (npair / 2 + 1) blocks
 constexpr int JAC_UNITS = ((NMAX / 2) * (NMAX / 4 + 1) + JAC_THREADS - 1) / JAC_THREADS;
 constexpr int JAC_MAX_SWEEPS = 30;
+constexpr int JAC_FIRST = JAC_UNITS < 2 ? JAC_UNITS : 2;  // units of a round's first batch
+template <int V> struct JacC { static constexpr int value = V; };
 static int g_jacobi_sweeps = JAC_MAX_SWEEPS;
 int jacobi_max_sweeps() { return g_jacobi_sweeps; }
 void set_jacobi_max_sweeps(int s) { g_jacobi_sweeps = s; }
@@ -651,52 +653,63 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_values(const JacJob *__r
       __syncthreads();
       // block (k, l), l = k + m (mod npair): every unordered pair of index
       // pairs once (m = H twice when npair is even: keep k < H).  The blocks
-      // of a round hold disjoint elements, so a thread loads all of its
-      // blocks before it stores any (one LDS latency per round, not one per
-      // block).
-      double b[JAC_UNITS][4];
-      int kk[JAC_UNITS], ll[JAC_UNITS];
+      // of a round hold disjoint elements, so they may be loaded and stored
+      // in any order: a thread loads units [J0, J1) of its blocks before it
+      // stores them (one LDS latency per batch, not one per block), first
+      // units 0 and 1, then the rest (the first wave's only), and keeps each
+      // unit's rotations and element offsets from its loads for its stores,
+      // within the register budget of 1024 threads.
+      auto blocks = [&](auto j0c, auto j1c) {
+        constexpr int J0 = decltype(j0c)::value, J1 = decltype(j1c)::value;
+        constexpr int NU = J1 - J0;
+        double b[NU][4], ck[NU], sk[NU], cl[NU], sl[NU];
+        int o00[NU], o01[NU], o10[NU], o11[NU];  // element offsets, -1: none
+        bool live[NU], diag[NU];
 #pragma unroll
-      for (int j = 0; j < JAC_UNITS; ++j) {
-        const int u = tid + j * JAC_THREADS;
-        kk[j] = -1;
-        if (u >= units) continue;
-        const int m = u / npair, k = u - m * npair;
-        if (m == H && !((npair & 1) || k < H)) continue;
-        int l = k + m;
-        if (l >= npair) l -= npair;
-        if (rs[k] == 0.0 && rs[l] == 0.0) continue;
-        kk[j] = k;
-        ll[j] = l;
-        const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
-        b[j][0] = a[jac_sym(pk, pl, LD)];
-        b[j][1] = ql >= 0 ? a[jac_sym(pk, ql, LD)] : 0.0;
-        b[j][2] = qk >= 0 ? a[jac_sym(qk, pl, LD)] : 0.0;
-        b[j][3] = (qk >= 0 && ql >= 0) ? a[jac_sym(qk, ql, LD)] : 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < JAC_UNITS; ++j) {
-        const int k = kk[j], l = ll[j];
-        if (k < 0) continue;
-        const double sk = rs[k], sl = rs[l], ck = rc[k], cl = rc[l];
-        const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
-        const double b00 = b[j][0], b01 = b[j][1], b10 = b[j][2], b11 = b[j][3];
-        // rows of pair k, then columns of pair l
-        const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
-        const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
-        const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
-        const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
-        if (k == l) {  // diagonal block, pk < qk
-          a[__umul24(pk, LD) + pk] = n00;
-          a[__umul24(pk, LD) + qk] = n01;
-          a[__umul24(qk, LD) + qk] = n11;
-        } else {
-          a[jac_sym(pk, pl, LD)] = n00;
-          if (ql >= 0) a[jac_sym(pk, ql, LD)] = n01;
-          if (qk >= 0) a[jac_sym(qk, pl, LD)] = n10;
-          if (qk >= 0 && ql >= 0) a[jac_sym(qk, ql, LD)] = n11;
+        for (int i = 0; i < NU; ++i) {
+          const int u = tid + (J0 + i) * JAC_THREADS;
+          live[i] = false;
+          if (u >= units) continue;
+          const int m = u / npair, k = u - m * npair;
+          if (m == H && !((npair & 1) || k < H)) continue;
+          int l = k + m;
+          if (l >= npair) l -= npair;
+          sk[i] = rs[k];
+          sl[i] = rs[l];
+          if (sk[i] == 0.0 && sl[i] == 0.0) continue;
+          live[i] = true;
+          diag[i] = k == l;  // then pk < qk, and (qk, pk) is (pk, qk)
+          ck[i] = rc[k];
+          cl[i] = rc[l];
+          const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
+          o00[i] = jac_sym(pk, pl, LD);
+          o01[i] = ql >= 0 ? jac_sym(pk, ql, LD) : -1;
+          o10[i] = qk >= 0 ? jac_sym(qk, pl, LD) : -1;
+          o11[i] = (qk >= 0 && ql >= 0) ? jac_sym(qk, ql, LD) : -1;
+          b[i][0] = a[o00[i]];
+          b[i][1] = o01[i] >= 0 ? a[o01[i]] : 0.0;
+          b[i][2] = o10[i] >= 0 ? a[o10[i]] : 0.0;
+          b[i][3] = o11[i] >= 0 ? a[o11[i]] : 0.0;
         }
-      }
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+          if (!live[i]) continue;
+          const double b00 = b[i][0], b01 = b[i][1], b10 = b[i][2], b11 = b[i][3];
+          // rows of pair k, then columns of pair l; each x y +- z w as
+          // fma(x, y, +-(z w)), the second product rounded (written out, so
+          // that the contraction does not depend on how the code is arranged)
+          const double r00 = fma(ck[i], b00, -(sk[i] * b10)), r01 = fma(ck[i], b01, -(sk[i] * b11));
+          const double r10 = fma(sk[i], b00, ck[i] * b10), r11 = fma(sk[i], b01, ck[i] * b11);
+          const double n00 = fma(cl[i], r00, -(sl[i] * r01)), n01 = fma(sl[i], r00, cl[i] * r01);
+          const double n10 = fma(cl[i], r10, -(sl[i] * r11)), n11 = fma(sl[i], r10, cl[i] * r11);
+          a[o00[i]] = n00;
+          if (o01[i] >= 0) a[o01[i]] = n01;
+          if (!diag[i] && o10[i] >= 0) a[o10[i]] = n10;
+          if (o11[i] >= 0) a[o11[i]] = n11;
+        }
+      };
+      blocks(JacC<0>(), JacC<JAC_FIRST>());
+      if constexpr (JAC_FIRST < JAC_UNITS) blocks(JacC<JAC_FIRST>(), JacC<JAC_UNITS>());
       __syncthreads();
     }
     if (rotated == 0) break;
