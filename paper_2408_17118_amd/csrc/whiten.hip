@@ -90,26 +90,41 @@ __device__ void mean_part_body(const WJob &j, int c) {
   const long long t0 = (long long)c * T / j.ch, t1 = (long long)(c + 1) * T / j.ch;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   // a lane's samples m, m + 64, ... are loaded U at a time ahead of their
-  // (in-order) adds; past the chunk's end a load reads its last sample and
-  // adds +0.0, which leaves the sum as it is (it starts at +0.0, so it is
-  // never -0.0), so the chunk's tail needs no loads one at a time
-  constexpr int U = 16;
+  // (in-order) adds, through a buffer resource over the row's chunk: a load
+  // past the chunk's end reads zero without a memory access and adds +0.0,
+  // which leaves the sum as it is (it starts at +0.0, so it is never -0.0);
+  // the U loads share one offset register (their distances are immediates)
+  constexpr int U = 8;
+  constexpr int ES = (int)sizeof(TIN);
+  static_assert(64 * (U - 1) * ES < 4096, "the loads' distances fit the immediate offset");
+  const long long len = t1 - t0;  // a chunk is far below 2^31 bytes
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
     bool bad = false;
-    const TIN *row = X + (size_t)n * (size_t)j.ld;
-    for (long long m = t0 + lane; m < t1; m += 64 * U) {
-      TIN v[U];
+    // the chunk's base and size are uniform; readfirstlane keeps the
+    // resource in scalar registers
+    const unsigned long long cb = (unsigned long long)(size_t)(X + (size_t)n * (size_t)j.ld + t0);
+    const unsigned int blo = __builtin_amdgcn_readfirstlane((unsigned int)cb);
+    const unsigned int bhi = __builtin_amdgcn_readfirstlane((unsigned int)(cb >> 32));
+    const int nrec = __builtin_amdgcn_readfirstlane((int)(len * ES));
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(size_t)(((unsigned long long)bhi << 32) | blo), (short)0, nrec, 0x00020000);
+    for (long long m = lane; m < len; m += 64 * U) {
+      const int vo = (int)m * ES;
+      double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const long long i = m + 64 * u;
-        v[u] = row[(size_t)(i < t1 ? i : t1 - 1)];
+        if constexpr (ES == 8)
+          v[u] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo + 64 * u * ES, 0, 0));
+        else
+          v[u] = (double)__builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo + 64 * u * ES, 0, 0));
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double x = m + 64 * u < t1 ? (double)v[u] : 0.0;
-        bad |= !isfinite(x);
-        s += x;
+        bad |= !isfinite(v[u]);
+        s += v[u];
       }
     }
     s = wsum(s);
