@@ -21,9 +21,11 @@
  *    enqueueing unless its comment says it synchronises (calls that report a
  *    count or a data-dependent error to the host do).  The batched fixed point
  *    also runs per-dataset work on four streams of its own (default priority,
- *    created on first use, destroyed with the context), ordered against the
- *    context's stream by events, so that the context's stream is still the
- *    only one the caller orders against; it synchronises before returning.
+ *    created on first use, destroyed with the context), and the batched
+ *    whitening the last steps of its problems with N <= 64 on the first of
+ *    them, ordered against the context's stream by events, so that the
+ *    context's stream is still the only one the caller orders against; both
+ *    synchronise before returning.
  *  - Return value: OICA_OK (0) or a negative OICA_E_* code.  Argument errors
  *    are detected on the host before any device work, so they can be tested
  *    without a GPU.  After an error, oica_last_error() gives a readable detail.

@@ -333,7 +333,9 @@ int oica_whiten_batched(oica_ctx *ctx, int D, oica_whiten_problem *problems, oic
   int *flags = (int *)((char *)ctx->ws + ((main_bytes + 255) & ~(size_t)255));
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemsetAsync(flags, 0, (size_t)D * sizeof(int), ctx->stream));
-  HIP_TRY(ctx, launch_whiten_batched(ctx->stream, D, jobs.data(), ctx->ws, flags));
+  if (int rc2 = ensure_aux(ctx)) return rc2;
+  HIP_TRY(ctx, launch_whiten_batched(ctx->stream, D, jobs.data(), ctx->ws, flags, ctx->aux[0],
+                                     ctx->aux_ev[KURT_STREAMS], ctx->aux_ev[0]));
   std::vector<int> hf(D);
   HIP_TRY(ctx, hipMemcpyAsync(hf.data(), flags, (size_t)D * sizeof(int), hipMemcpyDeviceToHost,
                               ctx->stream));

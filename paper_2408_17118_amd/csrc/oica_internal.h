@@ -182,8 +182,12 @@ struct WhitenJob {     // one problem of the batched whitening
   double *V, *mean, *eig;  // nullable outputs
 };
 size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs);
+// aux: nullable; with it, the problems with N <= 64 finish (eigen-solve,
+// canon, apply) on `aux` between `fork` (recorded on st) and `join` (waited
+// for by st), beside the others on st.
 hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, void *ws,
-                                 int *flags_dev);
+                                 int *flags_dev, hipStream_t aux, hipEvent_t fork,
+                                 hipEvent_t join);
 hipError_t launch_jacobi(hipStream_t st, int D, const JacJob *jobs_dev, const JacJob &one,
                          int n_max);
 hipError_t launch_apply_rows(hipStream_t st, int N, int n_out, int64_t T, const float *X,

@@ -1379,6 +1379,12 @@ static std::vector<int> stats_groups(int D, const WhitenJob *jobs, size_t *part_
   return first;
 }
 
+// Tables of one size class of a batch (Jacobi jobs, problems, launch ranges).
+static size_t class_tables_bytes(int D) {
+  return al256((size_t)D * sizeof(JacJob)) + al256((size_t)D * sizeof(WJob)) +
+         al256((size_t)W_KINDS * (D + 1) * sizeof(int));
+}
+
 size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
   size_t part = 0, b = 0;
   stats_groups(D, jobs, &part);
@@ -1386,7 +1392,7 @@ size_t whiten_batched_workspace_bytes(int D, const WhitenJob *jobs) {
   // tables: Jacobi jobs, problems, launch ranges (all problems, then per group)
   return part + b + al256((size_t)D * sizeof(JacJob)) + al256((size_t)D * sizeof(WJob)) +
          al256((size_t)W_KINDS * (D + 1) * sizeof(int)) +
-         al256((size_t)W_KINDS * 2 * (D + 1) * sizeof(int)) + 1024;
+         al256((size_t)W_KINDS * 2 * (D + 1) * sizeof(int)) + 2 * class_tables_bytes(D) + 1024;
 }
 
 hipError_t launch_whiten(hipStream_t st, int N, int64_t T, const void *X, oica_dtype raw_t,
@@ -1458,7 +1464,8 @@ hipError_t launch_apply_rows(hipStream_t st, int N, int n_out, int64_t T, const 
 // entry; the job tables are copied to the device first and the stream
 // synchronised, so `jobs` may be freed on return.
 hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, void *ws,
-                                 int *flags_dev) {
+                                 int *flags_dev, hipStream_t aux, hipEvent_t fork,
+                                 hipEvent_t join) {
   size_t part_bytes = 0;
   const std::vector<int> groups = stats_groups(D, jobs, &part_bytes);
   int n_max = 1;
@@ -1514,6 +1521,49 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
   e = hipMemcpyAsync(gstarts_dev, gstarts.data(), gstarts.size() * sizeof(int),
                      hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
+  // Size classes (N <= 64, N > 64): with an auxiliary stream and both classes
+  // present, the small class's eigen-solve, canon and apply run on `aux` while
+  // the large class's (whose N = 128 solves take longest) run on `st`, so the
+  // small apply no longer waits for the slowest solve.  Each problem's
+  // kernels and arithmetic are those of the one-stream form.
+  std::vector<int> cls[2];
+  for (int d = 0; d < D; ++d) cls[jobs[d].N > 64].push_back(d);
+  const bool split = aux != nullptr && !cls[0].empty() && !cls[1].empty();
+  std::vector<JacJob> cjj[2];
+  std::vector<WJob> cwj[2];
+  std::vector<int> cstarts[2];
+  JacJob *cjac_dev[2] = {nullptr, nullptr};
+  WJob *cwj_dev[2] = {nullptr, nullptr};
+  int *cstarts_dev[2] = {nullptr, nullptr};
+  int cn_max[2] = {1, 1};
+  if (split) {
+    char *q = (char *)gstarts_dev + al256((size_t)W_KINDS * 2 * (D + 1) * sizeof(int));
+    for (int c = 0; c < 2; ++c) {
+      const int n = (int)cls[c].size();
+      for (int d : cls[c]) {
+        cjj[c].push_back(jj[d]);
+        cwj[c].push_back(wj[d]);
+        cn_max[c] = std::max(cn_max[c], jobs[d].N);
+      }
+      cstarts[c].resize((size_t)W_KINDS * (n + 1));
+      job_starts(cwj[c].data(), n, cstarts[c].data());
+      cjac_dev[c] = (JacJob *)q;
+      q += al256((size_t)D * sizeof(JacJob));
+      cwj_dev[c] = (WJob *)q;
+      q += al256((size_t)D * sizeof(WJob));
+      cstarts_dev[c] = (int *)q;
+      q += al256((size_t)W_KINDS * (D + 1) * sizeof(int));
+      e = hipMemcpyAsync(cjac_dev[c], cjj[c].data(), (size_t)n * sizeof(JacJob),
+                         hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(cwj_dev[c], cwj[c].data(), (size_t)n * sizeof(WJob),
+                           hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(cstarts_dev[c], cstarts[c].data(), cstarts[c].size() * sizeof(int),
+                           hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+  }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   for (size_t g = 0; g + 1 < groups.size(); ++g) {
@@ -1536,17 +1586,37 @@ hipError_t launch_whiten_batched(hipStream_t st, int D, const WhitenJob *jobs, v
     hipLaunchKernelGGL(k_cov_final, dim3((tot(W_COVF) + 3) / 4), dim3(256), 0, st, wj_dev + d0, j0,
                        rng(W_COVF), n, tot(W_COVF));
   }
-  e = launch_jacobi(st, D, jac_dev, jj[0], n_max);
+  // eigen-solve, canon and apply of a set of problems on one stream
+  auto finish = [&](hipStream_t sc, int n, const JacJob *jdev, const JacJob &j1, const WJob *wdev,
+                    const WJob &w1, const int *sdev, const int *sh, int nmx) -> hipError_t {
+    hipError_t r = launch_jacobi(sc, n, jdev, j1, nmx);
+    if (r != hipSuccess) return r;
+    hipLaunchKernelGGL(k_canon, dim3(n), dim3(NMAX), 0, sc, wdev, w1);
+    const int n_ap4 = sh[W_APPLY4 * (n + 1) + n], n_ap8 = sh[W_APPLY8 * (n + 1) + n];
+    if (n_ap4 > 0)
+      hipLaunchKernelGGL(k_apply<false>, dim3(n_ap4), dim3(256),
+                         apply_prepare<false>(std::min(nmx, 64)), sc, wdev, w1,
+                         sdev + W_APPLY4 * (n + 1), n);
+    if (n_ap8 > 0)
+      hipLaunchKernelGGL(k_apply<true>, dim3(n_ap8), dim3(256), apply_prepare<true>(nmx), sc,
+                         wdev, w1, sdev + W_APPLY8 * (n + 1), n);
+    return hipGetLastError();
+  };
+  if (!split)
+    return finish(st, D, jac_dev, jj[0], wj_dev, wj[0], starts_dev, starts.data(), n_max);
+  e = hipEventRecord(fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(aux, fork, 0);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_canon, dim3(D), dim3(NMAX), 0, st, wj_dev, wj[0]);
-  const int n_ap4 = starts[W_APPLY4 * (D + 1) + D], n_ap8 = starts[W_APPLY8 * (D + 1) + D];
-  if (n_ap4 > 0)
-    hipLaunchKernelGGL(k_apply<false>, dim3(n_ap4), dim3(256), apply_prepare<false>(std::min(n_max, 64)),
-                       st, wj_dev, wj[0], starts_dev + W_APPLY4 * (D + 1), D);
-  if (n_ap8 > 0)
-    hipLaunchKernelGGL(k_apply<true>, dim3(n_ap8), dim3(256), apply_prepare<true>(n_max), st, wj_dev,
-                       wj[0], starts_dev + W_APPLY8 * (D + 1), D);
-  return hipGetLastError();
+  const int n0 = (int)cls[0].size(), n1 = (int)cls[1].size();
+  e = finish(aux, n0, cjac_dev[0], cjj[0][0], cwj_dev[0], cwj[0][0], cstarts_dev[0],
+             cstarts[0].data(), cn_max[0]);
+  // the join is recorded whatever happened, so the call's stream never waits
+  // on an event of an earlier call
+  hipError_t e1 = finish(st, n1, cjac_dev[1], cjj[1][0], cwj_dev[1], cwj[1][0], cstarts_dev[1],
+                         cstarts[1].data(), cn_max[1]);
+  hipError_t e2 = hipEventRecord(join, aux);
+  if (e2 == hipSuccess) e2 = hipStreamWaitEvent(st, join, 0);
+  return e != hipSuccess ? e : e1 != hipSuccess ? e1 : e2;
 }
 
 }  // namespace oica
