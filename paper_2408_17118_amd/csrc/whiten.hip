@@ -93,11 +93,12 @@ __device__ void mean_part_body(const WJob &j, int c) {
   // (in-order) adds, through a buffer resource over the row's chunk: a load
   // past the chunk's end reads zero without a memory access and adds +0.0,
   // which leaves the sum as it is (it starts at +0.0, so it is never -0.0);
-  // the U loads share one offset register (their distances are immediates)
+  // each load takes a 32-bit offset register instead of a 64-bit address
   constexpr int U = 8;
   constexpr int ES = (int)sizeof(TIN);
-  static_assert(64 * (U - 1) * ES < 4096, "the loads' distances fit the immediate offset");
-  const long long len = t1 - t0;  // a chunk is far below 2^31 bytes
+  // a chunk is at most ~T / 1024 samples of a row (n_chunks), far below 2^31
+  // bytes for any T whose N x T input fits the device
+  const long long len = t1 - t0;
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
     bool bad = false;
