@@ -96,8 +96,8 @@ __device__ void mean_part_body(const WJob &j, int c) {
   // each load takes a 32-bit offset register instead of a 64-bit address
   constexpr int U = 8;
   constexpr int ES = (int)sizeof(TIN);
-  // a chunk is at most ~T / 1024 samples of a row (n_chunks), far below 2^31
-  // bytes for any T whose N x T input fits the device
+  // a chunk holds about 256 samples of a row, or T / 1024 once T > 2.6e5
+  // (n_chunks): far below 2^31 bytes for any T whose N x T input fits the device
   const long long len = t1 - t0;
   for (int n = wave; n < N; n += 4) {
     double s = 0.0;
