@@ -188,7 +188,8 @@ def test_binding_rejects_wrong_dtypes_and_shapes(ctx):
 
 def test_whiten_batched_equals_single(ctx):
     """One batched call gives every dataset exactly the single call's outputs
-    (same kernels, one Jacobi launch for all eigenproblems)."""
+    (same kernels; the eigen-solve, canon and apply of the N <= 64 problems run
+    on a second stream beside the others')."""
     shapes = [(1, 1000), (2, 3000), (7, 5001), (33, 4000), (64, 20_000), (100, 9000), (128, 12_000)]
     Xs = []
     for i, (N, T) in enumerate(shapes):
@@ -204,6 +205,21 @@ def test_whiten_batched_equals_single(ctx):
     Vr = ica.whiten(host(Xs[-1]).astype(np.float64))[1]
     V = host(outs[-1][2])
     assert np.allclose(V, Vr, rtol=1e-8, atol=1e-8 * np.abs(Vr).max())
+
+
+@pytest.mark.parametrize("shapes", [[(5, 3000), (48, 7001), (64, 9000)],
+                                    [(65, 4001), (96, 6000), (128, 8000)]])
+def test_whiten_batched_one_size_class(ctx, shapes):
+    """A batch whose problems all fall in one size class (N <= 64, or N > 64)
+    runs on the call's stream alone; every output still equals the single
+    call's bit for bit, as with the mixed batch above (whose two classes finish
+    on two streams)."""
+    Xs = [dev(_mixture(N, T, 1, seed=700 + i).X) for i, (N, T) in enumerate(shapes)]
+    for out_dtype in (torch.float32, torch.bfloat16):
+        outs = ctx.whiten_batched(Xs, out_dtype=out_dtype)
+        for X, o in zip(Xs, outs):
+            for a, b in zip(o, ctx.whiten(X, out_dtype=out_dtype)):
+                assert torch.equal(a, b)
 
 
 def test_whiten_reads_a_window_in_place(ctx):
